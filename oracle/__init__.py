@@ -1,0 +1,22 @@
+"""CPU oracle of the FFA search (test infrastructure only).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package.  It shares no code with the GPU library.
+"""
+from .oracle import (  # noqa: F401
+    ALG1,
+    ALG2,
+    IN_F32,
+    IN_U8,
+    alg1,
+    alg2,
+    build,
+    default_widths,
+    downsample,
+    fold,
+    fold_step,
+    library,
+    mad_constant,
+    plan,
+    search,
+)

@@ -1,0 +1,551 @@
+/*
+ * ffa_oracle.c -- plain CPU reference of the FFA periodicity search with
+ * boxcar S/N evaluation (Cameron et al. 2017, "An investigation of pulsar
+ * searching techniques with the Fast Folding Algorithm").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * helper with the GPU library.
+ *
+ * Arithmetic: float input is carried in double precision; uint8 input is
+ * carried in int64, so folded profiles are exact integers.  The code follows
+ * the definitions step by step and is deliberately slow:
+ *   - plan      : Sec. 2.1 (trial periods, Eqs. 1-2, with N replaced by the
+ *                 padded length M*P0) and Sec. 2.3.1 (automatic octave
+ *                 downsampling by 2 each time the period doubles);
+ *   - rows      : Sec. 2.1 (pad to a power-of-two row count with zero rows;
+ *                 drop the data tail beyond an integer number of rows);
+ *   - fold      : the Staelin tree named in Sec. 2.1, level by level;
+ *   - Alg. 1    : Sec. 2.2.1 (median/MAD normalisation, Eqs. 3-4; boxcars
+ *                 divided by sqrt(width); score = maximum);
+ *   - Alg. 2    : Sec. 2.2.2 (boxcar first, 20% exclusion window around the
+ *                 maximum, Eq. 5).
+ * Readings of points the paper leaves open are listed next to the code.
+ *
+ * Parity status: plan, downsampling, fold and Alg. 1 are pinned by the
+ * `-m "not gpu"` tests (worked example, closed forms, invariants, library
+ * routines, impulse response, injected-pulse recovery).  Alg. 2's exclusion
+ * window placement and its ddof are readings with no printed example:
+ * "parity unpinned" beyond the checks of its limiting cases.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* sigma = K * MAD (Sec. 2.2.1, Eq. 4).  The paper gives K ~ 1.4826; it is the
+ * reciprocal of the normal distribution's 75% quantile, which makes the MAD
+ * of normal data an estimate of its standard deviation.  Taken to double
+ * precision: 1 / 0.6744897501960817. */
+#define ORACLE_K 1.482602218505602
+
+#define ORACLE_IN_F32 0
+#define ORACLE_IN_U8 1
+
+#define ORACLE_ALG1 1
+#define ORACLE_ALG2 2
+
+/* ------------------------------------------------------------------ plan */
+
+static int32_t next_pow2_i32(int32_t m) {
+  int32_t M = 1;
+  while (M < m) M <<= 1;
+  return M;
+}
+
+/* Enumerate the FFA executions ("steps") of a search.
+ *
+ * Octave o has downsampling factor f = 2^o (Sec. 2.3.1: the series is halved
+ * in length each time the trial period doubles).  In each octave the base
+ * period P0 (in downsampled bins) takes every integer in [B, 2B) whose period
+ * in seconds, P0*f*tsamp, lies in [pmin, pmax).  Per step:
+ *   N_f = floor(N / f)             samples after downsampling
+ *   m   = floor(N_f / P0)          whole rows of data (tail dropped, Sec. 2.1)
+ *   M   = smallest power of two >= m   rows after zero padding (Sec. 2.1)
+ * Steps with m < 2 are skipped (the period spacing of Eq. 1 needs two rows).
+ * The trials of a step are numbered first_trial + k, k = 0..M-1.
+ *
+ * Returns the number of steps; when the arrays are non-NULL and the count is
+ * at most cap, fills them.  Returns -1 on invalid arguments.
+ */
+int oracle_plan(int64_t N, double tsamp, double pmin, double pmax,
+                int32_t bins_min, int32_t max_octaves, int32_t cap,
+                int32_t* f_out, int32_t* P0_out, int32_t* m_out,
+                int32_t* M_out, int64_t* first_out) {
+  if (N < 2 || !(tsamp > 0) || !(pmin > 0) || !(pmax > pmin) || bins_min < 1)
+    return -1;
+  int32_t count = 0;
+  int64_t trials = 0;
+  for (int32_t o = 0; o < 62; ++o) {
+    if (max_octaves > 0 && o >= max_octaves) break;
+    int64_t f = (int64_t)1 << o;
+    if ((double)bins_min * (double)f * tsamp >= pmax) break;
+    int64_t Nf = N / f;
+    if (Nf < 2 * (int64_t)bins_min) break;
+    for (int32_t P0 = bins_min; P0 < 2 * bins_min; ++P0) {
+      double p = (double)P0 * (double)f * tsamp;
+      if (p < pmin || p >= pmax) continue;
+      int64_t m = Nf / P0;
+      if (m < 2) continue;
+      int32_t M = next_pow2_i32((int32_t)m);
+      if (f_out && count < cap) {
+        f_out[count] = (int32_t)f;
+        P0_out[count] = P0;
+        m_out[count] = (int32_t)m;
+        M_out[count] = M;
+        first_out[count] = trials;
+      }
+      ++count;
+      trials += M;
+    }
+  }
+  return count;
+}
+
+/* ----------------------------------------------------------- downsample */
+
+/* One halving of the time resolution (Sec. 2.3.1): y[i] = x[2i] + x[2i+1]
+ * for i < floor(n/2); an odd last sample is dropped.  A sum rather than a
+ * mean: the two differ by an exact power of two, and both S/N algorithms are
+ * invariant to a positive scale. */
+static void halve_f64(const double* x, int64_t n, double* y) {
+  for (int64_t i = 0; i < n / 2; ++i) y[i] = x[2 * i] + x[2 * i + 1];
+}
+
+static void halve_i64(const int64_t* x, int64_t n, int64_t* y) {
+  for (int64_t i = 0; i < n / 2; ++i) y[i] = x[2 * i] + x[2 * i + 1];
+}
+
+/* Series at factor f = 2^o built by o successive halvings. */
+void oracle_downsample_f64(const double* x, int64_t n, int32_t octave,
+                           double* out) {
+  double* cur = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* nxt = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  memcpy(cur, x, sizeof(double) * (size_t)n);
+  int64_t len = n;
+  for (int32_t o = 0; o < octave; ++o) {
+    halve_f64(cur, len, nxt);
+    len /= 2;
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  memcpy(out, cur, sizeof(double) * (size_t)len);
+  free(cur);
+  free(nxt);
+}
+
+void oracle_downsample_i64(const int64_t* x, int64_t n, int32_t octave,
+                           int64_t* out) {
+  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* nxt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  memcpy(cur, x, sizeof(int64_t) * (size_t)n);
+  int64_t len = n;
+  for (int32_t o = 0; o < octave; ++o) {
+    halve_i64(cur, len, nxt);
+    len /= 2;
+    int64_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  memcpy(out, cur, sizeof(int64_t) * (size_t)len);
+  free(cur);
+  free(nxt);
+}
+
+/* ----------------------------------------------------------------- fold */
+
+/* The FFA of one step (Sec. 2.1, after Staelin 1969).
+ *
+ * Level 0 holds one partial profile per row: row r is x[r*P0 .. r*P0+P0-1]
+ * for r < m and all zeros for m <= r < M (zero padding; the data tail beyond
+ * m*P0 samples is not used).
+ *
+ * At level l = 1..L (L = log2 M) the rows are cut into blocks of 2^l.  Each
+ * block has a head half A and a tail half B, each holding 2^(l-1) partial
+ * profiles from level l-1.  The block's 2^l new partials are
+ *
+ *     out_t[j] = A_{t/2}[j] + B_{t/2}[(j + ceil(t/2)) mod P0],
+ *     t = 0 .. 2^l - 1,  j = 0 .. P0 - 1,
+ *
+ * i.e. partial t of the block reuses partial t/2 of both halves, and the tail
+ * half is rotated left by ceil(t/2) bins.  Rotating left makes the folding
+ * period grow with t.  After level L, out_k is the folded profile of trial k,
+ * whose period is P0 + k/(M-1) bins (Eq. 2 with N replaced by M*P0).
+ *
+ * Reading: the paper gives no shift convention.  This one makes trial k drift
+ * the last row by exactly k bins relative to the first, the spacing Eq. 1
+ * implies for the padded length, and leaves row 0 unshifted.
+ */
+#define DEFINE_FOLD(NAME, T)                                                   \
+  void NAME(const T* x, int32_t P0, int32_t m, int32_t M, T* out) {            \
+    size_t cells = (size_t)M * (size_t)P0;                                     \
+    T* cur = (T*)calloc(cells, sizeof(T));                                     \
+    T* nxt = (T*)calloc(cells, sizeof(T));                                     \
+    for (int32_t r = 0; r < m; ++r)                                            \
+      for (int32_t j = 0; j < P0; ++j)                                         \
+        cur[(size_t)r * P0 + j] = x[(size_t)r * P0 + j];                       \
+    for (int32_t half = 1; half < M; half *= 2) {                              \
+      int32_t block = 2 * half;                                                \
+      for (int32_t b0 = 0; b0 < M; b0 += block) {                              \
+        const T* A = cur + (size_t)b0 * P0;                                    \
+        const T* B = cur + (size_t)(b0 + half) * P0;                           \
+        for (int32_t t = 0; t < block; ++t) {                                  \
+          int32_t src = t / 2;                                                 \
+          int32_t shift = (t + 1) / 2;                                         \
+          T* o = nxt + (size_t)(b0 + t) * P0;                                  \
+          for (int32_t j = 0; j < P0; ++j)                                     \
+            o[j] = A[(size_t)src * P0 + j] +                                   \
+                   B[(size_t)src * P0 + (j + shift) % P0];                     \
+        }                                                                      \
+      }                                                                        \
+      T* tmp = cur;                                                            \
+      cur = nxt;                                                               \
+      nxt = tmp;                                                               \
+    }                                                                          \
+    memcpy(out, cur, cells * sizeof(T));                                       \
+    free(cur);                                                                 \
+    free(nxt);                                                                 \
+  }
+
+DEFINE_FOLD(oracle_fold_f64, double)
+DEFINE_FOLD(oracle_fold_i64, int64_t)
+
+/* ------------------------------------------------------ Algorithm 1 (f64) */
+
+static int cmp_f64(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+static int cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Median of n values (sorted copy).  Even n: mean of the two middle order
+ * statistics (reading; the paper does not say). */
+static double median_f64(const double* v, int32_t n, double* scratch) {
+  memcpy(scratch, v, sizeof(double) * (size_t)n);
+  qsort(scratch, (size_t)n, sizeof(double), cmp_f64);
+  if (n % 2) return scratch[n / 2];
+  return 0.5 * (scratch[n / 2 - 1] + scratch[n / 2]);
+}
+
+/* Sum of the w bins starting at j, wrapping around the profile (the profile
+ * is one period, so the boxcar is circular). */
+static double box_f64(const double* F, int32_t P0, int32_t j, int32_t w) {
+  double s = 0.0;
+  for (int32_t i = 0; i < w; ++i) s += F[(j + i) % P0];
+  return s;
+}
+
+static int64_t box_i64(const int64_t* F, int32_t P0, int32_t j, int32_t w) {
+  int64_t s = 0;
+  for (int32_t i = 0; i < w; ++i) s += F[(j + i) % P0];
+  return s;
+}
+
+/* Algorithm 1 (Sec. 2.2.1).  Normalise the profile by its median and K*MAD
+ * (Eqs. 3-4), slide a boxcar of each width over every bin position, divide
+ * each boxcar sum by sqrt(width), and keep the maximum.  Written without the
+ * explicit normalised copy: (sum_w(F) - w*med) / (K*MAD*sqrt(w)) is the
+ * boxcar sum of the normalised profile divided by sqrt(w).
+ * Widths larger than the profile are skipped.  MAD = 0 gives score 0 and
+ * width 0 (reading: the normalisation is undefined).  Ties between widths
+ * keep the first width in the given order. */
+double oracle_alg1_f64(const double* F, int32_t P0, const int32_t* widths,
+                       int32_t nw, int32_t* best_w) {
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)P0);
+  double* dev = (double*)malloc(sizeof(double) * (size_t)P0);
+  double med = median_f64(F, P0, tmp);
+  for (int32_t j = 0; j < P0; ++j) dev[j] = fabs(F[j] - med);
+  double mad = median_f64(dev, P0, tmp);
+  free(tmp);
+  free(dev);
+  *best_w = 0;
+  if (mad == 0.0) return 0.0;
+  double sigma = ORACLE_K * mad;
+  double best = 0.0;
+  int have = 0;
+  for (int32_t wi = 0; wi < nw; ++wi) {
+    int32_t w = widths[wi];
+    if (w < 1 || w > P0) continue;
+    double peak = box_f64(F, P0, 0, w);
+    for (int32_t j = 1; j < P0; ++j) {
+      double s = box_f64(F, P0, j, w);
+      if (s > peak) peak = s;
+    }
+    double snr = (peak - (double)w * med) / (sigma * sqrt((double)w));
+    if (!have || snr > best) {
+      best = snr;
+      *best_w = w;
+      have = 1;
+    }
+  }
+  return have ? best : 0.0;
+}
+
+/* Algorithm 1 on an exact integer profile (uint8 input).  The median and MAD
+ * of integers are multiples of 1/2 and 1/4, so the score is formed from
+ * exact integers before any rounding:
+ *   med2 = 2*median,  mad4 = 4*MAD,
+ *   S/N_w = (peak_w - w*median) / (K*MAD*sqrt(w))
+ *         = 2*(2*peak_w - w*med2) / (K*mad4*sqrt(w)),
+ * evaluated in double as num / ((K*mad4)*sqrt(w)).  Every operation there is
+ * correctly rounded, so the result is a fixed function of the integers. */
+double oracle_alg1_i64(const int64_t* F, int32_t P0, const int32_t* widths,
+                       int32_t nw, int32_t* best_w) {
+  int64_t* tmp = (int64_t*)malloc(sizeof(int64_t) * (size_t)P0);
+  memcpy(tmp, F, sizeof(int64_t) * (size_t)P0);
+  qsort(tmp, (size_t)P0, sizeof(int64_t), cmp_i64);
+  int64_t med2 = (P0 % 2) ? 2 * tmp[P0 / 2] : tmp[P0 / 2 - 1] + tmp[P0 / 2];
+  /* |2F - med2| = 2*|F - median| */
+  for (int32_t j = 0; j < P0; ++j) {
+    int64_t d = 2 * F[j] - med2;
+    tmp[j] = d < 0 ? -d : d;
+  }
+  qsort(tmp, (size_t)P0, sizeof(int64_t), cmp_i64);
+  int64_t mad4 = (P0 % 2) ? 2 * tmp[P0 / 2] : tmp[P0 / 2 - 1] + tmp[P0 / 2];
+  free(tmp);
+  *best_w = 0;
+  if (mad4 == 0) return 0.0;
+  double best = 0.0;
+  int have = 0;
+  for (int32_t wi = 0; wi < nw; ++wi) {
+    int32_t w = widths[wi];
+    if (w < 1 || w > P0) continue;
+    int64_t peak = box_i64(F, P0, 0, w);
+    for (int32_t j = 1; j < P0; ++j) {
+      int64_t s = box_i64(F, P0, j, w);
+      if (s > peak) peak = s;
+    }
+    int64_t num = 2 * (2 * peak - (int64_t)w * med2);
+    double den = (ORACLE_K * (double)mad4) * sqrt((double)w);
+    double snr = (double)num / den;
+    if (!have || snr > best) {
+      best = snr;
+      *best_w = w;
+      have = 1;
+    }
+  }
+  return have ? best : 0.0;
+}
+
+/* ------------------------------------------------------ Algorithm 2 (f64) */
+
+/* Algorithm 2 (Sec. 2.2.2).  For each width: boxcar the raw profile, find the
+ * maximum I_max, exclude a window of 20% of the profile centred on it, take
+ * the mean I_av and standard deviation sigma of the remaining 80%, and score
+ * A = (I_max - I_av) / sigma (Eq. 5).  The score is the maximum over widths.
+ *
+ * Readings (the paper does not fix them): the window is placed in the
+ * boxcar-output index space, covers n_ex = round(P0/5) positions starting
+ * floor(n_ex/2) before the first maximum, wraps around the profile, and sigma
+ * is the population standard deviation.  sigma = 0 gives score 0.
+ * The "Ref" variant of Sec. 2.2.2 / Sec. 2.4 is this with one width. */
+double oracle_alg2_f64(const double* F, int32_t P0, const int32_t* widths,
+                       int32_t nw, int32_t* best_w) {
+  double* bx = (double*)malloc(sizeof(double) * (size_t)P0);
+  char* excl = (char*)malloc((size_t)P0);
+  int32_t n_ex = (2 * P0 + 5) / 10;
+  double best = 0.0;
+  int have = 0;
+  *best_w = 0;
+  for (int32_t wi = 0; wi < nw; ++wi) {
+    int32_t w = widths[wi];
+    if (w < 1 || w > P0) continue;
+    int32_t jmax = 0;
+    for (int32_t j = 0; j < P0; ++j) {
+      bx[j] = box_f64(F, P0, j, w);
+      if (bx[j] > bx[jmax]) jmax = j;
+    }
+    memset(excl, 0, (size_t)P0);
+    int32_t start = jmax - n_ex / 2;
+    for (int32_t i = 0; i < n_ex; ++i) excl[((start + i) % P0 + P0) % P0] = 1;
+    double s = 0.0;
+    int32_t cnt = 0;
+    for (int32_t j = 0; j < P0; ++j)
+      if (!excl[j]) {
+        s += bx[j];
+        ++cnt;
+      }
+    double a = 0.0;
+    if (cnt > 0) {
+      double mean = s / cnt;
+      double v = 0.0;
+      for (int32_t j = 0; j < P0; ++j)
+        if (!excl[j]) v += (bx[j] - mean) * (bx[j] - mean);
+      double sd = sqrt(v / cnt);
+      a = sd > 0.0 ? (bx[jmax] - mean) / sd : 0.0;
+    }
+    if (!have || a > best) {
+      best = a;
+      *best_w = w;
+      have = 1;
+    }
+  }
+  free(bx);
+  free(excl);
+  return have ? best : 0.0;
+}
+
+/* --------------------------------------------------------------- search */
+
+/* Score one profile with the chosen algorithm.  Integer profiles use the
+ * exact-integer Algorithm 1; Algorithm 2 works on the double copy. */
+static double score_profile(const void* prof, int is_int, int32_t P0,
+                            const int32_t* widths, int32_t nw, int alg,
+                            int32_t* best_w, double* dscratch) {
+  if (is_int) {
+    const int64_t* F = (const int64_t*)prof;
+    if (alg == ORACLE_ALG1) return oracle_alg1_i64(F, P0, widths, nw, best_w);
+    for (int32_t j = 0; j < P0; ++j) dscratch[j] = (double)F[j];
+    return oracle_alg2_f64(dscratch, P0, widths, nw, best_w);
+  }
+  const double* F = (const double*)prof;
+  if (alg == ORACLE_ALG1) return oracle_alg1_f64(F, P0, widths, nw, best_w);
+  return oracle_alg2_f64(F, P0, widths, nw, best_w);
+}
+
+/* The default width set when none is given (Sec. 2.2.1): 1, 2, 4, ... up to
+ * and including the first power of two larger than 20% of the profile
+ * length.  Returns the count written to w (at most 31). */
+int32_t oracle_default_widths(int32_t P0, int32_t* w) {
+  int32_t n = 0;
+  for (int32_t v = 1; n < 31; v *= 2) {
+    w[n++] = v;
+    if (5 * v > P0) break; /* v > 0.2*P0 */
+  }
+  return n;
+}
+
+/* Periodogram of a search, or of a subset of its steps.
+ *
+ * series : N samples, float32 (dtype 0) or uint8 (dtype 1)
+ * steps  : the plan's step list (as from oracle_plan), n_steps entries
+ * sel    : indices into the step list to evaluate (NULL = all)
+ * widths : width list (NULL/0 = the default rule per step)
+ * snr, width : outputs indexed by global trial number first_trial + k
+ *              (only the selected steps' entries are written)
+ * threads: OpenMP threads (<= 0: library default)
+ */
+int oracle_search(const void* series, int32_t dtype, int64_t N,
+                  int32_t n_steps, const int32_t* f_arr, const int32_t* P0_arr,
+                  const int32_t* m_arr, const int32_t* M_arr,
+                  const int64_t* first_arr, int32_t n_sel, const int32_t* sel,
+                  const int32_t* widths, int32_t nw, int32_t alg,
+                  int32_t threads, float* snr, int32_t* width) {
+  if (dtype != ORACLE_IN_F32 && dtype != ORACLE_IN_U8) return -1;
+  if (alg != ORACLE_ALG1 && alg != ORACLE_ALG2) return -1;
+  int is_int = dtype == ORACLE_IN_U8;
+  /* octave series: every octave a step uses, built by successive halving */
+  int32_t max_oct = 0;
+  for (int32_t s = 0; s < n_steps; ++s) {
+    int32_t o = 0;
+    while ((1 << o) < f_arr[s]) ++o;
+    if (o > max_oct) max_oct = o;
+  }
+  void** oct = (void**)calloc((size_t)max_oct + 1, sizeof(void*));
+  size_t esz = is_int ? sizeof(int64_t) : sizeof(double);
+  oct[0] = malloc(esz * (size_t)N);
+  if (is_int) {
+    const uint8_t* u = (const uint8_t*)series;
+    for (int64_t i = 0; i < N; ++i) ((int64_t*)oct[0])[i] = u[i];
+  } else {
+    const float* x = (const float*)series;
+    for (int64_t i = 0; i < N; ++i) ((double*)oct[0])[i] = x[i];
+  }
+  int64_t len = N;
+  for (int32_t o = 1; o <= max_oct; ++o) {
+    oct[o] = malloc(esz * (size_t)(len / 2 > 0 ? len / 2 : 1));
+    if (is_int)
+      halve_i64((const int64_t*)oct[o - 1], len, (int64_t*)oct[o]);
+    else
+      halve_f64((const double*)oct[o - 1], len, (double*)oct[o]);
+    len /= 2;
+  }
+  int32_t total = n_sel > 0 && sel ? n_sel : n_steps;
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t q = 0; q < total; ++q) {
+    int32_t s = sel ? sel[q] : q;
+    int32_t f = f_arr[s], P0 = P0_arr[s], m = m_arr[s], M = M_arr[s];
+    int32_t o = 0;
+    while ((1 << o) < f) ++o;
+    size_t cells = (size_t)M * (size_t)P0;
+    void* prof = malloc(esz * cells);
+    double* dscr = (double*)malloc(sizeof(double) * (size_t)P0);
+    if (is_int)
+      oracle_fold_i64((const int64_t*)oct[o], P0, m, M, (int64_t*)prof);
+    else
+      oracle_fold_f64((const double*)oct[o], P0, m, M, (double*)prof);
+    int32_t wbuf[32];
+    const int32_t* wl = widths;
+    int32_t nwl = nw;
+    if (!widths || nw <= 0) {
+      nwl = oracle_default_widths(P0, wbuf);
+      wl = wbuf;
+    }
+    for (int32_t k = 0; k < M; ++k) {
+      int32_t bw = 0;
+      const char* p = (const char*)prof + esz * (size_t)k * P0;
+      double v = score_profile(p, is_int, P0, wl, nwl, alg, &bw, dscr);
+      snr[first_arr[s] + k] = (float)v;
+      width[first_arr[s] + k] = bw;
+    }
+    free(dscr);
+    free(prof);
+  }
+  for (int32_t o = 0; o <= max_oct; ++o) free(oct[o]);
+  free(oct);
+  return 0;
+}
+
+/* Folded profiles of one step straight from the input series (for checking
+ * raw profiles).  Float input gives double profiles, uint8 gives int64. */
+int oracle_fold_step(const void* series, int32_t dtype, int64_t N, int32_t f,
+                     int32_t P0, int32_t m, int32_t M, void* out) {
+  if (dtype != ORACLE_IN_F32 && dtype != ORACLE_IN_U8) return -1;
+  int32_t o = 0;
+  while ((1 << o) < f) ++o;
+  if (dtype == ORACLE_IN_U8) {
+    int64_t* x = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    const uint8_t* u = (const uint8_t*)series;
+    for (int64_t i = 0; i < N; ++i) x[i] = u[i];
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    oracle_downsample_i64(x, N, o, d);
+    if ((int64_t)m * P0 > (N >> o)) {
+      free(x);
+      free(d);
+      return -1;
+    }
+    oracle_fold_i64(d, P0, m, M, (int64_t*)out);
+    free(x);
+    free(d);
+  } else {
+    double* x = (double*)malloc(sizeof(double) * (size_t)N);
+    const float* v = (const float*)series;
+    for (int64_t i = 0; i < N; ++i) x[i] = v[i];
+    double* d = (double*)malloc(sizeof(double) * (size_t)N);
+    oracle_downsample_f64(x, N, o, d);
+    if ((int64_t)m * P0 > (N >> o)) {
+      free(x);
+      free(d);
+      return -1;
+    }
+    oracle_fold_f64(d, P0, m, M, (double*)out);
+    free(x);
+    free(d);
+  }
+  return 0;
+}
+
+double oracle_mad_constant(void) { return ORACLE_K; }

@@ -1,0 +1,320 @@
+"""Pins of the CPU oracle: each check ties it to something other than itself --
+a hand-derived worked example, a closed form, an invariant, a library routine,
+brute force, or an expectation the paper states.  Each ``pin_*`` raises
+AssertionError when the oracle disagrees.  ``test_oracle_pins.py`` runs them on
+the oracle; ``test_oracle_mutations.py`` runs them on copies of the oracle with
+planted mistakes and requires that every mistake is caught.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def _rows(x, P0, m, M):
+    R = np.zeros((M, P0), dtype=x.dtype)
+    R[:m] = x[: m * P0].reshape(m, P0)
+    return R
+
+
+# ----------------------------------------------------------------- fold
+
+def pin_fold_worked_example(o):
+    """M=4, P0=3 tree worked by hand (Sec. 2.1)."""
+    g = _golden("ffa_worked_example.json")
+    x = np.array(g["rows"], dtype=np.int64).ravel()
+    F = o.fold(x, g["P0"], g["M"], g["M"])
+    assert np.array_equal(F, np.array(g["profiles"])), F
+    Ff = o.fold(x.astype(np.float64), g["P0"], g["M"], g["M"])
+    assert np.array_equal(Ff, np.array(g["profiles"], dtype=np.float64))
+
+
+def pin_fold_closed_forms(o):
+    """Trial 0 is the plain fold at P0; trial M-1 drifts exactly one bin per row
+    (period P0+1, the top of the range of Sec. 2.1); M = 2 by hand."""
+    g = np.random.default_rng(11)
+    for P0, m, M in [(7, 5, 8), (13, 16, 16), (5, 33, 64), (11, 2, 2), (9, 3, 4)]:
+        x = g.integers(-50, 50, size=m * P0 + 3).astype(np.int64)
+        R = _rows(x, P0, m, M)
+        F = o.fold(x, P0, m, M)
+        assert np.array_equal(F[0], R.sum(axis=0)), (P0, m, M)
+        top = sum(np.roll(R[r], -r) for r in range(M))
+        assert np.array_equal(F[M - 1], top), (P0, m, M)
+        if M == 2:
+            assert np.array_equal(F[1], R[0] + np.roll(R[1], -1))
+
+
+def pin_fold_invariants(o):
+    """Every profile sums to the m*P0 samples used (the tail and the zero rows
+    add nothing, Sec. 2.1); the fold is linear (exact in integers)."""
+    g = np.random.default_rng(12)
+    for P0, m, M in [(17, 20, 32), (31, 9, 16), (6, 64, 64)]:
+        a = g.integers(0, 256, size=m * P0 + 5).astype(np.int64)
+        b = g.integers(-9, 9, size=m * P0 + 5).astype(np.int64)
+        Fa, Fb = o.fold(a, P0, m, M), o.fold(b, P0, m, M)
+        assert (Fa.sum(axis=1) == a[: m * P0].sum()).all()
+        assert np.array_equal(o.fold(3 * a - 2 * b, P0, m, M), 3 * Fa - 2 * Fb)
+
+
+def implied_shifts(o, M, P0):
+    """s[k, r]: rotation the fold applies to row r in trial k, read off by
+    folding a unit impulse placed in row r."""
+    S = np.zeros((M, M), dtype=np.int64)
+    for r in range(M):
+        x = np.zeros(M * P0, np.int64)
+        x[r * P0] = 1
+        F = o.fold(x, P0, M, M)
+        for k in range(M):
+            j = np.nonzero(F[k])[0]
+            assert j.size == 1 and F[k, j[0]] == 1
+            S[k, r] = (-j[0]) % P0
+    return S
+
+
+def pin_fold_impulse_response(o):
+    """Trial k must fold at period P0 + k/(M-1) bins (Eqs. 1-2 with N -> M*P0),
+    i.e. rotate row r by about r*k/(M-1).  The tree's integer shifts stay within
+    L/6 bins of that drift, never decrease in k or r, and are exact for k = 0 and
+    k = M-1."""
+    for L in range(1, 7):
+        M = 1 << L
+        P0 = M + 3
+        S = implied_shifts(o, M, P0)
+        ideal = np.outer(np.arange(M), np.arange(M)) / (M - 1)
+        assert np.abs(S - ideal).max() <= L / 6 + 1e-9, L
+        assert (np.diff(S, axis=0) >= 0).all() and (np.diff(S, axis=1) >= 0).all()
+        assert (S[0] == 0).all() and (S[:, 0] == 0).all()
+        assert (S[M - 1] == np.arange(M)).all() and (S[:, M - 1] == np.arange(M)).all()
+
+
+def _brute_shift(L, k, r):
+    if L == 0:
+        return 0
+    h = 1 << (L - 1)
+    if r >= h:
+        return ((k + 1) >> 1) + _brute_shift(L - 1, k >> 1, r - h)
+    return _brute_shift(L - 1, k >> 1, r)
+
+
+def pin_fold_bruteforce(o):
+    """Direct folding with each row rotated by its own shift (no partial-sum
+    reuse) equals the tree, on random integers."""
+    g = np.random.default_rng(13)
+    for P0, m, M in [(5, 7, 8), (19, 30, 32), (8, 64, 64), (3, 17, 32)]:
+        L = M.bit_length() - 1
+        x = g.integers(-1000, 1000, size=m * P0).astype(np.int64)
+        R = _rows(x, P0, m, M)
+        F = o.fold(x, P0, m, M)
+        for k in range(M):
+            direct = sum(np.roll(R[r], -_brute_shift(L, k, r)) for r in range(M))
+            assert np.array_equal(F[k], direct), (P0, m, M, k)
+
+
+def pin_fold_recovers_period(o):
+    """A narrow pulse train with period P0 + k*/(M-1) samples is brightest in
+    trial k* (within one trial): the search finds the period it was given."""
+    g = np.random.default_rng(14)
+    for P0, M, kstar in [(40, 32, 11), (64, 64, 50), (33, 16, 3), (50, 32, 31)]:
+        P = P0 + kstar / (M - 1)
+        n = M * P0
+        x = np.zeros(n)
+        ph = g.uniform(0, P0 - 5)
+        t = ph
+        while t < n - 1:
+            x[int(round(t))] += 1.0
+            t += P
+        F = o.fold(x, P0, M, M)
+        best = int(np.argmax(F.max(axis=1)))
+        assert abs(best - kstar) <= 1, (P0, M, kstar, best)
+
+
+# --------------------------------------------------------------- Alg. 1
+
+def pin_alg1_worked_example(o):
+    g = _golden("alg1_worked_example.json")
+    x = np.array(g["profile"], dtype=np.float64)
+    v, w = o.alg1(x, g["widths"])
+    assert abs(v - g["score"]) < 1e-12 and w == g["best_width"]
+    for ws, expect in g["per_width"].items():
+        v1, w1 = o.alg1(x, [int(ws)])
+        assert abs(v1 - expect) < 1e-5 and w1 == int(ws), (ws, v1)
+    vi, wi = o.alg1(x.astype(np.int64), g["widths"])
+    assert abs(vi - g["score"]) < 1e-12 and wi == 1
+    assert abs(o.mad_constant() * g["mad"] - g["sigma"]) < 1e-12
+
+
+def _alg1_library(profile, widths):
+    """Algorithm 1 from library routines: numpy's median, scipy's MAD with the
+    normal scale, and circular boxcar sums from an FFT-free convolution of the
+    profile with itself tiled once."""
+    from scipy.stats import median_abs_deviation
+
+    med = np.median(profile)
+    sigma = median_abs_deviation(profile, scale="normal")
+    tiled = np.concatenate([profile, profile])
+    best, bw = None, 0
+    for w in widths:
+        box = np.convolve(tiled, np.ones(w), mode="valid")[: profile.size]
+        s = (box.max() - w * med) / (sigma * math.sqrt(w))
+        if best is None or s > best:
+            best, bw = s, w
+    return best, bw
+
+
+def pin_alg1_library(o):
+    g = np.random.default_rng(15)
+    for n in (8, 9, 64, 255, 256, 511):
+        for trial in range(3):
+            x = g.standard_normal(n)
+            x[g.integers(0, n)] += 6.0
+            if trial == 2:  # pulse across the wrap point
+                x[0] += 4.0
+                x[-1] += 4.0
+            widths = [1, 2, 3, 4, 6, 8]
+            v, w = o.alg1(x, widths)
+            ref, rw = _alg1_library(x, widths)
+            assert abs(v - ref) < 1e-9 * max(1.0, abs(ref)) and w == rw, (n, v, ref, w, rw)
+
+
+def pin_alg1_rotation_invariant(o):
+    """The phase origin of a folded profile is arbitrary: rotating it cannot
+    change the score (circular boxcars)."""
+    g = np.random.default_rng(16)
+    for n in (50, 257):
+        x = g.standard_normal(n)
+        x[n - 2:] += 5.0
+        x[:2] += 5.0
+        base = o.alg1(x, [1, 2, 4, 8])
+        for s in (1, 7, n // 2):
+            r = o.alg1(np.roll(x, s), [1, 2, 4, 8])
+            assert abs(r[0] - base[0]) < 1e-9 and r[1] == base[1]
+
+
+def pin_alg1_integer_path(o):
+    """The exact-integer evaluation (doubled median, quadrupled MAD) equals the
+    plain double evaluation of Eqs. 3-4 on the same integers."""
+    g = np.random.default_rng(17)
+    for n in (10, 11, 256, 257, 500):
+        x = g.integers(0, 3000, size=n).astype(np.int64)
+        x[g.integers(0, n)] += 20000
+        wl = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+        vi, wi = o.alg1(x, wl)
+        vf, wf = o.alg1(x.astype(np.float64), wl)
+        assert abs(vi - vf) < 1e-9 * abs(vf) and wi == wf, (n, vi, vf)
+
+
+def pin_alg1_mad_zero(o):
+    x = np.full(16, 7.0)
+    x[3] = 100.0
+    assert o.alg1(x, [1, 2]) == (0.0, 0)
+    assert o.alg1(x.astype(np.int64), [1, 2]) == (0.0, 0)
+
+
+def pin_alg1_snr_level(o):
+    """A top-hat of height S and width w = delta*P in unit white noise has S/N
+    S*sqrt(delta*P) (Eq. 10); with the matched width in the set, the score
+    averaged over 30 profiles lands close to it (the maximum over positions
+    and widths adds a small upward bias)."""
+    g = np.random.default_rng(18)
+    P, w, S = 1024, 16, 2.0
+    expect = S * math.sqrt(w)
+    vals = []
+    for _ in range(30):
+        x = g.standard_normal(P)
+        j = int(g.integers(0, P))
+        x[(j + np.arange(w)) % P] += S
+        vals.append(o.alg1(x, [1, 2, 4, 8, 16, 32, 64])[0])
+    ratio = float(np.mean(vals)) / expect
+    assert 0.90 < ratio < 1.15, ratio
+
+
+def pin_default_widths(o):
+    """Powers of two up to the first one exceeding 20% of the profile (Sec. 2.2.1)."""
+    assert o.default_widths(256) == [1, 2, 4, 8, 16, 32, 64]
+    assert o.default_widths(319) == [1, 2, 4, 8, 16, 32, 64]
+    assert o.default_widths(320) == [1, 2, 4, 8, 16, 32, 64, 128]
+    assert o.default_widths(5) == [1, 2]
+
+
+# ---------------------------------------------------- plan / downsample
+
+def pin_downsample(o):
+    g = np.random.default_rng(19)
+    for n in (64, 65, 1001):
+        xi = g.integers(0, 256, size=n)
+        for oc in range(4):
+            ref = xi[: (n >> oc) << oc].reshape(-1, 1 << oc).sum(axis=1)
+            assert np.array_equal(o.downsample(xi.astype(np.int64), oc), ref)
+        xf = g.standard_normal(n)
+        ref = xf[: (n >> 2) << 2].reshape(-1, 4).sum(axis=1)
+        assert np.allclose(o.downsample(xf, 2), ref, rtol=0, atol=1e-12)
+
+
+def pin_plan(o):
+    """Workloads of the benchmark: one octave of 500 base periods; three octaves
+    of 256; and seven octaves starting at f = 2 for 0.5-30 s at 0.512 ms.  The
+    trial periods of a step run from P0 to P0 + 1 inclusive in steps of
+    P0/(N* - P0) bins with N* = M*P0 (Eqs. 1-2)."""
+    p = o.plan(65536, 1e-3, 0.5, 1.0, 500)
+    assert p.n_steps == 500 and p.n_trials == 65152
+    assert list(p.P0[:3]) == [500, 501, 502] and p.P0[-1] == 999
+    p = o.plan(1 << 20, 1e-3, 0.256, 2.048, 256)
+    assert p.n_steps == 768 and p.n_trials == 1835008
+    assert sorted(set(p.f.tolist())) == [1, 2, 4]
+    p = o.plan(1 << 23, 0.512e-3, 0.5, 30.0, 256)
+    assert p.n_steps == 1505 and p.n_trials == 4491520
+    assert sorted(set(p.f.tolist())) == [2, 4, 8, 16, 32, 64, 128]
+    for s in (0, 700, 1504):
+        f, P0, m, M = (int(p.f[s]), int(p.P0[s]), int(p.m[s]), int(p.M[s]))
+        assert m == ((1 << 23) // f) // P0 and M >= m > M // 2, s
+    per = p.periods()
+    s = 100
+    a, M, P0, f = int(p.first[s]), int(p.M[s]), int(p.P0[s]), int(p.f[s])
+    bins = per[a:a + M] / (f * 0.512e-3)
+    assert abs(bins[0] - P0) < 1e-9 and abs(bins[-1] - (P0 + 1)) < 1e-9
+    assert np.allclose(np.diff(bins), P0 / (M * P0 - P0))
+
+
+def pin_search_matches_parts(o):
+    """The search driver is the composition of downsampling, fold and Alg. 1."""
+    g = np.random.default_rng(20)
+    x = g.integers(0, 256, size=6000).astype(np.uint8)
+    p = o.plan(6000, 1e-3, 0.020, 0.120, 20)
+    snr, wid = o.search(x, p, [1, 2, 4])
+    for s in range(0, p.n_steps, 7):
+        f, P0, m, M = int(p.f[s]), int(p.P0[s]), int(p.m[s]), int(p.M[s])
+        oc = f.bit_length() - 1
+        F = o.fold(o.downsample(x.astype(np.int64), oc), P0, m, M)
+        for k in range(M):
+            v, w = o.alg1(F[k], [1, 2, 4])
+            assert snr[p.first[s] + k] == np.float32(v) and wid[p.first[s] + k] == w
+
+
+ALL_PINS = [
+    pin_fold_worked_example,
+    pin_fold_closed_forms,
+    pin_fold_invariants,
+    pin_fold_impulse_response,
+    pin_fold_bruteforce,
+    pin_fold_recovers_period,
+    pin_alg1_worked_example,
+    pin_alg1_library,
+    pin_alg1_rotation_invariant,
+    pin_alg1_integer_path,
+    pin_alg1_mad_zero,
+    pin_alg1_snr_level,
+    pin_default_widths,
+    pin_downsample,
+    pin_plan,
+    pin_search_matches_parts,
+]

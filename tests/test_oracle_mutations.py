@@ -1,0 +1,52 @@
+"""Plant plausible mistakes in copies of the oracle source (on the CPU) and
+require that the pins catch every one of them."""
+import os
+import subprocess
+
+import pytest
+
+from oracle_pins import ALL_PINS
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "ffa_oracle.c")
+
+# (name, text in the oracle source, planted replacement)
+MUTATIONS = [
+    ("shift_floor", "int32_t shift = (t + 1) / 2;", "int32_t shift = t / 2;"),
+    ("shift_right", "B[(size_t)src * P0 + (j + shift) % P0]", "B[(size_t)src * P0 + (j + P0 - shift) % P0]"),
+    ("wrong_partial", "int32_t src = t / 2;", "int32_t src = t % half;"),
+    ("shift_on_head", "o[j] = A[(size_t)src * P0 + j] +                                   \\\n                   B[(size_t)src * P0 + (j + shift) % P0];",
+     "o[j] = A[(size_t)src * P0 + (j + shift) % P0] +                      \\\n                   B[(size_t)src * P0 + j];"),
+    ("median_lower", "return 0.5 * (scratch[n / 2 - 1] + scratch[n / 2]);", "return scratch[n / 2];"),
+    ("k_rounded", "#define ORACLE_K 1.482602218505602", "#define ORACLE_K 1.4826"),
+    ("box_not_circular", "for (int32_t i = 0; i < w; ++i) s += F[(j + i) % P0];\n  return s;\n}\n\nstatic int64_t",
+     "for (int32_t i = 0; i < w && j + i < P0; ++i) s += F[j + i];\n  return s;\n}\n\nstatic int64_t"),
+    ("divide_by_width", "double snr = (peak - (double)w * med) / (sigma * sqrt((double)w));",
+     "double snr = (peak - (double)w * med) / (sigma * (double)w);"),
+    ("mad_about_zero", "for (int32_t j = 0; j < P0; ++j) dev[j] = fabs(F[j] - med);",
+     "for (int32_t j = 0; j < P0; ++j) dev[j] = fabs(F[j]);"),
+    ("int_num_halved", "int64_t num = 2 * (2 * peak - (int64_t)w * med2);", "int64_t num = 2 * peak - (int64_t)w * med2;"),
+    ("downsample_dup", "y[i] = x[2 * i] + x[2 * i + 1];\n}\n\nstatic void halve_i64", "y[i] = x[2 * i] + x[2 * i];\n}\n\nstatic void halve_i64"),
+    ("rows_ceil", "int64_t m = Nf / P0;", "int64_t m = (Nf + P0 - 1) / P0;"),
+    ("pad_one_more", "while (M < m) M <<= 1;", "while (M <= m) M <<= 1;"),
+    ("default_width_rule", "if (5 * v > P0) break;", "if (5 * v >= P0) break;"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_mutation_is_caught(oracle_mod, tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found once: {name}"
+    mut = tmp_path / f"{name}.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / f"lib{name}.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(mut), "-lm"],
+                   check=True)
+    caught = []
+    with oracle_mod.library(str(so)):
+        for pin in ALL_PINS:
+            try:
+                pin(oracle_mod)
+            except Exception:  # noqa: BLE001 - any failure counts as caught
+                caught.append(pin.__name__)
+    assert caught, f"planted mistake {name} passed every pin"
