@@ -1,0 +1,196 @@
+/*
+ * ffa.h -- C ABI of the MI355X FFA periodicity search.
+ *
+ * The library folds a time series at every trial period of a period range
+ * with the Fast Folding Algorithm and scores every folded profile with a
+ * boxcar matched filter, producing a periodogram (Cameron et al. 2017,
+ * "An investigation of pulsar searching techniques with the Fast Folding
+ * Algorithm", MNRAS; referred to below as "the paper").
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device (HBM) pointers on the GPU that was
+ *     current when the plan was created; everything else is host memory.
+ *   - The caller owns every data buffer and every workspace.  The library
+ *     owns plans and servers and never frees caller memory.
+ *   - Calls that take a stream enqueue work on it and return before the GPU
+ *     is done (asynchronous).  `stream` is a hipStream_t passed as void*;
+ *     NULL is the default stream.  Argument errors are detected on the host
+ *     and returned before anything is enqueued.
+ *   - A launch error is returned as FFA_ERR_DEVICE by the call that made it.
+ *   - No C++ exception crosses this boundary.  ffa_last_error() gives a
+ *     human-readable detail of the calling thread's last failure.
+ *   - Input samples must be finite.
+ */
+#ifndef FFA_H_
+#define FFA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffa_plan_s* ffa_plan;
+typedef struct ffa_server_s* ffa_server;
+
+typedef enum {
+  FFA_OK = 0,
+  FFA_ERR_INVALID = -1,     /* bad argument; nothing enqueued */
+  FFA_ERR_NOMEM = -2,       /* host or device allocation failed */
+  FFA_ERR_DEVICE = -3,      /* HIP call or kernel launch failed */
+  FFA_ERR_UNSUPPORTED = -4, /* valid but outside what the library handles */
+  FFA_ERR_BUSY = -5,        /* server admission queue full */
+  FFA_ERR_TIMEOUT = -6      /* wait ran out of time */
+} ffa_status;
+
+/* Sample type of the input series (the two formats the paper's search reads,
+ * Sec. 2.3.1): 32-bit float, or 8-bit unsigned summed exactly in integers. */
+typedef enum { FFA_IN_F32 = 0, FFA_IN_U8 = 1 } ffa_dtype;
+
+/* Profile score.  ALG1: boxcar matched filter on the profile normalised by its
+ * median and K*MAD (Sec. 2.2.1, Eqs. 3-4).  ALG2: boxcar first, then mean and
+ * standard deviation outside a 20% window around the peak (Sec. 2.2.2,
+ * Eq. 5). */
+typedef enum { FFA_SNR_ALG1_MAD = 1, FFA_SNR_ALG2_OFFPULSE = 2 } ffa_snr;
+
+/* Search description.
+ *   N          samples in the series (>= 2)
+ *   tsamp_s    sampling interval in seconds
+ *   pmin_s, pmax_s   period range [pmin, pmax) in seconds
+ *   widths, n_widths boxcar widths in bins (copied; NULL/0 selects the
+ *              paper's rule per step: 1, 2, 4, ... up to and including the
+ *              first power of two above 20% of P0, Sec. 2.2.1).  Widths larger
+ *              than a step's P0 are skipped for that step.  At most 32.
+ *   bins_min   B: the base period P0 (in downsampled bins) runs over [B, 2B)
+ *              in each octave; octave o searches the series downsampled by
+ *              f = 2^o (Sec. 2.3.1).  2 <= B <= 1024.
+ *   max_octaves  0 = as many as pmax needs, else at most this many octaves.
+ *   dtype      ffa_dtype;   snr  ffa_snr.
+ *
+ * Steps: for each octave f = 1, 2, 4, ... and each integer P0 in [B, 2B)
+ * with pmin <= P0*f*tsamp < pmax, one FFA execution folds m = floor(N_f/P0)
+ * rows of the series downsampled by f (N_f = floor(N/f) samples; the tail is
+ * dropped), zero-padded to M = 2^ceil(log2 m) rows (Sec. 2.1).  Steps with
+ * m < 2 are skipped.  Trial k = 0..M-1 of a step has period
+ * f*tsamp*(P0 + k/(M-1)) seconds (Eqs. 1-2 with N replaced by M*P0).
+ * Trials are numbered in step order: octave ascending, then P0 ascending,
+ * then k. */
+typedef struct {
+  int64_t N;
+  double tsamp_s;
+  double pmin_s;
+  double pmax_s;
+  const int32_t* widths;
+  int32_t n_widths;
+  int32_t bins_min;
+  int32_t max_octaves;
+  int32_t dtype;
+  int32_t snr;
+} ffa_plan_desc;
+
+/* Build a plan: step list, pass split of every step, device-side tables.
+ * Allocates device memory for the tables on the current GPU.  Errors:
+ * FFA_ERR_INVALID (bad field, no step, a step with no usable width),
+ * FFA_ERR_UNSUPPORTED (uint8 series with 255*N >= 2^31, or a step too large
+ * for the kernels), FFA_ERR_NOMEM. */
+ffa_status ffa_plan_create(const ffa_plan_desc* desc, ffa_plan* out);
+ffa_status ffa_plan_destroy(ffa_plan plan);
+
+/* Totals of a plan.  ws_bytes is the device workspace ffa_search and
+ * ffa_fold need.  Any output pointer may be NULL. */
+ffa_status ffa_plan_query(ffa_plan plan, int64_t* n_trials, int32_t* n_steps,
+                          size_t* ws_bytes);
+
+/* Shape of step s: octave factor f, base period P0, data rows m, padded rows
+ * M, index of its first trial.  Any output pointer may be NULL. */
+ffa_status ffa_plan_step(ffa_plan plan, int32_t s, int32_t* f, int32_t* P0,
+                         int32_t* m, int32_t* M, int64_t* first_trial);
+
+/* Pass split of step s: number of FFA passes and the butterfly levels each
+ * pass runs on chip (depths[0..n_passes-1], at most 8 entries written). */
+ffa_status ffa_plan_passes(ffa_plan plan, int32_t s, int32_t* n_passes,
+                           int32_t* depths);
+
+/* Trial periods in seconds, host array of n_trials doubles. */
+ffa_status ffa_plan_periods(ffa_plan plan, double* host_periods_s);
+
+/* Periodogram of one series (Sec. 2.2: one score per folded profile, plotted
+ * against trial period).
+ *   d_series  N samples, float32 or uint8 per the plan's dtype
+ *   d_snr     n_trials float32: score of each trial (0 where the profile's
+ *             MAD is 0)
+ *   d_width   n_trials int32: boxcar width in bins that gave the score (first
+ *             width in list order on ties; 0 where MAD is 0)
+ *   d_ws      workspace of at least ws_bytes (ffa_plan_query), 256-B aligned
+ * Float series are centred on their mean before folding; the scores of both
+ * algorithms are unchanged by an offset.  uint8 series are summed exactly in
+ * 32-bit integers.  Errors: FFA_ERR_INVALID (NULL pointer, small workspace,
+ * wrong device), FFA_ERR_DEVICE. */
+ffa_status ffa_search(ffa_plan plan, const void* d_series, float* d_snr,
+                      int32_t* d_width, void* d_ws, size_t ws_bytes,
+                      void* stream);
+
+/* Raw folded profiles of step `step` (Sec. 2.1): M rows of P0 bins, row k is
+ * trial k.  float32 series give float32 sums; uint8 series give exact int32
+ * sums.  Not centred.  Errors as ffa_search. */
+ffa_status ffa_fold(ffa_plan plan, const void* d_series, int32_t step,
+                    void* d_profiles, void* d_ws, size_t ws_bytes,
+                    void* stream);
+
+/* Best trial of a periodogram: the largest score, the first trial on ties.
+ *   d_snr        n_trials scores (as from ffa_search)
+ *   d_best       one int64: index of the best trial
+ * Errors: FFA_ERR_INVALID, FFA_ERR_DEVICE. */
+ffa_status ffa_best(const float* d_snr, int64_t n_trials, int64_t* d_best,
+                    void* stream);
+
+/* Batched search: the periodograms of n series, each with its own plan, in
+ * one persistent launch over a shared work queue.
+ *   plans[i], d_series[i], d_snr[i], d_width[i]  host arrays of n entries
+ *   d_ws   workspace of at least ffa_batch_workspace(n, plans) bytes
+ * Results equal those of ffa_search on each series.  The plans must have been
+ * created on the current GPU. */
+ffa_status ffa_batch_workspace(int32_t n, const ffa_plan* plans,
+                               size_t* ws_bytes);
+ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,
+                            const void* const* d_series, float* const* d_snr,
+                            int32_t* const* d_width, void* d_ws,
+                            size_t ws_bytes, void* stream);
+
+/* Search server: continuous batching of requests that arrive over time.
+ * The server keeps device buffers in a pool of at most hbm_budget_bytes,
+ * admits a request when its footprint (series + workspace + periodogram)
+ * fits in what is free, and runs each scheduling round as one batched
+ * launch over every admitted request.  Requests arriving while a round runs
+ * join the next round.  n_streams > 1 overlaps host-device copies with
+ * compute.  All server calls are thread-safe. */
+ffa_status ffa_server_create(size_t hbm_budget_bytes, int32_t n_streams,
+                             ffa_server* out);
+
+/* Submit a search of `series` (host memory if is_device == 0, else a device
+ * pointer that must stay valid until the request completes) with `plan`.
+ * The plan must outlive the request.  Returns a ticket.  Errors:
+ * FFA_ERR_INVALID, FFA_ERR_UNSUPPORTED (footprint above the whole budget),
+ * FFA_ERR_BUSY (admission queue full). */
+ffa_status ffa_server_submit(ffa_server s, ffa_plan plan, const void* series,
+                             int is_device, int64_t* ticket);
+
+/* Wait for a ticket (timeout_us < 0: forever).  Copies the periodogram to the
+ * host arrays (n_trials entries each; either may be NULL) and reports the
+ * submit-to-completion latency in seconds.  A ticket can be waited on once.
+ * Errors: FFA_ERR_INVALID (unknown ticket), FFA_ERR_TIMEOUT, FFA_ERR_DEVICE
+ * (the request's launch failed; other requests are unaffected). */
+ffa_status ffa_server_wait(ffa_server s, int64_t ticket, int64_t timeout_us,
+                           float* host_snr, int32_t* host_width,
+                           double* latency_s);
+ffa_status ffa_server_destroy(ffa_server s);
+
+const char* ffa_status_str(ffa_status st);
+const char* ffa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFA_H_ */

@@ -1,0 +1,250 @@
+"""Python binding of libffa.so (ctypes).  Argument marshalling only: every step
+of the search runs in the library's HIP kernels.  PyTorch supplies device
+memory and streams (``tensor.data_ptr()``, ``torch.cuda.current_stream()``).
+
+Importing this module loads the in-tree ``libffa.so`` and raises ImportError
+when it has not been built (``python -m paper_1703_05581_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffa.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1703_05581_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FFA_OK = 0
+FFA_ERR_INVALID = -1
+FFA_ERR_NOMEM = -2
+FFA_ERR_DEVICE = -3
+FFA_ERR_UNSUPPORTED = -4
+FFA_ERR_BUSY = -5
+FFA_ERR_TIMEOUT = -6
+FFA_IN_F32 = 0
+FFA_IN_U8 = 1
+FFA_SNR_ALG1_MAD = 1
+FFA_SNR_ALG2_OFFPULSE = 2
+
+# every symbol include/ffa.h declares
+EXPORTS = (
+    "ffa_plan_create", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
+    "ffa_plan_periods", "ffa_search", "ffa_fold", "ffa_best", "ffa_batch_workspace",
+    "ffa_search_batch", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
+    "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
+)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64),
+        ("tsamp_s", ctypes.c_double),
+        ("pmin_s", ctypes.c_double),
+        ("pmax_s", ctypes.c_double),
+        ("widths", ctypes.POINTER(ctypes.c_int32)),
+        ("n_widths", ctypes.c_int32),
+        ("bins_min", ctypes.c_int32),
+        ("max_octaves", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("snr", ctypes.c_int32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+_P = ctypes.POINTER
+
+_lib.ffa_plan_create.argtypes = [_P(PlanDesc), _P(_vp)]
+_lib.ffa_plan_destroy.argtypes = [_vp]
+_lib.ffa_plan_query.argtypes = [_vp, _P(_i64), _P(_i32), _P(_sz)]
+_lib.ffa_plan_step.argtypes = [_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i64)]
+_lib.ffa_plan_passes.argtypes = [_vp, _i32, _P(_i32), _P(_i32)]
+_lib.ffa_plan_periods.argtypes = [_vp, _P(ctypes.c_double)]
+_lib.ffa_search.argtypes = [_vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.ffa_fold.argtypes = [_vp, _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.ffa_best.argtypes = [_vp, _i64, _vp, _vp]
+_lib.ffa_batch_workspace.argtypes = [_i32, _P(_vp), _P(_sz)]
+_lib.ffa_search_batch.argtypes = [_i32, _P(_vp), _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
+_lib.ffa_server_create.argtypes = [_sz, _i32, _P(_vp)]
+_lib.ffa_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int, _P(_i64)]
+_lib.ffa_server_wait.argtypes = [_vp, _i64, _i64, _vp, _vp, _P(ctypes.c_double)]
+_lib.ffa_server_destroy.argtypes = [_vp]
+_lib.ffa_status_str.argtypes = [ctypes.c_int]
+_lib.ffa_status_str.restype = ctypes.c_char_p
+_lib.ffa_last_error.argtypes = []
+_lib.ffa_last_error.restype = ctypes.c_char_p
+for _n in EXPORTS:
+    if _n not in ("ffa_status_str", "ffa_last_error"):
+        getattr(_lib, _n).restype = ctypes.c_int
+
+
+class FFAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = _lib.ffa_last_error().decode(errors="replace")
+        name = _lib.ffa_status_str(status).decode()
+        super().__init__(f"{where}: {name} ({detail})")
+
+
+def _check(st: int, where: str) -> None:
+    if st != FFA_OK:
+        raise FFAError(st, where)
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+@dataclass
+class StepInfo:
+    f: int
+    P0: int
+    m: int
+    M: int
+    first_trial: int
+
+
+class Plan:
+    """A search plan (ffa_plan_create).  ``dtype`` is "f32" or "u8"."""
+
+    def __init__(self, N: int, tsamp: float, pmin: float, pmax: float, bins_min: int,
+                 widths=None, dtype: str = "f32", snr: int = FFA_SNR_ALG1_MAD, max_octaves: int = 0):
+        self._h = _vp()
+        w = list(widths) if widths else []
+        self._warr = (ctypes.c_int32 * max(len(w), 1))(*w)
+        desc = PlanDesc(N=N, tsamp_s=tsamp, pmin_s=pmin, pmax_s=pmax,
+                        widths=ctypes.cast(self._warr, _P(ctypes.c_int32)) if w else None,
+                        n_widths=len(w), bins_min=bins_min, max_octaves=max_octaves,
+                        dtype=FFA_IN_U8 if dtype == "u8" else FFA_IN_F32, snr=snr)
+        _check(_lib.ffa_plan_create(ctypes.byref(desc), ctypes.byref(self._h)), "ffa_plan_create")
+        self.N = N
+        self.tsamp = tsamp
+        self.dtype = dtype
+        nt, ns, ws = _i64(), _i32(), _sz()
+        _check(_lib.ffa_plan_query(self._h, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(ws)),
+               "ffa_plan_query")
+        self.n_trials, self.n_steps, self.ws_bytes = nt.value, ns.value, ws.value
+
+    @classmethod
+    def from_args(cls, pa, snr: int = FFA_SNR_ALG1_MAD) -> "Plan":
+        """From a ``synth.PlanArgs``."""
+        return cls(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min, pa.widths, pa.dtype, snr,
+                   pa.max_octaves)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def close(self) -> None:
+        if self._h:
+            _lib.ffa_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def step(self, s: int) -> StepInfo:
+        f, P0, m, M = _i32(), _i32(), _i32(), _i32()
+        ft = _i64()
+        _check(_lib.ffa_plan_step(self._h, s, ctypes.byref(f), ctypes.byref(P0), ctypes.byref(m),
+                                  ctypes.byref(M), ctypes.byref(ft)), "ffa_plan_step")
+        return StepInfo(f.value, P0.value, m.value, M.value, ft.value)
+
+    def passes(self, s: int) -> list[int]:
+        n = _i32()
+        d = (ctypes.c_int32 * 8)()
+        _check(_lib.ffa_plan_passes(self._h, s, ctypes.byref(n), d), "ffa_plan_passes")
+        return [d[i] for i in range(n.value)]
+
+    def periods(self):
+        import numpy as np
+
+        out = np.empty(self.n_trials, dtype=np.float64)
+        _check(_lib.ffa_plan_periods(self._h, out.ctypes.data_as(_P(ctypes.c_double))),
+               "ffa_plan_periods")
+        return out
+
+    # ------------------------------------------------------------ device calls
+
+    def workspace(self, device=None):
+        import torch
+
+        return torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device or "cuda")
+
+    @staticmethod
+    def _aligned(ws) -> int:
+        p = ws.data_ptr()
+        return (p + 255) // 256 * 256
+
+    def search(self, series, snr=None, width=None, ws=None, stream=None):
+        """Periodogram of ``series`` (a cuda tensor).  Returns (snr f32, width i32)."""
+        import torch
+
+        self._check_series(series)
+        dev = series.device
+        if snr is None:
+            snr = torch.empty(self.n_trials, dtype=torch.float32, device=dev)
+        if width is None:
+            width = torch.empty(self.n_trials, dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = self.workspace(dev)
+        base = self._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        _check(_lib.ffa_search(self._h, series.data_ptr(), snr.data_ptr(), width.data_ptr(), base,
+                               avail, _stream_ptr(stream)), "ffa_search")
+        return snr, width
+
+    def fold(self, series, step: int, out=None, ws=None, stream=None):
+        """Raw profiles (M, P0) of step ``step`` (f32 or exact int32)."""
+        import torch
+
+        self._check_series(series)
+        info = self.step(step)
+        dt = torch.int32 if self.dtype == "u8" else torch.float32
+        if out is None:
+            out = torch.empty((info.M, info.P0), dtype=dt, device=series.device)
+        if ws is None:
+            ws = self.workspace(series.device)
+        base = self._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        _check(_lib.ffa_fold(self._h, series.data_ptr(), step, out.data_ptr(), base, avail,
+                             _stream_ptr(stream)), "ffa_fold")
+        return out
+
+    def _check_series(self, series):
+        import torch
+
+        want = torch.uint8 if self.dtype == "u8" else torch.float32
+        if series.dtype != want or series.numel() != self.N or not series.is_contiguous():
+            raise ValueError(f"series must be a contiguous {want} tensor of {self.N} samples")
+        if not series.is_cuda:
+            raise ValueError("series must be on the GPU")
+
+
+def best(snr, stream=None) -> int:
+    """Index of the best trial of a periodogram (first on ties), computed on the GPU."""
+    import torch
+
+    out = torch.empty(1, dtype=torch.int64, device=snr.device)
+    _check(_lib.ffa_best(snr.data_ptr(), snr.numel(), out.data_ptr(), _stream_ptr(stream)), "ffa_best")
+    return int(out.item())

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every declared entry point, validates arguments, and plans exactly the steps
+the oracle plans."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1703_05581_amd import ffa, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "ffa.h")).read()
+    return sorted(set(re.findall(r"\b(ffa_[a-z_]+)\s*\(", hdr)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 17
+    lib = ffa.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ffa.EXPORTS)
+
+
+def test_status_strings():
+    assert ffa.lib().ffa_status_str(0) == b"FFA_OK"
+    assert ffa.lib().ffa_status_str(-5) == b"FFA_ERR_BUSY"
+
+
+@pytest.mark.parametrize("wl", [1, 2, 3])
+def test_plan_matches_oracle(oracle_mod, wl):
+    pa = synth.plan_args(wl)
+    p = ffa.Plan.from_args(pa)
+    o = oracle_mod.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
+    assert p.n_steps == o.n_steps and p.n_trials == o.n_trials
+    for s in range(p.n_steps):
+        st = p.step(s)
+        assert (st.f, st.P0, st.m, st.M, st.first_trial) == (
+            o.f[s], o.P0[s], o.m[s], o.M[s], o.first[s]), s
+        d = p.passes(s)
+        assert sum(d) == int(o.M[s]).bit_length() - 1 and all(x >= 1 for x in d)
+    assert np.array_equal(p.periods(), o.periods())
+
+
+def test_plan_matches_oracle_random(oracle_mod):
+    g = np.random.default_rng(5)
+    for _ in range(40):
+        N = int(g.integers(100, 300000))
+        tsamp = float(g.choice([1e-3, 0.512e-3, 6.4e-5, 2.5e-4]))
+        B = int(g.integers(2, 300))
+        pmin = float(g.uniform(B * tsamp * 0.5, B * tsamp * 4))
+        pmax = pmin * float(g.uniform(1.01, 40))
+        mo = int(g.integers(0, 4))
+        try:
+            p = ffa.Plan(N, tsamp, pmin, pmax, B, [1, 2, 4], max_octaves=mo)
+        except ffa.FFAError as e:
+            assert e.status == ffa.FFA_ERR_INVALID
+            assert oracle_mod.plan(N, tsamp, pmin, pmax, B, mo).n_steps == 0
+            continue
+        o = oracle_mod.plan(N, tsamp, pmin, pmax, B, mo)
+        assert p.n_steps == o.n_steps and p.n_trials == o.n_trials
+        got = np.array([tuple(vars(p.step(s)).values()) for s in range(p.n_steps)])
+        ref = np.stack([o.f, o.P0, o.m, o.M, o.first], axis=1)
+        assert np.array_equal(got, ref)
+
+
+def _desc(**kw):
+    base = dict(N=65536, tsamp_s=1e-3, pmin_s=0.5, pmax_s=1.0, widths=None, n_widths=0,
+                bins_min=500, max_octaves=0, dtype=0, snr=1)
+    base.update(kw)
+    return ffa.PlanDesc(**base)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(N=1), ffa.FFA_ERR_INVALID),
+    (dict(tsamp_s=0.0), ffa.FFA_ERR_INVALID),
+    (dict(pmax_s=0.4), ffa.FFA_ERR_INVALID),
+    (dict(bins_min=1), ffa.FFA_ERR_INVALID),
+    (dict(bins_min=2000), ffa.FFA_ERR_INVALID),
+    (dict(dtype=7), ffa.FFA_ERR_INVALID),
+    (dict(snr=9), ffa.FFA_ERR_INVALID),
+    (dict(n_widths=40), ffa.FFA_ERR_INVALID),
+    (dict(n_widths=3), ffa.FFA_ERR_INVALID),           # NULL widths
+    (dict(pmin_s=50.0, pmax_s=60.0), ffa.FFA_ERR_INVALID),  # no step
+    (dict(N=1 << 24, dtype=1, pmin_s=0.5, pmax_s=1.0), ffa.FFA_ERR_UNSUPPORTED),
+])
+def test_plan_create_rejects(kw, status):
+    h = ctypes.c_void_p()
+    d = _desc(**kw)
+    assert ffa.lib().ffa_plan_create(ctypes.byref(d), ctypes.byref(h)) == status
+    assert not h
+    assert ffa.lib().ffa_last_error()
+
+
+def test_plan_rejects_widths_all_above_p0():
+    w = (ctypes.c_int32 * 1)(600)
+    d = _desc(widths=ctypes.cast(w, ctypes.POINTER(ctypes.c_int32)), n_widths=1)
+    h = ctypes.c_void_p()
+    assert ffa.lib().ffa_plan_create(ctypes.byref(d), ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+
+
+def test_null_arguments_rejected_before_gpu():
+    lib = ffa.lib()
+    assert lib.ffa_plan_query(None, None, None, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_search(None, None, None, None, None, 0, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_fold(None, None, 0, None, None, 0, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_best(None, 0, None, None) == ffa.FFA_ERR_INVALID
+    p = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2, 4])
+    # a small workspace is refused on the host, before any device call
+    assert lib.ffa_search(p.handle, 1, 2, 3, 256, 16, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_search(p.handle, 1, 2, 3, 257, p.ws_bytes, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_fold(p.handle, 1, p.n_steps, 3, 256, p.ws_bytes, None) == ffa.FFA_ERR_INVALID

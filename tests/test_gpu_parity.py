@@ -1,0 +1,178 @@
+"""GPU search and fold against the oracle, through the C ABI."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from parity import check_periodogram, check_profiles, step_trials
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ffa():
+    from paper_1703_05581_amd import ffa as mod
+
+    return mod
+
+
+def _sample_steps(plan_o, count: int) -> list[int]:
+    n = plan_o.n_steps
+    if n <= count:
+        return list(range(n))
+    picks = set(np.linspace(0, n - 1, count).round().astype(int).tolist())
+    # every octave's first and last step
+    for f in np.unique(plan_o.f):
+        where = np.nonzero(plan_o.f == f)[0]
+        picks.update([int(where[0]), int(where[-1])])
+    return sorted(picks)
+
+
+def run_case(torch, ffa, oracle, x, N, tsamp, pmin, pmax, B, widths, dtype, steps_max=None,
+             check_fold=0, max_octaves=0):
+    exact = dtype == "u8"
+    print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype}", flush=True)
+    plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, max_octaves=max_octaves)
+    xt = torch.from_numpy(x).cuda()
+    snr, wid = plan.search(xt)
+    torch.cuda.synchronize()
+    snr_g, w_g = snr.cpu().numpy(), wid.cpu().numpy()
+    op = oracle.plan(N, tsamp, pmin, pmax, B, max_octaves)
+    steps = list(range(op.n_steps)) if steps_max is None else _sample_steps(op, steps_max)
+    snr_o, w_o = oracle.search(x, op, widths, steps=steps)
+    idx = step_trials(op, steps)
+    summary = check_periodogram(oracle, x, op, widths, snr_g, w_g, snr_o, w_o, idx, exact)
+    for s in steps[:: max(1, len(steps) // max(check_fold, 1))][:check_fold]:
+        prof = plan.fold(xt, s).cpu().numpy()
+        ref = oracle.fold_step(x, int(op.f[s]), int(op.P0[s]), int(op.m[s]), int(op.M[s]))
+        check_profiles(prof, ref, exact)
+    return plan, summary
+
+
+W10 = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+
+# (N, tsamp, pmin, pmax, B, widths) -- small searches that cover: m = 2, m a
+# power of two and one above it, odd and prime P0, P0 in every register class
+# (<= 64, 128, 256, 512, 1024, 2048), one, two and three passes, widths above P0.
+SMALL = [
+    (1000, 1e-3, 0.300, 0.600, 300, [1, 2, 4]),            # m = 2 and 3 (L = 1, 2)
+    (6000, 1e-3, 0.020, 0.120, 20, [1, 2, 4, 8, 16, 32, 64]),  # P0 < 64, widths > P0 dropped
+    (20000, 1e-3, 0.070, 0.250, 70, W10),                   # P0 in (64, 140)
+    (65536, 1e-3, 0.5, 1.0, 500, W10),                      # P0 500..999, 2-pass
+    (30000, 1e-3, 0.200, 0.520, 200, W10),                  # 256 < P0 < 512 and below
+    (50000, 1e-3, 1.900, 2.200, 1000, [1, 2, 4, 8]),        # P0 near 2047, 2 passes
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"N{c[0]}_B{c[4]}" for c in SMALL])
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_small_search_and_fold(torch_cuda, ffa, oracle_mod, case, dtype):
+    from paper_1703_05581_amd import synth
+
+    N, tsamp, pmin, pmax, B, widths = case
+    x = synth.random_series(7 + N, N, dtype)
+    run_case(torch_cuda, ffa, oracle_mod, x, N, tsamp, pmin, pmax, B, widths, dtype,
+             steps_max=40, check_fold=4)
+
+
+def test_three_pass_u8(torch_cuda, ffa, oracle_mod):
+    """Large P0 with enough rows to need three passes."""
+    from paper_1703_05581_amd import synth
+
+    N, B = 600000, 1000
+    plan = ffa.Plan(N, 1e-3, 1.990, 2.010, B, [1, 2, 4, 8])
+    assert max(len(plan.passes(s)) for s in range(plan.n_steps)) >= 3
+    x = synth.random_series(99, N, "u8")
+    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 1.990, 2.010, B, [1, 2, 4, 8], "u8",
+             steps_max=3, check_fold=2)
+
+
+def test_default_widths_and_octave_limit(torch_cuda, ffa, oracle_mod):
+    from paper_1703_05581_amd import synth
+
+    x = synth.random_series(3, 100000, "u8")
+    run_case(torch_cuda, ffa, oracle_mod, x, 100000, 1e-3, 0.1, 1.6, 100, None, "u8",
+             steps_max=30, max_octaves=3)
+
+
+def test_mad_zero(torch_cuda, ffa, oracle_mod):
+    """A constant series folds to constant profiles: MAD = 0 gives S/N 0, width 0."""
+    x = np.full(20000, 128, np.uint8)
+    plan, _ = run_case(torch_cuda, ffa, oracle_mod, x, 20000, 1e-3, 0.3, 0.6, 300, [1, 2, 4], "u8")
+    snr, wid = plan.search(torch_cuda.from_numpy(x).cuda())
+    assert float(snr.abs().max()) == 0.0 and int(wid.abs().max()) == 0
+
+
+def test_f32_large_offset(torch_cuda, ffa, oracle_mod):
+    """Float series with a large mean (128, sd 16): centring keeps float32 S/N
+    within tolerance."""
+    from paper_1703_05581_amd import synth
+
+    x = synth.random_series(17, 1 << 18, "f32", mean=128.0, sd=16.0)
+    run_case(torch_cuda, ffa, oracle_mod, x, 1 << 18, 1e-3, 0.256, 2.048, 256, W10, "f32",
+             steps_max=16, check_fold=2)
+
+
+# ----------------------------------------------------------------- workloads
+
+def test_workload1_full(torch_cuda, ffa, oracle_mod):
+    """65536 f32 samples, P0 = 500..999: every trial against the oracle."""
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload1()
+    pa = s.plan
+    _, summ = run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax,
+                       pa.bins_min, list(pa.widths), "f32", check_fold=3)
+    # the injected 733.3-sample pulsar is the best trial
+    op = oracle_mod.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
+    best_p = op.periods()[summ["best_trial"]] / pa.tsamp
+    assert abs(best_p - 733.3) < 0.1 and summ["best_snr"] > 10
+
+
+def test_workload2_sampled(torch_cuda, ffa, oracle_mod):
+    """2^20 uint8 samples, three octaves: sampled steps bit-exact."""
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload2()
+    pa = s.plan
+    run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
+             list(pa.widths), "u8", steps_max=24, check_fold=3)
+
+
+def test_workload3_sampled(torch_cuda, ffa, oracle_mod):
+    """2^23 float32 samples with red noise, 0.5-30 s: sampled steps, including
+    the three-pass ones."""
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload3()
+    pa = s.plan
+    run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
+             list(pa.widths), "f32", steps_max=10, check_fold=2)
+
+
+def test_deterministic(torch_cuda, ffa):
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload1()
+    plan = ffa.Plan.from_args(s.plan)
+    x = torch_cuda.from_numpy(s.data).cuda()
+    a = [t.clone() for t in plan.search(x)]
+    b = plan.search(x)
+    assert torch_cuda.equal(a[0], b[0]) and torch_cuda.equal(a[1], b[1])
+
+
+def test_best(torch_cuda, ffa):
+    g = np.random.default_rng(3)
+    for n in (1, 5, 1000, 300001):
+        v = g.standard_normal(n).astype(np.float32)
+        v[g.integers(0, n, size=3)] = 9.0  # ties: first wins
+        t = torch_cuda.from_numpy(v).cuda()
+        assert ffa.best(t) == int(np.argmax(v))
