@@ -17,6 +17,12 @@ LIB_PATH = os.path.join(HERE, "libffa.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1703_05581_amd.build`")
 
+# torch ships its own HIP runtime and loads it by file name.  Importing torch
+# first lets libffa.so's libamdhip64.so.7 dependency resolve to that same
+# runtime by soname, so the process holds one HIP runtime and torch's device
+# pointers and streams are valid in the library.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 FFA_OK = 0
