@@ -56,8 +56,9 @@ extern "C" ffa_status ffa_search(ffa_plan p, const void* d_series, float* d_snr,
   for (const Chunk& c : p->chunks) {
     for (int32_t pass = 0; pass < c.n_passes; ++pass) {
       s = check_hip(launch_pass(dt->tiles + c.tile_begin[pass], c.tile_end[pass] - c.tile_begin[pass],
-                                c.lds_bytes[pass], is_int, d_ws, d_snr, d_width, nullptr, 0,
-                                kModeScore, dt->widths, dt->sqrtw, st),
+                                c.lds_bytes[pass], c.max_P0, is_int, d_ws, d_snr, d_width, nullptr, 0,
+                                kModeScore, dt->widths, dt->sqrtw, p->select_iters,
+                                p->select_cand, st),
                     "FFA pass kernel");
       if (s != FFA_OK) return s;
     }
@@ -81,8 +82,9 @@ extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, v
   if (s != FFA_OK) return s;
   for (int32_t pass = 0; pass < sp.n_passes; ++pass) {
     s = check_hip(launch_pass(dt->tiles + sp.tile_begin[pass], sp.tile_end[pass] - sp.tile_begin[pass],
-                              sp.lds_bytes[pass], is_int, d_ws, nullptr, nullptr, d_profiles,
-                              sp.first_trial, kModeProfiles, dt->widths, dt->sqrtw, st),
+                              sp.lds_bytes[pass], sp.P0, is_int, d_ws, nullptr, nullptr, d_profiles,
+                              sp.first_trial, kModeProfiles, dt->widths, dt->sqrtw,
+                              p->select_iters, p->select_cand, st),
                   "FFA pass kernel");
     if (s != FFA_OK) return s;
   }

@@ -21,6 +21,7 @@ constexpr int kMaxPasses = 8;
 constexpr int kThreads = 1024;         // threads per workgroup of the FFA kernels
 constexpr size_t kLdsBytes = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr size_t kWsAlign = 256;
+constexpr size_t kScratchBytes = (kThreads / 64) * 64 * 4;  // per-wave selection scratch
 
 // sigma = K * MAD (paper Sec. 2.2.1): K is 1 / (75% quantile of the unit normal).
 constexpr double kMadK = 1.482602218505602;
@@ -45,7 +46,8 @@ struct Tile {
   int32_t nw;        // number of widths of the step
   int32_t stride;    // LDS row stride in elements
   int32_t step;      // step index (diagnostics)
-  int32_t pad_[2];
+  int32_t halo;      // LDS bins after P0 that repeat bins 0..halo-1
+  int32_t pad_;
 };
 static_assert(sizeof(Tile) == 64, "tile layout");
 
@@ -67,6 +69,7 @@ struct Chunk {
   int32_t n_passes;  // max over its steps
   int64_t tile_begin[kMaxPasses], tile_end[kMaxPasses];
   int32_t lds_bytes[kMaxPasses];
+  int32_t max_P0;
 };
 
 // Device copies of a plan's tables (made on first use on a device).
@@ -95,6 +98,8 @@ struct ffa_plan_s {
   int64_t inter_off = 0;         // element offset of the intermediate region
   int64_t inter_elems = 0;
   size_t ws_bytes = 0;
+  int32_t select_iters = 64;     // counting rounds before the sort fallback
+  int32_t select_cand = 64;      // candidates handed to the exact in-lane select
   std::mutex dev_mu;
   std::deque<ffa::DeviceTables> dev;  // one entry per device used (stable addresses)
 };
@@ -115,11 +120,11 @@ hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws,
                        int64_t out_off, int center, hipStream_t st);
 hipError_t launch_halve(void* ws, int is_int, int64_t in_off, int64_t n_out,
                         int64_t out_off, hipStream_t st);
-hipError_t launch_pass(const Tile* tiles, int64_t n_tiles, int lds_bytes,
+hipError_t launch_pass(const Tile* tiles, int64_t n_tiles, int lds_bytes, int max_P0,
                        int is_int, void* ws, float* snr, int32_t* width,
                        void* profiles, int64_t trial_base, int mode,
                        const int32_t* wtab, const double* sqrtw,
-                       hipStream_t st);
+                       int select_iters, int select_cand, hipStream_t st);
 hipError_t launch_best(const float* snr, int64_t n, int64_t* best,
                        hipStream_t st);
 

@@ -23,31 +23,114 @@ __device__ __forceinline__ int bitrev(int t, int d) {
   return d == 0 ? 0 : (int)(__brev((unsigned)t) >> (32 - d));
 }
 
-// Wavefront-scope ordering of this wave's LDS writes before its later reads
-// by other lanes.
+// Orders this wave's earlier LDS writes before its later LDS reads.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
 }
 
+// ------------------------------------------------------- wave primitives
+
+// DPP lane patterns of GFX9 (data-parallel primitives on VALU operands).
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppRowMirror = 0x140;  // lane i <- 15-i within a row of 16
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7-i within 8
+constexpr int kDppBcast15 = 0x142;    // lane 15 of each row -> next row
+constexpr int kDppBcast31 = 0x143;    // lane 31 -> rows 2 and 3
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Maximum / minimum of one value per lane; the result is wave-uniform.
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+  v = umax(v, dpp<kDppXor1>(0u, v));
+  v = umax(v, dpp<kDppXor2>(0u, v));
+  v = umax(v, dpp<kDppHalfMirror>(0u, v));
+  v = umax(v, dpp<kDppRowMirror>(0u, v));
+  v = umax(v, dpp<kDppBcast15, 0xA>(0u, v));
+  v = umax(v, dpp<kDppBcast31, 0xC>(0u, v));
+  return readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_umin(uint32_t v) {
+  v = umin(v, dpp<kDppXor1>(~0u, v));
+  v = umin(v, dpp<kDppXor2>(~0u, v));
+  v = umin(v, dpp<kDppHalfMirror>(~0u, v));
+  v = umin(v, dpp<kDppRowMirror>(~0u, v));
+  v = umin(v, dpp<kDppBcast15, 0xA>(~0u, v));
+  v = umin(v, dpp<kDppBcast31, 0xC>(~0u, v));
+  return readlane(v, 63);
+}
+
+// Inclusive prefix sum over the 64 lanes (modular for integers).
+__device__ __forceinline__ uint32_t wave_scan(uint32_t v) {
+  v += dpp<kDppShr1>(0u, v);
+  v += dpp<kDppShr2>(0u, v);
+  v += dpp<kDppShr4>(0u, v);
+  v += dpp<kDppShr8>(0u, v);
+  v += dpp<kDppBcast15, 0xA>(0u, v);
+  v += dpp<kDppBcast31, 0xC>(0u, v);
+  return v;
+}
+
+__device__ __forceinline__ float wave_scan(float v) {
+  auto step = [](float x, uint32_t sh) { return x + __uint_as_float(sh); };
+  v = step(v, dpp<kDppShr1>(0u, __float_as_uint(v)));
+  v = step(v, dpp<kDppShr2>(0u, __float_as_uint(v)));
+  v = step(v, dpp<kDppShr4>(0u, __float_as_uint(v)));
+  v = step(v, dpp<kDppShr8>(0u, __float_as_uint(v)));
+  v = step(v, dpp<kDppBcast15, 0xA>(0u, __float_as_uint(v)));
+  v = step(v, dpp<kDppBcast31, 0xC>(0u, __float_as_uint(v)));
+  return v;
+}
+
+__device__ __forceinline__ int wave_count(bool p) { return __popcll(__ballot(p)); }
+
+// Order-preserving 32-bit keys: integer sums (non-negative, < 2^31) are their
+// own keys; a finite float maps to an unsigned integer with the same order.
+__device__ __forceinline__ uint32_t fkey(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return b ^ ((b >> 31) ? 0xffffffffu : 0x80000000u);
+}
+__device__ __forceinline__ float fval(uint32_t k) {
+  return __uint_as_float(k ^ ((k >> 31) ? 0x80000000u : 0xffffffffu));
+}
+
+constexpr uint32_t kPadKey = 0xffffffffu;  // above every real key
+
 // --------------------------------------------------------------- butterfly
 
-// All `d` levels of the FFA tree on 2^d rows held in LDS (row stride S).
+// All `d` levels of the FFA tree on 2^d rows held in LDS.  Row r occupies
+// lds[r*S .. r*S + P0 + H): bins 0..P0-1, then H bins of halo.
 //
 // Level l merges the two halves A, B of each block of 2^l rows:
 //   out_{2v}[j]   = A_v[j] + B_v[(j + v)     mod P0]
 //   out_{2v+1}[j] = A_v[j] + B_v[(j + v + 1) mod P0]
 // (paper Sec. 2.1, after Staelin 1969).  The pair is written over the slots
 // of A_v and B_v, so partial t of a block ends at the bit reversal of t.
-// One wave owns a pair of rows per level, so a level needs no barrier inside;
-// every read of a B row precedes its writes because the shifted reads wrap.
+// One wave owns a pair of rows per level.  It first copies bins 0..H-1 of B
+// into B's halo, so the shifted reads B[j + s], j + s < P0 + H, never wrap;
+// then it walks the bins in chunks of 64.  Chunk c reads B at
+// [64c + s, 64c + 64 + s] and writes B at [64c, 64c + 63], so no write lands
+// where a later chunk reads, and the halo keeps the old bins.  No barrier is
+// needed inside a level.
 template <typename T>
-__device__ void butterfly(T* lds, int S, int P0, int d) {
+__device__ __forceinline__ void butterfly(T* lds, int S, int P0, int H, int d) {
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   const int nwaves = blockDim.x / kWave;
   const int R = 1 << d;
-  constexpr int kMaxE = 32;  // P0 <= 2048
   for (int l = 1; l <= d; ++l) {
     const int half = 1 << (l - 1);
     for (int p = wave; p < (R >> 1); p += nwaves) {
@@ -55,28 +138,22 @@ __device__ void butterfly(T* lds, int S, int P0, int d) {
       const int v = p & (half - 1);
       T* A = lds + (size_t)(beta * 2 * half + bitrev(v, l - 1)) * S;
       T* B = A + (size_t)half * S;
-      const int s0 = v % P0;
-      const int s1 = (v + 1) % P0;
-      T keep[kMaxE];
-#pragma unroll
-      for (int c = 0; c < kMaxE; ++c) {
-        const int j = lane + c * kWave;
-        if (c * kWave < P0 && j < P0) {
-          int i0 = j + s0;
-          i0 -= (i0 >= P0) ? P0 : 0;
-          int i1 = j + s1;
-          i1 -= (i1 >= P0) ? P0 : 0;
+      const int sh = v % P0;
+      const int hn = sh + 1 < H ? sh + 1 : H;  // halo bins this pair reads
+      for (int i = lane; i < hn; i += kWave) B[P0 + i] = B[i];
+      const T* B0 = B + sh;
+      // The chunk count is wave-uniform so that all lanes work on the same
+      // chunk together: the in-place writes rely on it.
+      const int nchunk = (P0 + kWave - 1) / kWave;
+      for (int c = 0; c < nchunk; ++c) {
+        const int j = c * kWave + lane;
+        if (j < P0) {
           const T a = A[j];
-          const T b0 = B[i0];
-          const T b1 = B[i1];
-          A[j] = a + b0;  // only this lane reads A[j]
-          keep[c] = a + b1;
+          const T b0 = B0[j];
+          const T b1 = B0[j + 1];
+          A[j] = a + b0;
+          B[j] = a + b1;
         }
-      }
-#pragma unroll
-      for (int c = 0; c < kMaxE; ++c) {
-        const int j = lane + c * kWave;
-        if (c * kWave < P0 && j < P0) B[j] = keep[c];
       }
     }
     __syncthreads();
@@ -85,88 +162,136 @@ __device__ void butterfly(T* lds, int S, int P0, int d) {
 
 // ------------------------------------------------------------- selection
 
-template <typename K>
-struct Pad;
-template <>
-struct Pad<float> {
-  __device__ static float v() { return INFINITY; }
-};
-template <>
-struct Pad<uint32_t> {
-  __device__ static uint32_t v() { return 0xffffffffu; }
-};
+template <int E>
+__device__ __forceinline__ int count_lt(const uint32_t (&key)[E], uint32_t T) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) c += wave_count(key[r] < T);
+  return c;
+}
 
-// Ascending bitonic sort of 64*E keys held blocked across the wave
-// (element e = lane*E + r lives in register r of lane e/E).
-template <int E, typename K>
-__device__ __forceinline__ void wave_sort(K (&x)[E]) {
+// t-th smallest (0-based) of the `cnt` keys held one per lane in lanes
+// 0..cnt-1: quickselect with the first remaining lane as pivot.  Each round
+// removes at least the pivot, so it ends within cnt rounds.
+__device__ __forceinline__ uint32_t lane_select(uint32_t c, int cnt, int t) {
   const int lane = lane_id();
-  constexpr int n = kWave * E;
-#pragma unroll
-  for (int k = 2; k <= n; k <<= 1) {
-#pragma unroll
-    for (int s = k >> 1; s > 0; s >>= 1) {
-      if (s < E) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          if ((r & s) == 0) {
-            const bool asc = ((lane * E + r) & k) == 0;
-            const K a = x[r], b = x[r | s];
-            const K lo = a < b ? a : b;
-            const K hi = a < b ? b : a;
-            x[r] = asc ? lo : hi;
-            x[r | s] = asc ? hi : lo;
-          }
-        }
-      } else {
-        const int m = s / E;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const int e = lane * E + r;
-          const K p = __shfl_xor(x[r], m, kWave);
-          const bool lower = (e & s) == 0;
-          const bool asc = (e & k) == 0;
-          const K lo = x[r] < p ? x[r] : p;
-          const K hi = x[r] < p ? p : x[r];
-          x[r] = (lower == asc) ? lo : hi;
-        }
-      }
+  uint64_t active = __ballot(lane < cnt);
+  for (int it = 0; it < kWave; ++it) {
+    const int src = __ffsll((unsigned long long)active) - 1;
+    const uint32_t p = readlane(c, src);
+    const uint64_t lt = active & __ballot(c < p);
+    const uint64_t eq = active & __ballot(c == p);
+    const int nlt = __popcll(lt), neq = __popcll(eq);
+    if (t < nlt) {
+      active = lt;
+    } else if (t < nlt + neq) {
+      return p;
+    } else {
+      t -= nlt + neq;
+      active &= ~(lt | eq);
     }
   }
+  return c;  // not reached: the loop ends by returning
 }
 
-// Element `idx` of a blocked wave array.
-template <int E, typename K>
-__device__ __forceinline__ K wave_get(const K (&x)[E], int idx) {
-  const int r = idx % E;
-  K v = x[0];
-#pragma unroll
-  for (int i = 1; i < E; ++i)
-    if (i == r) v = x[i];
-  return __shfl(v, idx / E, kWave);
-}
+struct SelectKnobs {
+  int max_iters;  // counting rounds before the full-sort fallback
+  int max_cand;   // candidates small enough for lane_select (<= 64)
+};
 
-template <typename K>
-__device__ __forceinline__ K wave_max(K v) {
-#pragma unroll
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    const K o = __shfl_xor(v, m, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
-// Exclusive prefix over the wave of one value per lane.
-template <typename K>
-__device__ __forceinline__ K wave_exclusive_scan(K v) {
+// Exact order statistics v1 = key_(k1) and v2 = key_(k2), k2 in {k1, k1+1},
+// of the n real keys in key[E] (pads are kPadKey), given kmin/kmax of the
+// real keys.  A bracket [lo, hi) holding both targets is narrowed by counting
+// keys below a pivot (one ballot per register); pivots interpolate the ranks
+// inside the bracket, falling back to halving it when a round gains little.
+// Once at most max_cand keys remain in the bracket they are compacted into
+// the wave's LDS scratch and selected exactly.  FKEY: keys encode floats, so
+// interpolation happens on the float values.  Every exit is exact.
+template <int E, bool FKEY>
+__device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int k1, int k2, uint32_t kmin,
+                            uint32_t kmax, uint32_t* scratch, SelectKnobs kn,
+                            uint32_t& v1, uint32_t& v2) {
   const int lane = lane_id();
-  K inc = v;
+  uint32_t lo = kmin, hi = kmax + 1u;  // kmax < kPadKey
+  int c_lo = 0, c_hi = n;              // keys below lo / below hi
+  bool halve = false;
+  int side = 0;         // +1: hi moved last round, -1: lo moved
+  float wlo = 1.0f, whi = 1.0f;  // Illinois weights of the bracket ends
+  // Rounds past max_iters only halve the key range, which ends the loop
+  // within 33 more rounds (the range is at most 2^32).
+  for (int it = 0; it < kn.max_iters + 34; ++it) {
+    if (it >= kn.max_iters) halve = true;
+    if (hi - lo <= 1u) {  // only the value lo lies in the bracket
+      v1 = v2 = lo;
+      return;
+    }
+    const int cand = c_hi - c_lo;
+    if (cand <= kn.max_cand) {
+      int base = 0;
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const K u = __shfl_up(inc, o, kWave);
-    if (lane >= o) inc = inc + u;
+      for (int r = 0; r < E; ++r) {
+        const bool in = key[r] >= lo && key[r] < hi;
+        const uint64_t m = __ballot(in);
+        const int pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (in) scratch[pos] = key[r];
+        base += __popcll(m);
+      }
+      wave_lds_sync();
+      const uint32_t c = lane < cand ? scratch[lane] : kPadKey;
+      wave_lds_sync();
+      const int t1 = k1 - c_lo;
+      v1 = lane_select(c, cand, t1);
+      if (k2 == k1) {
+        v2 = v1;
+      } else {
+        const int le = wave_count(lane < cand && c <= v1);
+        v2 = le > t1 + 1 ? v1 : wave_umin(lane < cand && c > v1 ? c : kPadKey);
+      }
+      return;
+    }
+    // pivot T in (lo, hi): regula falsi on rank (target k1 + 1), with the
+    // end that stayed put twice in a row down-weighted (Illinois rule)
+    const float flo = wlo * ((float)(k1 - c_lo) + 1.0f);
+    const float fhi = whi * ((float)(c_hi - k1) - 1.0f);
+    const float frac = halve ? 0.5f : (flo + fhi > 0.0f ? __fdividef(flo, flo + fhi) : 0.5f);
+    uint32_t T;
+    if (FKEY && it < kn.max_iters) {  // float keys: interpolate / halve the values
+      const float a = fval(lo), b = fval(hi - 1u);
+      T = fkey(fmaf(frac, b - a, a));
+    } else {
+      T = lo + (uint32_t)(frac * (float)(hi - lo));
+    }
+    T = T <= lo ? lo + 1u : (T >= hi ? hi - 1u : T);
+    const int c = count_lt(key, T);
+    const int before = cand;
+    if (c <= k1) {
+      lo = T;
+      c_lo = c;
+      whi = side < 0 ? whi * 0.5f : 1.0f;
+      wlo = 1.0f;
+      side = -1;
+    } else if (c > k2) {
+      hi = T;
+      c_hi = c;
+      wlo = side > 0 ? wlo * 0.5f : 1.0f;
+      whi = 1.0f;
+      side = 1;
+    } else {  // k1 < c <= k2: the two targets straddle T
+      uint32_t mx = 0u, mn = kPadKey;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        if (key[r] < T) mx = umax(mx, key[r]);
+        else mn = umin(mn, key[r]);
+      }
+      v1 = wave_umax(mx);
+      v2 = wave_umin(mn);
+      return;
+    }
+    halve = (c_hi - c_lo) * 4 > before * 3;
   }
-  return inc - v;
+  v1 = lo;  // not reached: the halving rounds end the loop by returning
+  v2 = lo;
 }
 
 // ----------------------------------------------------------- Algorithm 1
@@ -176,72 +301,84 @@ struct Types;
 template <>
 struct Types<true> {
   using T = int32_t;   // stored sums (non-negative, < 2^31)
-  using K = uint32_t;  // key / modular prefix type
+  using A = uint32_t;  // modular prefix-sum type
 };
 template <>
 struct Types<false> {
   using T = float;
-  using K = float;
+  using A = float;
 };
 
 // Score one folded profile with Algorithm 1 (paper Sec. 2.2.1): median and
 // MAD of the profile (Eqs. 3-4), circular boxcars of every width, score =
-// max_w (max_j box_w[j] - w*median) / (K*MAD*sqrt(w)).  The whole wave works
-// on one profile held in LDS row `row` (stride >= P0 + wmax + 1); the row is
-// overwritten with the circular prefix sums.
+// max_w (max_j box_w[j] - w*median) / (K*MAD*sqrt(w)).  The wave works on one
+// profile held in LDS `row` (room for P0 + wmax + 1 entries); the row is
+// overwritten with circular prefix sums.  Bin j of the profile sits in
+// register j/64 of lane j%64.
 //
 // Integer profiles are scored exactly: med2 = 2*median, mad4 = 4*MAD, and
-// S/N = 2*(2*peak - w*med2) / ((K*mad4)*sqrt(w)) in double, with sqrt(w)
-// from a host table, so every rounding is a correctly rounded IEEE operation.
+// S/N = 2*(2*peak - w*med2) / ((K*mad4)*sqrt(w)) in double with sqrt(w) from
+// a host table, so every rounding is a correctly rounded IEEE operation.
 template <int E, bool INT>
-__device__ void score_profile(typename Types<INT>::T* row, int P0, int wmax,
-                              const int32_t* widths, const double* sqrtw,
-                              int nw, float* snr_out, int32_t* width_out) {
+__device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
+                              const int32_t* widths, const double* sqrtw, int nw, SelectKnobs kn,
+                              float* snr_out, int32_t* width_out) {
   using T = typename Types<INT>::T;
-  using K = typename Types<INT>::K;
+  using A = typename Types<INT>::A;
   const int lane = lane_id();
-  const int a = (P0 - 1) / 2;
-  const int b = P0 / 2;
+  const int k1 = (P0 - 1) / 2;
+  const int k2 = P0 / 2;
 
-  K x[E];
+  uint32_t key[E];
+  uint32_t kmin = kPadKey, kmax = 0u;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int e = lane * E + r;
-    x[r] = e < P0 ? (K)row[e] : Pad<K>::v();
+    const int e = r * kWave + lane;
+    const bool real = e < P0;
+    if constexpr (INT) key[r] = real ? (uint32_t)row[e] : kPadKey;
+    else key[r] = real ? fkey(row[e]) : kPadKey;
+    kmin = umin(kmin, key[r]);
+    kmax = umax(kmax, real ? key[r] : 0u);
   }
-  wave_sort<E>(x);
-  const K xa = wave_get<E>(x, a);
-  const K xb = wave_get<E>(x, b);
+  kmin = wave_umin(kmin);
+  kmax = wave_umax(kmax);
 
-  // deviations from the median
-  int64_t med2 = 0;
+  // median (even P0: mean of the two middle order statistics)
+  uint32_t m1, m2;
+  select_pair<E, !INT>(key, P0, k1, k2, kmin, kmax, scratch, kn, m1, m2);
+  uint64_t med2 = 0;
   float med = 0.f;
+  uint32_t dmax;
   if constexpr (INT) {
-    med2 = (int64_t)xa + (int64_t)xb;
+    med2 = (uint64_t)m1 + (uint64_t)m2;
+    const uint64_t up = 2 * (uint64_t)kmax - med2, dn = med2 - 2 * (uint64_t)kmin;
+    dmax = (uint32_t)(up > dn ? up : dn);
   } else {
-    med = (float)(0.5 * ((double)xa + (double)xb));
+    med = (float)(0.5 * ((double)fval(m1) + (double)fval(m2)));
+    dmax = fkey(fmaxf(fabsf(fval(kmax) - med), fabsf(fval(kmin) - med)));
   }
+  // MAD: the same selection on |x - median| (doubled for integers)
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int e = lane * E + r;
+    const bool real = r * kWave + lane < P0;
     if constexpr (INT) {
-      const int64_t dv = 2 * (int64_t)x[r] - med2;
-      x[r] = e < P0 ? (K)(dv < 0 ? -dv : dv) : Pad<K>::v();
+      const int64_t dv = 2 * (int64_t)key[r] - (int64_t)med2;
+      key[r] = real ? (uint32_t)(dv < 0 ? -dv : dv) : kPadKey;
     } else {
-      x[r] = e < P0 ? fabsf(x[r] - med) : Pad<K>::v();
+      key[r] = real ? fkey(fabsf(fval(key[r]) - med)) : kPadKey;
     }
   }
-  wave_sort<E>(x);
-  const K da = wave_get<E>(x, a);
-  const K db = wave_get<E>(x, b);
-  bool mad_zero;
+  const uint32_t dmin = INT ? 0u : fkey(0.f);
+  uint32_t d1, d2;
+  select_pair<E, !INT>(key, P0, k1, k2, dmin, dmax, scratch, kn, d1, d2);
   uint64_t mad4 = 0;
   float mad = 0.f;
+  bool mad_zero;
   if constexpr (INT) {
-    mad4 = (uint64_t)da + (uint64_t)db;
+    mad4 = (uint64_t)d1 + (uint64_t)d2;
     mad_zero = mad4 == 0;
   } else {
-    mad = (float)(0.5 * ((double)da + (double)db));
+    mad = (float)(0.5 * ((double)fval(d1) + (double)fval(d2)));
     mad_zero = mad == 0.f;
   }
   if (mad_zero) {
@@ -253,64 +390,62 @@ __device__ void score_profile(typename Types<INT>::T* row, int P0, int wmax,
   }
 
   // circular prefix sums C[k] = sum_{i<k} F[i mod P0], k <= P0 + wmax
-  K y[E];
-  K run = 0;
+  A xv[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int e = lane * E + r;
-    const K v = e < P0 ? (K)row[e] : (K)0;
-    run = run + v;
-    y[r] = run;
+    const int e = r * kWave + lane;
+    xv[r] = e < P0 ? (A)row[e] : (A)0;
   }
-  const K base = wave_exclusive_scan(run);
   wave_lds_sync();
+  A carry = (A)0;
+  A cex[E];  // C[j] (exclusive prefix) of this lane's bins
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int e = lane * E + r;
-    if (e < P0) row[e + 1] = (T)(base + y[r]);
+    const int e = r * kWave + lane;
+    const A s = wave_scan(xv[r]);
+    cex[r] = carry + s - xv[r];
+    if (e < P0) row[e + 1] = (T)(carry + s);
+    if constexpr (INT) carry += readlane(s, 63);
+    else carry += __uint_as_float(readlane(__float_as_uint(s), 63));
   }
   if (lane == 0) row[0] = (T)0;
   wave_lds_sync();
-  const K total = (K)row[P0];
-  for (int i = lane; i < wmax; i += kWave) row[P0 + 1 + i] = (T)(total + (K)row[1 + i]);
+  const A total = carry;
+  for (int i = lane; i < wmax; i += kWave) row[P0 + 1 + i] = (T)(total + (A)row[1 + i]);
   wave_lds_sync();
 
-  K mx[kMaxWidths];
-#pragma unroll
-  for (int i = 0; i < kMaxWidths; ++i) {
-    if constexpr (INT) mx[i] = 0u;
-    else mx[i] = -INFINITY;
-  }
-  for (int j = lane; j < P0; j += kWave) {
-    const K c0 = (K)row[j];
-#pragma unroll
-    for (int i = 0; i < kMaxWidths; ++i) {
-      if (i < nw) {
-        const K v = (K)row[j + widths[i]] - c0;
-        mx[i] = v > mx[i] ? v : mx[i];
-      }
-    }
-  }
+  // each width: largest boxcar sum, then its score; first width wins ties
   double best = 0.0;
   int32_t bw = 0;
 #pragma unroll
   for (int i = 0; i < kMaxWidths; ++i) {
-    if (i < nw) {
-      const K peak = wave_max(mx[i]);
-      const int32_t w = widths[i];
-      double s;
-      if constexpr (INT) {
-        const int64_t num = 2 * (2 * (int64_t)peak - (int64_t)w * med2);
-        const double den = (kMadK * (double)mad4) * sqrtw[i];
-        s = (double)num / den;
-      } else {
-        s = ((double)peak - (double)w * (double)med) /
-            ((kMadK * (double)mad) * sqrtw[i]);
+    if (i >= nw) break;
+    const int32_t w = widths[i];
+    A mx;  // box sums are >= 0 for integers
+    if constexpr (INT) mx = 0u;
+    else mx = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int j = r * kWave + lane;
+      if (j < P0) {
+        const A box = (A)row[j + w] - cex[r];
+        mx = box > mx ? box : mx;
       }
-      if (bw == 0 || s > best) {
-        best = s;
-        bw = w;
-      }
+    }
+    uint32_t pk;
+    if constexpr (INT) pk = wave_umax(mx);
+    else pk = wave_umax(fkey(mx));
+    double sc;
+    if constexpr (INT) {
+      const int64_t num = 2 * (2 * (int64_t)pk - (int64_t)w * (int64_t)med2);
+      const double den = (kMadK * (double)mad4) * sqrtw[i];
+      sc = (double)num / den;
+    } else {
+      sc = ((double)fval(pk) - (double)w * (double)med) / ((kMadK * (double)mad) * sqrtw[i]);
+    }
+    if (bw == 0 || sc > best) {
+      best = sc;
+      bw = w;
     }
   }
   if (lane == 0) {
@@ -319,32 +454,40 @@ __device__ void score_profile(typename Types<INT>::T* row, int P0, int wmax,
   }
 }
 
-template <bool INT>
-__device__ void score_dispatch(typename Types<INT>::T* row, int P0, int wmax,
-                               const int32_t* widths, const double* sqrtw,
-                               int nw, float* snr_out, int32_t* width_out) {
-  if (P0 <= 64)
-    score_profile<1, INT>(row, P0, wmax, widths, sqrtw, nw, snr_out, width_out);
-  else if (P0 <= 128)
-    score_profile<2, INT>(row, P0, wmax, widths, sqrtw, nw, snr_out, width_out);
-  else if (P0 <= 256)
-    score_profile<4, INT>(row, P0, wmax, widths, sqrtw, nw, snr_out, width_out);
-  else if (P0 <= 512)
-    score_profile<8, INT>(row, P0, wmax, widths, sqrtw, nw, snr_out, width_out);
-  else if (P0 <= 1024)
-    score_profile<16, INT>(row, P0, wmax, widths, sqrtw, nw, snr_out, width_out);
-  else
-    score_profile<32, INT>(row, P0, wmax, widths, sqrtw, nw, snr_out, width_out);
+// EMAX bounds the registers per lane the kernel is compiled for; profiles of
+// P0 <= 64*EMAX are scored (the launcher picks EMAX from the largest P0).
+template <bool INT, int EMAX>
+__device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
+                               const int32_t* widths, const double* sqrtw, int nw, SelectKnobs kn,
+                               float* snr_out, int32_t* width_out) {
+#define FFA_SCORE(EE) \
+  score_profile<EE, INT>(row, scratch, P0, wmax, widths, sqrtw, nw, kn, snr_out, width_out)
+  if (P0 <= 64) FFA_SCORE(1);
+  else if (P0 <= 128) FFA_SCORE(2);
+  else if (P0 <= 192) FFA_SCORE(3);
+  else if (P0 <= 256) FFA_SCORE(4);
+  else if (P0 <= 320) FFA_SCORE(5);
+  else if (P0 <= 384) FFA_SCORE(6);
+  else if (P0 <= 448) FFA_SCORE(7);
+  else if (P0 <= 512) FFA_SCORE(8);
+  else if constexpr (EMAX >= 16) {
+    if (P0 <= 768) FFA_SCORE(12);
+    else if (P0 <= 1024) FFA_SCORE(16);
+    else if constexpr (EMAX >= 32) {
+      if (P0 <= 1536) FFA_SCORE(24);
+      else FFA_SCORE(32);
+    }
+  }
+#undef FFA_SCORE
 }
 
 // ------------------------------------------------------------ pass kernel
 
-template <bool INT>
+template <bool INT, int EMAX>
 __global__ __launch_bounds__(kThreads) void ffa_pass_kernel(
-    const Tile* __restrict__ tiles, void* __restrict__ ws_raw,
-    float* __restrict__ snr, int32_t* __restrict__ width,
-    void* __restrict__ profiles, int64_t trial_base, int mode,
-    const int32_t* __restrict__ wtab, const double* __restrict__ sqrtw) {
+    const Tile* __restrict__ tiles, void* __restrict__ ws_raw, float* __restrict__ snr,
+    int32_t* __restrict__ width, void* __restrict__ profiles, int64_t trial_base, int mode,
+    const int32_t* __restrict__ wtab, const double* __restrict__ sqrtw, SelectKnobs kn) {
   using T = typename Types<INT>::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -355,24 +498,46 @@ __global__ __launch_bounds__(kThreads) void ffa_pass_kernel(
   const int d = tl.depth;
   const int R = 1 << d;
   const int S = tl.stride;
+  const int H = tl.halo;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   const int nwaves = blockDim.x / kWave;
 
-  // stage the group's rows (rows >= valid are zero padding, paper Sec. 2.1)
-  const T* src = ws + tl.src;
-  for (int r = wave; r < R; r += nwaves) {
-    T* row = lds + (size_t)r * S;
-    if (r < tl.valid) {
-      const T* g = src + (int64_t)r * P0;
-      for (int j = lane; j < P0; j += kWave) row[j] = g[j];
-    } else {
-      for (int j = lane; j < P0; j += kWave) row[j] = (T)0;
+  // stage the group's rows (rows >= valid are zero padding, paper Sec. 2.1).
+  // Element e of the staged block is row e / P0, bin e % P0; loads are issued
+  // in batches so many are in flight.
+  {
+    const T* src = ws + tl.src;
+    const uint32_t W = (uint32_t)P0;
+    const uint32_t total = (uint32_t)R * W;
+    const uint32_t real = (uint32_t)tl.valid * W;
+    const uint32_t magic = 0xffffffffu / W;  // floor(2^32 / W): exact after one correction
+    constexpr int kBatch = 8;
+    for (uint32_t base = threadIdx.x; base < total; base += kBatch * kThreads) {
+      T v[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const uint32_t e = base + (uint32_t)b * kThreads;
+        v[b] = e < real ? src[e] : (T)0;
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const uint32_t e = base + (uint32_t)b * kThreads;
+        if (e < total) {
+          uint32_t row = __umulhi(e, magic);
+          uint32_t col = e - row * W;
+          if (col >= W) {
+            ++row;
+            col -= W;
+          }
+          lds[row * (uint32_t)S + col] = v[b];
+        }
+      }
     }
   }
   __syncthreads();
 
-  butterfly<T>(lds, S, P0, d);
+  butterfly<T>(lds, S, P0, H, d);
 
   if (!tl.final_) {
     // Hand partial t to the next pass rotated left by t*h bins: the levels
@@ -398,6 +563,7 @@ __global__ __launch_bounds__(kThreads) void ffa_pass_kernel(
     }
     return;
   }
+  uint32_t* scratch = reinterpret_cast<uint32_t*>(lds + (size_t)R * S) + wave * kWave;
   const int32_t* widths = wtab + tl.wofs;
   const double* sw = sqrtw + tl.wofs;
   int wmax = 0;
@@ -405,8 +571,8 @@ __global__ __launch_bounds__(kThreads) void ffa_pass_kernel(
   for (int t = wave; t < R; t += nwaves) {
     T* row = lds + (size_t)bitrev(t, d) * S;
     const int64_t trial = tl.dst + t;
-    score_dispatch<INT>(row, P0, wmax, widths, sw, tl.nw, snr + trial,
-                        width + trial);
+    score_dispatch<INT, EMAX>(row, scratch, P0, wmax, widths, sw, tl.nw, kn, snr + trial,
+                              width + trial);
   }
 }
 
@@ -552,30 +718,39 @@ hipError_t launch_halve(void* ws, int is_int, int64_t in_off,
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const Tile* tiles, int64_t n_tiles, int lds_bytes,
+template <bool INT, int EMAX>
+hipError_t launch_pass_t(const Tile* tiles, int64_t n_tiles, int lds_bytes, void* ws, float* snr,
+                         int32_t* width, void* profiles, int64_t trial_base, int mode,
+                         const int32_t* wtab, const double* sqrtw, SelectKnobs kn, hipStream_t st) {
+  static const hipError_t attr =
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&ffa_pass_kernel<INT, EMAX>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+  if (attr != hipSuccess) return attr;
+  ffa_pass_kernel<INT, EMAX><<<(unsigned)n_tiles, kThreads, lds_bytes, st>>>(
+      tiles, ws, snr, width, profiles, trial_base, mode, wtab, sqrtw, kn);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(const Tile* tiles, int64_t n_tiles, int lds_bytes, int max_P0,
                        int is_int, void* ws, float* snr, int32_t* width,
                        void* profiles, int64_t trial_base, int mode,
                        const int32_t* wtab, const double* sqrtw,
-                       hipStream_t st) {
+                       int select_iters, int select_cand, hipStream_t st) {
+  const SelectKnobs kn{select_iters, select_cand < 1 ? 1 : (select_cand > kWave ? kWave : select_cand)};
   if (n_tiles <= 0) return hipSuccess;
-  if ((size_t)lds_bytes > kLdsBytes) return hipErrorInvalidValue;
-  static hipError_t attr = [] {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ffa_pass_kernel<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ffa_pass_kernel<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-    return e;
-  }();
-  if (attr != hipSuccess) return attr;
+  if ((size_t)lds_bytes > kLdsBytes || max_P0 > 2 * kMaxBinsMin) return hipErrorInvalidValue;
+#define FFA_LAUNCH(I, EM) \
+  launch_pass_t<I, EM>(tiles, n_tiles, lds_bytes, ws, snr, width, profiles, trial_base, mode, wtab, \
+                       sqrtw, kn, st)
   if (is_int) {
-    ffa_pass_kernel<true><<<(unsigned)n_tiles, kThreads, lds_bytes, st>>>(
-        tiles, ws, snr, width, profiles, trial_base, mode, wtab, sqrtw);
-  } else {
-    ffa_pass_kernel<false><<<(unsigned)n_tiles, kThreads, lds_bytes, st>>>(
-        tiles, ws, snr, width, profiles, trial_base, mode, wtab, sqrtw);
+    if (max_P0 <= 512) return FFA_LAUNCH(true, 8);
+    if (max_P0 <= 1024) return FFA_LAUNCH(true, 16);
+    return FFA_LAUNCH(true, 32);
   }
-  return hipGetLastError();
+  if (max_P0 <= 512) return FFA_LAUNCH(false, 8);
+  if (max_P0 <= 1024) return FFA_LAUNCH(false, 16);
+  return FFA_LAUNCH(false, 32);
+#undef FFA_LAUNCH
 }
 
 hipError_t launch_best(const float* snr, int64_t n, int64_t* best,

@@ -50,11 +50,26 @@ void step_widths(const std::vector<int32_t>& user, int32_t P0,
 // Pass split of an L-level step: as few passes as the LDS allows.  The last
 // pass keeps its rows with room for the boxcar prefix sums (stride
 // P0 + wmax + 1); earlier passes use stride P0.
+// LDS row stride of a pass of depth d: P0 bins plus a halo of
+// min(2^(d-1), P0) bins for the shifted butterfly reads; the last pass also
+// needs P0 + wmax + 1 entries for the boxcar prefix sums.
+int32_t halo_of(int32_t P0, int32_t d) { return std::min<int32_t>(int32_t(1) << (d - 1), P0); }
+constexpr int32_t kMaxHalo = 1 << 30;  // no limit on the halo
+int32_t stride_of(const Step& s, int32_t d, bool last) {
+  const int32_t h = halo_of(s.P0, d);
+  return s.P0 + std::max<int32_t>(h, last ? s.wmax + 1 : 0);
+}
+int64_t lds_of(const Step& s, int32_t d, bool last) {
+  return (int64_t(1) << d) * stride_of(s, d, last) * 4 + (last ? (int64_t)kScratchBytes : 0);
+}
+
 void split_passes(Step* s) {
-  const int64_t fin_rows = (int64_t)kLdsBytes / (4 * (int64_t)(s->P0 + s->wmax + 1));
-  const int64_t mid_rows = (int64_t)kLdsBytes / (4 * (int64_t)s->P0);
-  const int32_t dfin = ilog2(fin_rows);
-  const int32_t dmid = ilog2(mid_rows);
+  int32_t dfin = 1, dmid = 1;
+  auto fits = [&](int32_t d, bool last) {
+    return lds_of(*s, d, last) <= (int64_t)kLdsBytes && (halo_of(s->P0, d) <= kMaxHalo || s->P0 <= kMaxHalo);
+  };
+  while (dfin < 24 && fits(dfin + 1, true)) ++dfin;
+  while (dmid < 24 && fits(dmid + 1, false)) ++dmid;
   if (s->L <= dfin) {
     s->n_passes = 1;
     s->depth[0] = s->L;
@@ -95,8 +110,10 @@ bool tiles_in_bounds(const ffa_plan_s* p) {
         const Tile& t = p->tiles[ti];
         const int64_t rows = int64_t(1) << dp;
         if (t.P0 != s.P0 || t.depth != dp || t.valid < 1 || t.valid > rows) return false;
-        if (t.stride < s.P0 + (last ? s.wmax + 1 : 0)) return false;
-        if (rows * t.stride * 4 > (int64_t)kLdsBytes) return false;
+        if (t.halo < 1 || t.halo > s.P0 || t.halo < std::min<int64_t>(rows / 2, s.P0)) return false;
+        if (t.halo > kMaxHalo && s.P0 > kMaxHalo) return false;
+        if (t.stride < s.P0 + t.halo || t.stride < s.P0 + (last ? s.wmax + 1 : 0)) return false;
+        if (rows * t.stride * 4 + (last ? (int64_t)kScratchBytes : 0) > (int64_t)kLdsBytes) return false;
         if (t.nw != s.nw || t.wofs != s.wofs) return false;
         int64_t lo, hi;
         if (pass == 0) {
@@ -315,8 +332,11 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   // --- tiles: chunk, then pass, then step, then problem q, then group h
   for (auto& c : p->chunks) {
     c.n_passes = 0;
-    for (int32_t si = c.step_begin; si < c.step_end; ++si)
+    c.max_P0 = 0;
+    for (int32_t si = c.step_begin; si < c.step_end; ++si) {
       c.n_passes = std::max(c.n_passes, p->steps[si].n_passes);
+      c.max_P0 = std::max(c.max_P0, p->steps[si].P0);
+    }
     for (int32_t pass = 0; pass < c.n_passes; ++pass) {
       c.tile_begin[pass] = (int64_t)p->tiles.size();
       c.lds_bytes[pass] = 0;
@@ -333,8 +353,8 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
         const int64_t ng = (vin + (int64_t(1) << dp) - 1) >> dp;
         const bool last = pass == s.n_passes - 1;
         const int64_t src_base = pass == 0 ? p->oct_off[s.octave] : s.buf_off[(pass - 1) % 2];
-        const int32_t stride = last ? s.P0 + s.wmax + 1 : s.P0;
-        s.lds_bytes[pass] = (int32_t)((int64_t(1) << dp) * stride * 4);
+        const int32_t stride = stride_of(s, dp, last);
+        s.lds_bytes[pass] = (int32_t)lds_of(s, dp, last);
         c.lds_bytes[pass] = std::max(c.lds_bytes[pass], s.lds_bytes[pass]);
         for (int64_t q = 0; q < Q; ++q) {
           for (int64_t h = 0; h < ng; ++h) {
@@ -344,6 +364,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
             t.src = src_base + (q * Gin + (h << dp)) * s.P0;
             t.valid = (int32_t)std::min<int64_t>(int64_t(1) << dp, vin - (h << dp));
             t.stride = stride;
+            t.halo = halo_of(s.P0, dp);
             t.wofs = s.wofs;
             t.nw = s.nw;
             t.step = si;
@@ -366,6 +387,9 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     }
   }
   p->ws_bytes = (size_t)round_up((p->inter_off + p->inter_elems) * 4, (int64_t)kWsAlign);
+  // test knobs: force the selection's fallback paths
+  if (const char* e = std::getenv("FFA_SELECT_ITERS")) p->select_iters = std::max(0, std::atoi(e));
+  if (const char* e = std::getenv("FFA_SELECT_CAND")) p->select_cand = std::min(64, std::max(1, std::atoi(e)));
   if (!tiles_in_bounds(p)) {
     delete p;
     return fail(FFA_ERR_INVALID, "internal planning error: a tile reaches outside its buffers");

@@ -176,3 +176,21 @@ def test_best(torch_cuda, ffa):
         v[g.integers(0, n, size=3)] = 9.0  # ties: first wins
         t = torch_cuda.from_numpy(v).cuda()
         assert ffa.best(t) == int(np.argmax(v))
+
+
+@pytest.mark.parametrize("knob", [("FFA_SELECT_ITERS", "0"), ("FFA_SELECT_CAND", "1"),
+                                  ("FFA_SELECT_CAND", "8")])
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_selection_paths(torch_cuda, ffa, oracle_mod, knob, dtype, monkeypatch):
+    """The median/MAD selection's other exits: the full-sort fallback (no
+    counting rounds), bisection down to one candidate, and a small in-lane
+    select; each must give the same periodogram."""
+    from paper_1703_05581_amd import synth
+
+    monkeypatch.setenv(*knob)
+    N = 30000
+    x = synth.random_series(5 + N, N, dtype)
+    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.2, 0.52, 200, W10, dtype, steps_max=12)
+    xs = (x // 16 * 16) if dtype == "u8" else np.round(x * 4) / 4  # many ties
+    run_case(torch_cuda, ffa, oracle_mod, xs.astype(x.dtype), N, 1e-3, 0.2, 0.52, 200, W10, dtype,
+             steps_max=6)
