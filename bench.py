@@ -3,20 +3,30 @@
 Workload: one 2^20-sample uint8 series (tsamp 1 ms, N(128, 16^2) noise with
 three pulsars), base periods P0 in [256, 512) bins over octaves f = 1, 2, 4
 (0.256-2.048 s), ten boxcar widths; 768 FFA executions, 1,835,008 trials.
-One step = one ffa_search of that series (downsampling, every FFA butterfly
-level, Algorithm 1 scoring of every folded profile, periodogram written), with
-the series already resident in HBM.
+One step = one search of that series: ffa_prepare (octave downsampling),
+ffa_search_prepared (every FFA butterfly level, Algorithm 1 scoring of every
+folded profile, periodogram written) and ffa_best (best trial), with the
+series already resident in HBM.
 
 Metric: trial*samples/s = sum over executions of M*(m*P0) per second.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one
 GPU.
+
+Profiling helpers (run under rocprofv3, then summarised by this script):
+  --calibrate-copy      after the timed steps, copy 256 MiB device-to-device
+                        three times (a plain copy of known size, to scale the
+                        HBM byte counters)
+  --pmc-summary DB      print per-kernel averages of the counters in a
+                        rocprofv3 database and exit
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit VALU operations (no packed
 # form is used), in tera-operations per second.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+KERNEL_SRC = os.path.join(ROOT, "paper_1703_05581_amd", "csrc", "ffa_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ffa_tile_kernel.u8_2e20.traffic.md")
+COPY_BYTES = 256 << 20
 
 
 def parse():
@@ -35,9 +48,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=48,
+    ap.add_argument("--cpu-steps", type=int, default=768,
                     help="FFA executions the oracle times for the CPU baseline")
     ap.add_argument("--check", action="store_true", help="check sampled trials against the oracle")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--pmc-summary", metavar="DB")
+    ap.add_argument("--searches", type=int, default=0,
+                    help="with --pmc-summary: searches the profiled run made")
     return ap.parse_args()
 
 
@@ -61,10 +78,53 @@ def workload_units(plan):
     return ts, in_bytes + 8 * trials, ops
 
 
+def source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per search of the FFA kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = re.search(r"^kernel_source_sha256_16: (\w+)", text, re.M)
+    b = re.search(r"^traffic_bytes_per_search: ([0-9.eE+]+)", text, re.M)
+    if not h or not b or h.group(1) != source_hash():
+        return None
+    return float(b.group(1))
+
+
+def pmc_summary(db_path: str, searches: int) -> None:
+    import sqlite3
+
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select kernel_name, counter_name, count(*), sum(value) from counters_collection "
+                      "group by kernel_name, counter_name").fetchall()
+    print(f"kernel_source_sha256_16: {source_hash()}")
+    print("| kernel | counter | dispatches | mean per dispatch | total |")
+    print("|---|---|---|---|---|")
+    tot = {}
+    for name, ctr, n, total in sorted(rows, key=lambda r: -r[3]):
+        short = re.sub(r"\(.*", "", name)[:60]
+        print(f"| {short} | {ctr} | {n} | {total / n:.6g} | {total:.6g} |")
+        tot[(short, ctr)] = (n, total)
+    if searches:
+        for (short, ctr), (n, total) in tot.items():
+            if "ffa_tile_kernel" in short:
+                print(f"{ctr}_KiB_per_search: {total / searches:.6g}")
+
+
 def main():
     a = parse()
+    if a.pmc_summary:
+        pmc_summary(a.pmc_summary, a.searches)
+        return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(no multi-GPU path is built)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -82,22 +142,35 @@ def main():
     ws = plan.workspace(dev)
     ts, alg_bytes, alg_ops = workload_units(plan)
 
+    best_t = torch.empty(1, dtype=torch.int64, device=dev)
     for _ in range(a.warmup):
-        plan.search(x, snr, wid, ws)
+        plan.prepare(x, ws)
+        plan.search_prepared(snr, wid, ws)
+        ffa.best(snr, out=best_t)
     torch.cuda.synchronize()
+    # The library launches on torch's current stream, where the events are
+    # recorded: e_mid..e_end brackets exactly the FFA kernel launches of a step.
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(a.steps):
-        plan.search(x, snr, wid, ws)
-    e1.record(stream)
+    for e_beg, e_mid, e_end, e_best in ev:
+        e_beg.record(stream)
+        plan.prepare(x, ws)
+        e_mid.record(stream)
+        plan.search_prepared(snr, wid, ws)
+        e_end.record(stream)
+        ffa.best(snr, out=best_t)
+        e_best.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / a.steps
+    ms = ev[0][0].elapsed_time(ev[-1][3]) / a.steps
     sec = ms / 1e3
+    kern_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / a.steps
+    prep_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / a.steps
+    best_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / a.steps
+    ksec = kern_ms / 1e3
+    traffic = stored_traffic()
 
     out = {
         "metric": "FFA trial*samples/s incl. boxcar S/N (Algorithm 1)",
@@ -110,7 +183,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8->i32",
+        "dtype": "i32",
         "data": "synthetic (seeded; workload 2 of paper_1703_05581_amd.synth)",
         "config": {"workload": "uint8 series 2^20 samples, tsamp 1 ms, P0 256..511 at f=1,2,4, "
                                "10 widths, 768 FFA executions, 1835008 trials",
@@ -118,20 +191,31 @@ def main():
                    "trial_samples": ts},
         "roofline": {
             "bound": "alu",
-            "achieved": alg_ops / sec / 1e12,
+            "kernel": "ffa_tile_kernel (all launches of one search)",
+            "achieved": alg_ops / ksec / 1e12,
             "peak": VALU_PEAK_TOPS,
             "unit": "TOP/s",
-            "frac": alg_ops / sec / 1e12 / VALU_PEAK_TOPS,
-            "traffic": None,
+            "frac": alg_ops / ksec / 1e12 / VALU_PEAK_TOPS,
+            "traffic": traffic,
+            "kernel_ms_per_search": kern_ms,
         },
+        "prepare_ms_per_search": prep_ms,
+        "best_ms_per_search": best_ms,
         "hbm": {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / sec / 1e9,
                 "frac_of_8TBs": alg_bytes / sec / 1e9 / HBM_PEAK_GBS},
         "wall_s": wall,
     }
-    best = ffa.best(snr)
+    best = int(best_t.item())
     per = plan.periods()
     out["best_trial"] = {"index": best, "period_s": float(per[best]),
                          "snr": float(snr[best].item()), "width": int(wid[best].item())}
+
+    if a.calibrate_copy:
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     if a.check or not a.no_cpu_baseline:
         import oracle
@@ -139,15 +223,19 @@ def main():
         op = oracle.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
         g = np.random.default_rng(1)
         sel = np.sort(g.choice(op.n_steps, size=min(a.cpu_steps, op.n_steps), replace=False))
-        threads = os.cpu_count() or 1
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            threads = os.cpu_count() or 1
+        threads = max(1, min(threads, 16))
         t0 = time.perf_counter()
         snr_o, w_o = oracle.search(series.data, op, list(pa.widths), steps=sel, threads=threads)
         cpu_s = time.perf_counter() - t0
         sample_ts = int(sum(int(op.M[s]) * int(op.m[s]) * int(op.P0[s]) for s in sel))
         out["cpu_baseline"] = {"value": sample_ts / cpu_s, "unit": "trial*samples/s", "cores": threads,
                                "kind": "oracle",
-                               "sample": f"{sel.size} of {op.n_steps} FFA executions (seeded pick), "
-                                         f"{sample_ts:.3e} trial*samples in {cpu_s:.1f} s"}
+                               "sample": f"{sel.size} of {op.n_steps} FFA executions of the same "
+                                         f"series, {sample_ts:.3e} trial*samples in {cpu_s:.1f} s"}
         if a.check:
             sys.path.insert(0, os.path.join(ROOT, "tests"))
             from parity import check_periodogram, step_trials

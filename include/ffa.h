@@ -131,6 +131,16 @@ ffa_status ffa_search(ffa_plan plan, const void* d_series, float* d_snr,
                       int32_t* d_width, void* d_ws, size_t ws_bytes,
                       void* stream);
 
+/* ffa_search in two parts.  ffa_prepare builds the downsampled octave series
+ * of `d_series` in the workspace (centred on the mean for float input);
+ * ffa_search_prepared then runs every FFA pass and the scoring of every
+ * profile, reading the octave series that the last ffa_prepare on the same
+ * workspace and plan left there.  Same arguments and errors as ffa_search. */
+ffa_status ffa_prepare(ffa_plan plan, const void* d_series, void* d_ws,
+                       size_t ws_bytes, void* stream);
+ffa_status ffa_search_prepared(ffa_plan plan, float* d_snr, int32_t* d_width,
+                               void* d_ws, size_t ws_bytes, void* stream);
+
 /* Raw folded profiles of step `step` (Sec. 2.1): M rows of P0 bins, row k is
  * trial k.  float32 series give float32 sums; uint8 series give exact int32
  * sums.  Not centred.  Errors as ffa_search. */
@@ -138,19 +148,25 @@ ffa_status ffa_fold(ffa_plan plan, const void* d_series, int32_t step,
                     void* d_profiles, void* d_ws, size_t ws_bytes,
                     void* stream);
 
-/* Best trial of a periodogram: the largest score, the first trial on ties.
- *   d_snr        n_trials scores (as from ffa_search)
- *   d_best       one int64: index of the best trial
+/* Best trial of a periodogram (the peak of Sec. 2.2's periodogram): the
+ * largest score, the first trial on ties; NaN scores never win, -0 equals +0.
+ *   d_snr        n_trials scores (as from ffa_search), 1 <= n_trials < 2^32
+ *   d_best       one int64 on the device: index of the best trial (also used
+ *                as the reduction's accumulator while the call runs)
  * Errors: FFA_ERR_INVALID, FFA_ERR_DEVICE. */
 ffa_status ffa_best(const float* d_snr, int64_t n_trials, int64_t* d_best,
                     void* stream);
 
-/* Batched search: the periodograms of n series, each with its own plan, in
- * one persistent launch over a shared work queue.
+/* Batched search: the periodograms of n series, each with its own plan (any
+ * mix of sample types).  The series are spread over a few streams that the
+ * library owns on the current GPU, which wait for earlier work on `stream`
+ * and which `stream` waits for, so the call behaves as if it were enqueued on
+ * `stream`.
  *   plans[i], d_series[i], d_snr[i], d_width[i]  host arrays of n entries
- *   d_ws   workspace of at least ffa_batch_workspace(n, plans) bytes
- * Results equal those of ffa_search on each series.  The plans must have been
- * created on the current GPU. */
+ *   d_ws   workspace of at least ffa_batch_workspace(n, plans) bytes,
+ *          256-B aligned
+ * Results equal those of ffa_search on each series.  Errors as ffa_search;
+ * after a launch error the work already enqueued still runs to its end. */
 ffa_status ffa_batch_workspace(int32_t n, const ffa_plan* plans,
                                size_t* ws_bytes);
 ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,

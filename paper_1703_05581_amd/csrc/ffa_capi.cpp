@@ -1,4 +1,4 @@
-// C ABI entry points that enqueue GPU work: search, fold, best.
+// C ABI entry points that enqueue GPU work: prepare, search, fold, best.
 #include <cstdint>
 
 #include "ffa_internal.h"
@@ -11,17 +11,34 @@ using namespace ffa;
 
 namespace {
 
-ffa_status check_ws(ffa_plan p, const void* ws, size_t ws_bytes) {
+ffa_status check_ws(size_t need, const void* ws, size_t ws_bytes) {
   if (!ws) return fail(FFA_ERR_INVALID, "null workspace");
-  if (ws_bytes < p->ws_bytes) return fail(FFA_ERR_INVALID, "workspace smaller than ffa_plan_query's ws_bytes");
+  if (ws_bytes < need) return fail(FFA_ERR_INVALID, "workspace smaller than the plan's ws_bytes");
   if (reinterpret_cast<uintptr_t>(ws) % kWsAlign) return fail(FFA_ERR_INVALID, "workspace not 256-byte aligned");
   return FFA_OK;
 }
 
-// Octave series 0..last_octave into the workspace.  Float input is centred
-// on its mean when `center` is set.
-ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave,
-                         int center, hipStream_t st) {
+TileArgs base_args(ffa_plan p, const DeviceTables* dt) {
+  TileArgs a{};
+  a.widths = dt->widths;
+  a.sqrtw = dt->sqrtw;
+  a.oct_base = 0;
+  a.ring_off = p->ring_off;
+  a.slot_elems = p->slot_elems;
+  a.n_slots = p->n_slots;
+  a.select_iters = p->select_iters;
+  a.select_cand = p->select_cand;
+  return a;
+}
+
+}  // namespace
+
+namespace ffa {
+
+// Octave series 0..last_octave of one series into the series region at the
+// start of `ws`.  Float input is centred on its mean when `center`.
+ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave, int center,
+                         hipStream_t st) {
   const int is_int = p->desc.dtype == FFA_IN_U8;
   if (!is_int && center) {
     ffa_status s = check_hip(launch_mean(reinterpret_cast<const float*>(series), p->desc.N, ws, st),
@@ -39,53 +56,80 @@ ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_
   return FFA_OK;
 }
 
-}  // namespace
+ffa_status run_launches(ffa_plan p, const DeviceTables* dt, float* snr, int32_t* width, void* ws,
+                       hipStream_t st) {
+  const int is_int = p->desc.dtype == FFA_IN_U8;
+  TileArgs a = base_args(p, dt);
+  a.phases = dt->phases;
+  a.tile_phase = dt->tile_phase;
+  a.snr = snr;
+  a.width = width;
+  a.mode = kModeScore;
+  for (const Launch& w : p->launches) {
+    if (w.ntiles == 0) continue;
+    a.tile0 = w.tile0;
+    ffa_status s = check_hip(launch_tiles(a, w.ntiles, w.lds_bytes, w.max_P0, is_int, ws, st),
+                             "FFA kernel");
+    if (s != FFA_OK) return s;
+  }
+  return FFA_OK;
+}
 
-extern "C" ffa_status ffa_search(ffa_plan p, const void* d_series, float* d_snr, int32_t* d_width,
-                                 void* d_ws, size_t ws_bytes, void* stream) {
-  if (!p || !d_series || !d_snr || !d_width) return fail(FFA_ERR_INVALID, "null argument");
-  ffa_status s = check_ws(p, d_ws, ws_bytes);
+}  // namespace ffa
+
+extern "C" ffa_status ffa_prepare(ffa_plan p, const void* d_series, void* d_ws, size_t ws_bytes,
+                                  void* stream) {
+  if (!p || !d_series) return fail(FFA_ERR_INVALID, "null argument");
+  ffa_status s = check_ws(p->ws_bytes, d_ws, ws_bytes);
+  if (s != FFA_OK) return s;
+  return build_octaves(p, d_series, d_ws, p->n_octaves - 1, 1, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" ffa_status ffa_search_prepared(ffa_plan p, float* d_snr, int32_t* d_width, void* d_ws,
+                                          size_t ws_bytes, void* stream) {
+  if (!p || !d_snr || !d_width) return fail(FFA_ERR_INVALID, "null argument");
+  ffa_status s = check_ws(p->ws_bytes, d_ws, ws_bytes);
   if (s != FFA_OK) return s;
   const DeviceTables* dt = nullptr;
   s = device_tables(p, &dt);
   if (s != FFA_OK) return s;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int is_int = p->desc.dtype == FFA_IN_U8;
-  s = build_octaves(p, d_series, d_ws, p->n_octaves - 1, 1, st);
+  return run_launches(p, dt, d_snr, d_width, d_ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" ffa_status ffa_search(ffa_plan p, const void* d_series, float* d_snr, int32_t* d_width,
+                                 void* d_ws, size_t ws_bytes, void* stream) {
+  if (!p || !d_series || !d_snr || !d_width) return fail(FFA_ERR_INVALID, "null argument");
+  ffa_status s = ffa_prepare(p, d_series, d_ws, ws_bytes, stream);
   if (s != FFA_OK) return s;
-  for (const Chunk& c : p->chunks) {
-    for (int32_t pass = 0; pass < c.n_passes; ++pass) {
-      s = check_hip(launch_pass(dt->tiles + c.tile_begin[pass], c.tile_end[pass] - c.tile_begin[pass],
-                                c.lds_bytes[pass], c.max_P0, is_int, d_ws, d_snr, d_width, nullptr, 0,
-                                kModeScore, dt->widths, dt->sqrtw, p->select_iters,
-                                p->select_cand, st),
-                    "FFA pass kernel");
-      if (s != FFA_OK) return s;
-    }
-  }
-  return FFA_OK;
+  return ffa_search_prepared(p, d_snr, d_width, d_ws, ws_bytes, stream);
 }
 
 extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, void* d_profiles,
                                void* d_ws, size_t ws_bytes, void* stream) {
   if (!p || !d_series || !d_profiles) return fail(FFA_ERR_INVALID, "null argument");
   if (step < 0 || step >= (int32_t)p->steps.size()) return fail(FFA_ERR_INVALID, "step out of range");
-  ffa_status s = check_ws(p, d_ws, ws_bytes);
+  ffa_status s = check_ws(p->ws_bytes, d_ws, ws_bytes);
   if (s != FFA_OK) return s;
   const DeviceTables* dt = nullptr;
   s = device_tables(p, &dt);
   if (s != FFA_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int is_int = p->desc.dtype == FFA_IN_U8;
   const Step& sp = p->steps[step];
   s = build_octaves(p, d_series, d_ws, sp.octave, 0, st);
   if (s != FFA_OK) return s;
+  // the step's passes in order, one launch each
+  const int is_int = p->desc.dtype == FFA_IN_U8;
+  TileArgs a = base_args(p, dt);
+  a.tile_phase = nullptr;
+  a.profiles = d_profiles;
+  a.trial_base = sp.first_trial;
+  a.mode = kModeProfiles;
   for (int32_t pass = 0; pass < sp.n_passes; ++pass) {
-    s = check_hip(launch_pass(dt->tiles + sp.tile_begin[pass], sp.tile_end[pass] - sp.tile_begin[pass],
-                              sp.lds_bytes[pass], sp.P0, is_int, d_ws, nullptr, nullptr, d_profiles,
-                              sp.first_trial, kModeProfiles, dt->widths, dt->sqrtw,
-                              p->select_iters, p->select_cand, st),
-                  "FFA pass kernel");
+    const Phase& ph = p->fold_phases[(size_t)sp.fold_phase0 + pass];
+    a.phases = dt->fold_phases + sp.fold_phase0 + pass;
+    a.tile0 = ph.tile0;
+    const int lds = (int)(((int64_t)1 << ph.depth) * ph.stride * 4 + (ph.last ? (int64_t)kScratchBytes : 0));
+    s = check_hip(launch_tiles(a, ph.ntiles, lds, ph.P0, is_int, d_ws, st), "FFA kernel");
     if (s != FFA_OK) return s;
   }
   return FFA_OK;
@@ -93,6 +137,7 @@ extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, v
 
 extern "C" ffa_status ffa_best(const float* d_snr, int64_t n_trials, int64_t* d_best, void* stream) {
   if (!d_snr || !d_best || n_trials < 1) return fail(FFA_ERR_INVALID, "bad argument");
+  if (n_trials > 0xffffffffll) return fail(FFA_ERR_INVALID, "n_trials must be below 2^32");
   return check_hip(launch_best(d_snr, n_trials, d_best, reinterpret_cast<hipStream_t>(stream)),
                    "best kernel");
 }

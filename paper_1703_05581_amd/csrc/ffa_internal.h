@@ -1,4 +1,4 @@
-// Internal declarations of the FFA library: plan layout, work tiles and the
+// Internal declarations of the FFA library: plan layout, work queue and the
 // kernel launchers.  Not part of the public ABI (include/ffa.h).
 #pragma once
 
@@ -16,40 +16,67 @@
 namespace ffa {
 
 constexpr int kMaxWidths = 32;
-constexpr int kMaxBinsMin = 1024;      // P0 < 2*B <= 2048
+constexpr int kMaxBinsMin = 1024;         // P0 < 2*B <= 2048
 constexpr int kMaxPasses = 8;
-constexpr int kThreads = 1024;         // threads per workgroup of the FFA kernels
+constexpr int kThreads = 1024;            // threads per workgroup of the FFA kernel
 constexpr size_t kLdsBytes = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr size_t kWsAlign = 256;
 constexpr size_t kScratchBytes = (kThreads / 64) * 64 * 4;  // per-wave selection scratch
+constexpr int kBatchStreams = 4;          // streams a batched search spreads its series over
 
 // sigma = K * MAD (paper Sec. 2.2.1): K is 1 / (75% quantile of the unit normal).
 constexpr double kMadK = 1.482602218505602;
 
-// Output modes of the last pass of a step.
-enum : int32_t { kModeIntermediate = 0, kModeScore = 1, kModeProfiles = 2 };
+// What the last pass of a step does with its profiles.
+enum : int32_t { kModeScore = 1, kModeProfiles = 2 };
 
-// One workgroup's work: 2^depth rows of P0 bins (a "group"), all butterfly
-// levels of one pass run on chip, then either written back (rotated) for the
-// next pass or scored / written as profiles.
-struct Tile {
-  int64_t src;       // element offset in the workspace of row 0 of the group
-  int64_t dst;       // intermediate: element offset of output t = 0
-                     // last pass: global trial index of output t = 0
+// One pass of one step: Q*ng tiles, each 2^depth rows of P0 bins (a "group")
+// whose butterfly levels run on chip.  Tile k is problem q = k / ng, group
+// h = k % ng.
+struct Phase {
+  int64_t tile0;        // first tile of the phase in its plan's queue order
+  int64_t oct_off;      // pass 0: series-relative offset of the octave series
+  int64_t first_trial;  // trial index of the step's trial 0
+  int32_t ntiles;
+  int32_t ng;           // groups with data per problem
+  int32_t step;         // step index in the plan
+  int32_t pass;
+  int32_t last;         // 1 on the step's last pass
   int32_t P0;
-  int32_t depth;     // rows = 1 << depth
-  int32_t valid;     // rows >= valid are zero and not read
-  int32_t h;         // group index: output t is rotated left by t*h bins
-  int32_t dst_step;  // intermediate: elements between outputs t and t+1
-  int32_t final_;    // 1 on the last pass of the step
-  int32_t wofs;      // offset of the step's widths in the width tables
-  int32_t nw;        // number of widths of the step
-  int32_t stride;    // LDS row stride in elements
-  int32_t step;      // step index (diagnostics)
-  int32_t halo;      // LDS bins after P0 that repeat bins 0..halo-1
-  int32_t pad_;
+  int32_t M;
+  int32_t depth;        // levels run by this pass
+  int32_t D;            // levels run by the earlier passes
+  int32_t vin;          // rows with data per problem
+  int32_t stride;       // LDS row stride (elements)
+  int32_t halo;         // LDS bins after P0 that repeat bins 0..halo-1
+  int32_t wofs;         // the step's widths in the width tables
+  int32_t nw;
+  int32_t isqrt_ofs;    // the step's 1/sqrt(width) values in the sqrt table
+  int32_t launch;       // index of the launch that runs the phase
+  int32_t pad_[2];
 };
-static_assert(sizeof(Tile) == 64, "tile layout");
+static_assert(sizeof(Phase) == 96, "phase layout");
+
+// Arguments of one launch of the FFA kernel: tiles tile0 .. tile0+grid-1 of a
+// plan's queue (or of one step's passes, for a fold).
+struct TileArgs {
+  const Phase* phases;        // queue-ordered phases (or one fold phase)
+  const int32_t* tile_phase;  // phase index of every queue tile; null: all tiles are phases[0]
+  const int32_t* widths;
+  const double* sqrtw;
+  float* snr;
+  int32_t* width;
+  void* profiles;             // fold: M*P0 output of the step
+  int64_t tile0;
+  int64_t oct_base;           // element offset of the series region in the workspace
+  int64_t ring_off;           // element offset of the intermediate ring
+  int64_t slot_elems;         // elements per ring slot (two buffers of M*P0)
+  int64_t trial_base;         // fold: trial index of output row 0
+  int32_t n_slots;
+  int32_t mode;
+  int32_t select_iters;
+  int32_t select_cand;
+};
 
 struct Step {
   int32_t f, octave, P0, m, M, L;
@@ -57,25 +84,26 @@ struct Step {
   int32_t n_passes;
   int32_t depth[kMaxPasses];
   int32_t wofs, nw, wmax;
-  int32_t chunk;
-  // tiles of pass p: [tile_begin[p], tile_end[p]) in Plan::tiles
-  int64_t tile_begin[kMaxPasses], tile_end[kMaxPasses];
-  int64_t buf_off[2];  // intermediate ping-pong buffers (elements, workspace-relative)
-  int32_t lds_bytes[kMaxPasses];
+  int32_t tiles[kMaxPasses];  // tiles of each pass
+  int32_t total_tiles;
+  int32_t lds_bytes;          // largest LDS footprint of its passes
+  int32_t fold_phase0;        // its phases in pass order, in Plan::fold_phases
 };
 
-struct Chunk {
-  int32_t step_begin, step_end;
-  int32_t n_passes;  // max over its steps
-  int64_t tile_begin[kMaxPasses], tile_end[kMaxPasses];
-  int32_t lds_bytes[kMaxPasses];
+// One launch of a search: a window of the queue whose tiles depend only on
+// tiles of earlier launches.
+struct Launch {
+  int64_t tile0, ntiles;
+  int32_t lds_bytes;
   int32_t max_P0;
 };
 
 // Device copies of a plan's tables (made on first use on a device).
 struct DeviceTables {
   int device = -1;
-  Tile* tiles = nullptr;
+  Phase* phases = nullptr;
+  Phase* fold_phases = nullptr;
+  int32_t* tile_phase = nullptr;
   int32_t* widths = nullptr;
   double* sqrtw = nullptr;
 };
@@ -86,22 +114,31 @@ struct ffa_plan_s {
   ffa_plan_desc desc;
   std::vector<int32_t> user_widths;
   std::vector<ffa::Step> steps;
-  std::vector<ffa::Chunk> chunks;
-  std::vector<ffa::Tile> tiles;
-  std::vector<int32_t> wtab;     // widths of every step, concatenated
-  std::vector<double> sqrtw;     // sqrt(width), same layout
+  std::vector<ffa::Phase> phases;       // queue order: pass p of step s at key s + p*lookahead
+  std::vector<ffa::Phase> fold_phases;  // per step, its passes in order
+  std::vector<int32_t> tile_phase;      // queue tile -> index in phases
+  std::vector<ffa::Launch> launches;     // launches of a search, in order
+  std::vector<int32_t> wtab;            // widths of every step, concatenated
+  std::vector<double> sqrtw;            // sqrt(width), same layout, then 1/sqrt(width)
   int64_t n_trials = 0;
-  int32_t n_octaves = 0;         // octaves 0..n_octaves-1 are built
-  std::vector<int64_t> oct_off;  // element offset of each octave series
+  int64_t n_tiles = 0;
+  int32_t max_passes = 1;
+  int32_t lookahead = 1;                // keys per window
+  int32_t n_slots = 1;                  // intermediate ring slots
+  int64_t slot_elems = 0;               // intermediate elements per slot
+  int32_t lds_bytes = 0;                // largest tile LDS footprint
+  int32_t max_P0 = 0;
+  int32_t n_octaves = 0;                // octaves 0..n_octaves-1 are built
+  std::vector<int64_t> oct_off;         // series-relative offset of each octave series
   std::vector<int64_t> oct_len;
-  int64_t hdr_elems = 0;         // header (centring scratch) in elements
-  int64_t inter_off = 0;         // element offset of the intermediate region
-  int64_t inter_elems = 0;
+  int64_t hdr_elems = 0;                // header (centring scratch) in elements
+  int64_t series_elems = 0;             // header + octave series
+  int64_t ring_off = 0;                 // workspace: series region, then the ring
   size_t ws_bytes = 0;
-  int32_t select_iters = 64;     // counting rounds before the sort fallback
-  int32_t select_cand = 64;      // candidates handed to the exact in-lane select
+  int32_t select_iters = 64;            // counting rounds before key halving
+  int32_t select_cand = 64;             // candidates handed to the in-lane select
   std::mutex dev_mu;
-  std::deque<ffa::DeviceTables> dev;  // one entry per device used (stable addresses)
+  std::deque<ffa::DeviceTables> dev;    // one entry per device used (stable addresses)
 };
 
 namespace ffa {
@@ -113,19 +150,25 @@ ffa_status check_hip(hipError_t e, const char* what);
 // Device tables of plan p on the current device (creates them on first use).
 ffa_status device_tables(ffa_plan p, const DeviceTables** out);
 
+ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave,
+                         int center, hipStream_t st);
+// Every launch of plan p's search on `st`, workspace `ws` already holding the
+// octave series.
+ffa_status run_launches(ffa_plan p, const DeviceTables* dt, float* snr, int32_t* width, void* ws,
+                       hipStream_t st);
+
 // Kernel launchers (ffa_kernels.hip).  All element offsets are in 4-byte
 // elements relative to ws.  is_int selects int32 accumulation (uint8 input).
 hipError_t launch_mean(const float* x, int64_t n, void* ws, hipStream_t st);
-hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws,
-                       int64_t out_off, int center, hipStream_t st);
-hipError_t launch_halve(void* ws, int is_int, int64_t in_off, int64_t n_out,
-                        int64_t out_off, hipStream_t st);
-hipError_t launch_pass(const Tile* tiles, int64_t n_tiles, int lds_bytes, int max_P0,
-                       int is_int, void* ws, float* snr, int32_t* width,
-                       void* profiles, int64_t trial_base, int mode,
-                       const int32_t* wtab, const double* sqrtw,
-                       int select_iters, int select_cand, hipStream_t st);
-hipError_t launch_best(const float* snr, int64_t n, int64_t* best,
-                       hipStream_t st);
+hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws, int64_t out_off,
+                       int center, hipStream_t st);
+hipError_t launch_halve(void* ws, int is_int, int64_t in_off, int64_t n_out, int64_t out_off,
+                        hipStream_t st);
+// Checks that the kernel variant for max_P0 fits lds_bytes of dynamic LDS on
+// the current device (static LDS included); caches the answer.
+bool tiles_fit(int is_int, int max_P0, int lds_bytes);
+hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
+                        void* ws, hipStream_t st);
+hipError_t launch_best(const float* snr, int64_t n, int64_t* best, hipStream_t st);
 
 }  // namespace ffa

@@ -6,8 +6,12 @@
 // each folded profile with Algorithm 1 (paper Sec. 2.2.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "ffa_internal.h"
 
@@ -138,22 +142,40 @@ __device__ __forceinline__ void butterfly(T* lds, int S, int P0, int H, int d) {
       const int v = p & (half - 1);
       T* A = lds + (size_t)(beta * 2 * half + bitrev(v, l - 1)) * S;
       T* B = A + (size_t)half * S;
-      const int sh = v % P0;
+      const int sh = v < P0 ? v : v % P0;
       const int hn = sh + 1 < H ? sh + 1 : H;  // halo bins this pair reads
       for (int i = lane; i < hn; i += kWave) B[P0 + i] = B[i];
-      const T* B0 = B + sh;
-      // The chunk count is wave-uniform so that all lanes work on the same
-      // chunk together: the in-place writes rely on it.
-      const int nchunk = (P0 + kWave - 1) / kWave;
-      for (int c = 0; c < nchunk; ++c) {
-        const int j = c * kWave + lane;
-        if (j < P0) {
-          const T a = A[j];
-          const T b0 = B0[j];
-          const T b1 = B0[j + 1];
-          A[j] = a + b0;
-          B[j] = a + b1;
-        }
+      // The chunk loop is wave-uniform so that all lanes work on the same
+      // chunk together: the in-place writes rely on it.  Full chunks run
+      // unpredicated, two at a time; the last partial chunk is predicated.
+      T* pa = A + lane;
+      T* pb = B + lane;
+      const T* pb0 = B + sh + lane;
+      const int nfull = P0 / kWave;
+      int c = 0;
+      for (; c + 2 <= nfull; c += 2) {
+        const T a0 = pa[0], a1 = pa[kWave];
+        const T x0 = pb0[0], y0 = pb0[1], x1 = pb0[kWave], y1 = pb0[kWave + 1];
+        pa[0] = a0 + x0;
+        pb[0] = a0 + y0;
+        pa[kWave] = a1 + x1;
+        pb[kWave] = a1 + y1;
+        pa += 2 * kWave;
+        pb += 2 * kWave;
+        pb0 += 2 * kWave;
+      }
+      if (c < nfull) {
+        const T a0 = pa[0], x0 = pb0[0], y0 = pb0[1];
+        pa[0] = a0 + x0;
+        pb[0] = a0 + y0;
+        pa += kWave;
+        pb += kWave;
+        pb0 += kWave;
+      }
+      if (nfull * kWave + lane < P0) {
+        const T a0 = pa[0], x0 = pb0[0], y0 = pb0[1];
+        pa[0] = a0 + x0;
+        pb[0] = a0 + y0;
       }
     }
     __syncthreads();
@@ -321,8 +343,8 @@ struct Types<false> {
 // a host table, so every rounding is a correctly rounded IEEE operation.
 template <int E, bool INT>
 __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
-                              const int32_t* widths, const double* sqrtw, int nw, SelectKnobs kn,
-                              float* snr_out, int32_t* width_out) {
+                              const int32_t* widths, const double* sqrtw, const double* isqrtw,
+                              int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
   using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
   const int lane = lane_id();
@@ -361,9 +383,9 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const bool real = r * kWave + lane < P0;
-    if constexpr (INT) {
-      const int64_t dv = 2 * (int64_t)key[r] - (int64_t)med2;
-      key[r] = real ? (uint32_t)(dv < 0 ? -dv : dv) : kPadKey;
+    if constexpr (INT) {  // 2*x and med2 are below 2^32 (sums below 2^31)
+      const uint32_t tx = 2u * key[r], m2 = (uint32_t)med2;
+      key[r] = real ? (tx >= m2 ? tx - m2 : m2 - tx) : kPadKey;
     } else {
       key[r] = real ? fkey(fabsf(fval(key[r]) - med)) : kPadKey;
     }
@@ -414,8 +436,14 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   for (int i = lane; i < wmax; i += kWave) row[P0 + 1 + i] = (T)(total + (A)row[1 + i]);
   wave_lds_sync();
 
-  // each width: largest boxcar sum, then its score; first width wins ties
-  double best = 0.0;
+  // Each width: largest boxcar sum, then its score num_w / ((K*MAD)*sqrt(w)).
+  // The divisor scale is the same for every width, so widths are ranked by
+  // num_w * (1/sqrt(w)) first; the exact division runs only for a width
+  // within 1e-12 of the best seen so far.  A width skipped that way is
+  // strictly below the final maximum, so the result and the first-width tie
+  // rule are those of dividing for every width.
+  const double scale = INT ? kMadK * (double)mad4 : kMadK * (double)mad;
+  double best = 0.0, amax = -INFINITY;
   int32_t bw = 0;
 #pragma unroll
   for (int i = 0; i < kMaxWidths; ++i) {
@@ -424,28 +452,36 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     A mx;  // box sums are >= 0 for integers
     if constexpr (INT) mx = 0u;
     else mx = -INFINITY;
+    const T* rw = row + w + lane;
+    const int nfull = P0 / kWave;  // registers holding 64 real bins
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const int j = r * kWave + lane;
-      if (j < P0) {
-        const A box = (A)row[j + w] - cex[r];
-        mx = box > mx ? box : mx;
+      if (r < nfull) {  // wave-uniform branch
+        const A b = (A)rw[r * kWave] - cex[r];
+        if constexpr (INT) mx = umax(mx, b);
+        else mx = fmaxf(mx, b);
+      } else if (r == nfull && lane < P0 - r * kWave) {
+        const A b = (A)rw[r * kWave] - cex[r];
+        if constexpr (INT) mx = umax(mx, b);
+        else mx = fmaxf(mx, b);
       }
     }
-    uint32_t pk;
-    if constexpr (INT) pk = wave_umax(mx);
-    else pk = wave_umax(fkey(mx));
-    double sc;
+    double num;
     if constexpr (INT) {
-      const int64_t num = 2 * (2 * (int64_t)pk - (int64_t)w * (int64_t)med2);
-      const double den = (kMadK * (double)mad4) * sqrtw[i];
-      sc = (double)num / den;
+      const uint32_t pk = wave_umax(mx);
+      num = (double)(2 * (2 * (int64_t)pk - (int64_t)w * (int64_t)med2));
     } else {
-      sc = ((double)fval(pk) - (double)w * (double)med) / ((kMadK * (double)mad) * sqrtw[i]);
+      const float pk = fval(wave_umax(fkey(mx)));
+      num = (double)pk - (double)w * (double)med;
     }
-    if (bw == 0 || sc > best) {
-      best = sc;
-      bw = w;
+    const double a = num * isqrtw[i];
+    amax = a > amax ? a : amax;
+    if (a >= amax - 1e-12 * fabs(amax)) {
+      const double sc = num / (scale * sqrtw[i]);
+      if (bw == 0 || sc > best) {
+        best = sc;
+        bw = w;
+      }
     }
   }
   if (lane == 0) {
@@ -458,10 +494,10 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 // P0 <= 64*EMAX are scored (the launcher picks EMAX from the largest P0).
 template <bool INT, int EMAX>
 __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
-                               const int32_t* widths, const double* sqrtw, int nw, SelectKnobs kn,
-                               float* snr_out, int32_t* width_out) {
+                               const int32_t* widths, const double* sqrtw, const double* isqrtw,
+                               int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
 #define FFA_SCORE(EE) \
-  score_profile<EE, INT>(row, scratch, P0, wmax, widths, sqrtw, nw, kn, snr_out, width_out)
+  score_profile<EE, INT>(row, scratch, P0, wmax, widths, sqrtw, isqrtw, nw, kn, snr_out, width_out)
   if (P0 <= 64) FFA_SCORE(1);
   else if (P0 <= 128) FFA_SCORE(2);
   else if (P0 <= 192) FFA_SCORE(3);
@@ -481,36 +517,49 @@ __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint
 #undef FFA_SCORE
 }
 
-// ------------------------------------------------------------ pass kernel
+// ------------------------------------------------------------- tile kernel
 
+// One workgroup per tile.  A launch covers tiles whose inputs were all
+// written by earlier launches on the stream (the planner's windows), so
+// workgroups never wait on one another.
 template <bool INT, int EMAX>
-__global__ __launch_bounds__(kThreads) void ffa_pass_kernel(
-    const Tile* __restrict__ tiles, void* __restrict__ ws_raw, float* __restrict__ snr,
-    int32_t* __restrict__ width, void* __restrict__ profiles, int64_t trial_base, int mode,
-    const int32_t* __restrict__ wtab, const double* __restrict__ sqrtw, SelectKnobs kn) {
+__global__ __launch_bounds__(kThreads) void ffa_tile_kernel(TileArgs a, void* __restrict__ ws_raw) {
   using T = typename Types<INT>::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   T* ws = reinterpret_cast<T*>(ws_raw);
-
-  const Tile tl = tiles[blockIdx.x];
-  const int P0 = tl.P0;
-  const int d = tl.depth;
-  const int R = 1 << d;
-  const int S = tl.stride;
-  const int H = tl.halo;
+  const SelectKnobs kn{a.select_iters, a.select_cand};
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   const int nwaves = blockDim.x / kWave;
 
+  const int64_t t = a.tile0 + blockIdx.x;
+  const Phase ph = a.phases[a.tile_phase ? a.tile_phase[t] : 0];
+  const int32_t k = (int32_t)(t - ph.tile0);
+  const int32_t q = k / ph.ng;
+  const int32_t h = k - q * ph.ng;
+  const int64_t buf0 = a.ring_off + (int64_t)(ph.step % a.n_slots) * a.slot_elems;
+  const int64_t buf1 = buf0 + (int64_t)ph.M * ph.P0;
+
+  // geometry of this tile
+  const int d = ph.depth;
+  const int R = 1 << d;
+  const int P0 = ph.P0;
+  const int S = ph.stride;
+  const int H = ph.halo;
+  const int64_t Gin = (int64_t)ph.M >> ph.D;
+  const int64_t in_base = ph.pass == 0 ? a.oct_base + ph.oct_off : ((ph.pass - 1) & 1 ? buf1 : buf0);
+  const int64_t src_off = in_base + ((int64_t)q * Gin + ((int64_t)h << d)) * P0;
+  const int valid = min(R, ph.vin - (h << d));
+
   // stage the group's rows (rows >= valid are zero padding, paper Sec. 2.1).
-  // Element e of the staged block is row e / P0, bin e % P0; loads are issued
-  // in batches so many are in flight.
+  // Element e of the staged block is row e / P0, bin e % P0; loads are
+  // issued in batches so many are in flight.
   {
-    const T* src = ws + tl.src;
+    const T* src = ws + src_off;
     const uint32_t W = (uint32_t)P0;
     const uint32_t total = (uint32_t)R * W;
-    const uint32_t real = (uint32_t)tl.valid * W;
+    const uint32_t real = (uint32_t)valid * W;
     const uint32_t magic = 0xffffffffu / W;  // floor(2^32 / W): exact after one correction
     constexpr int kBatch = 8;
     for (uint32_t base = threadIdx.x; base < total; base += kBatch * kThreads) {
@@ -539,40 +588,44 @@ __global__ __launch_bounds__(kThreads) void ffa_pass_kernel(
 
   butterfly<T>(lds, S, P0, H, d);
 
-  if (!tl.final_) {
+  if (!ph.last) {
     // Hand partial t to the next pass rotated left by t*h bins: the levels
     // above this pass then act on the rotated rows like a plain FFA tree.
-    for (int t = wave; t < R; t += nwaves) {
-      const T* srow = lds + (size_t)bitrev(t, d) * S;
-      const int rot = (int)(((int64_t)t * tl.h) % P0);
-      T* out = ws + tl.dst + (int64_t)t * tl.dst_step;
+    const int64_t Gout = Gin >> d;
+    T* out0 = ws + ((ph.pass & 1) ? buf1 : buf0) + (((int64_t)q << d) * Gout + h) * P0;
+    const int64_t dst_step = Gout * P0;
+    for (int tt = wave; tt < R; tt += nwaves) {
+      const T* srow = lds + (size_t)bitrev(tt, d) * S;
+      const int rot = (int)(((int64_t)tt * h) % P0);
+      T* out = out0 + (int64_t)tt * dst_step;
       for (int j = lane; j < P0; j += kWave) {
         int i = j + rot;
         i -= (i >= P0) ? P0 : 0;
         out[j] = srow[i];
       }
     }
-    return;
-  }
-  if (mode == kModeProfiles) {
-    T* out = reinterpret_cast<T*>(profiles);
-    for (int t = wave; t < R; t += nwaves) {
-      const T* srow = lds + (size_t)bitrev(t, d) * S;
-      T* o = out + (tl.dst - trial_base + t) * (int64_t)P0;
+  } else if (a.mode == kModeProfiles) {
+    T* out = reinterpret_cast<T*>(a.profiles) +
+             (ph.first_trial + ((int64_t)q << d) - a.trial_base) * (int64_t)P0;
+    for (int tt = wave; tt < R; tt += nwaves) {
+      const T* srow = lds + (size_t)bitrev(tt, d) * S;
+      T* o = out + (int64_t)tt * P0;
       for (int j = lane; j < P0; j += kWave) o[j] = srow[j];
     }
-    return;
-  }
-  uint32_t* scratch = reinterpret_cast<uint32_t*>(lds + (size_t)R * S) + wave * kWave;
-  const int32_t* widths = wtab + tl.wofs;
-  const double* sw = sqrtw + tl.wofs;
-  int wmax = 0;
-  for (int i = 0; i < tl.nw; ++i) wmax = widths[i] > wmax ? widths[i] : wmax;
-  for (int t = wave; t < R; t += nwaves) {
-    T* row = lds + (size_t)bitrev(t, d) * S;
-    const int64_t trial = tl.dst + t;
-    score_dispatch<INT, EMAX>(row, scratch, P0, wmax, widths, sw, tl.nw, kn, snr + trial,
-                              width + trial);
+  } else {
+    uint32_t* scratch = reinterpret_cast<uint32_t*>(lds + (size_t)R * S) + wave * kWave;
+    const int32_t* widths = a.widths + ph.wofs;
+    const double* sw = a.sqrtw + ph.wofs;
+    const double* isw = a.sqrtw + ph.isqrt_ofs;
+    int wmax = 0;
+    for (int i = 0; i < ph.nw; ++i) wmax = widths[i] > wmax ? widths[i] : wmax;
+    const int64_t trial0 = ph.first_trial + ((int64_t)q << d);
+    for (int tt = wave; tt < R; tt += nwaves) {
+      T* row = lds + (size_t)bitrev(tt, d) * S;
+      const int64_t trial = trial0 + tt;
+      score_dispatch<INT, EMAX>(row, scratch, P0, wmax, widths, sw, isw, ph.nw, kn,
+                                a.snr + trial, a.width + trial);
+    }
   }
 }
 
@@ -633,50 +686,42 @@ __global__ void halve_kernel(const T* __restrict__ in, int64_t n_out,
   if (i < n_out) out[i] = in[2 * i] + in[2 * i + 1];
 }
 
-// Largest score, first index on ties (one workgroup; NaN never wins).
-__global__ __launch_bounds__(1024) void best_kernel(const float* __restrict__ s,
-                                                    int64_t n,
-                                                    int64_t* __restrict__ best) {
-  __shared__ float bv[1024];
-  __shared__ int64_t bi[1024];
-  float v = -INFINITY;
-  int64_t idx = -1;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const float x = s[i];
-    if (x > v || (idx < 0 && x == v)) {
-      v = x;
-      idx = i;
-    }
+// Best trial: the largest score, the first index on ties, NaN never wins.
+// Each score and index pack into one 64-bit key, larger for a better trial:
+// the score's order-preserving key above (2^32 - 1 - index), so one atomic
+// maximum per wave finds it.  The key accumulates in the output word itself.
+__device__ __forceinline__ uint64_t best_key(float v, int64_t i) {
+  const uint32_t k = v != v ? 0u : fkey(v + 0.0f);  // NaN lowest; -0 counts as +0
+  return ((uint64_t)k << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
+}
+
+__global__ void best_init_kernel(unsigned long long* __restrict__ acc) { *acc = 0ull; }
+
+__global__ __launch_bounds__(256) void best_max_kernel(const float* __restrict__ s, int64_t n,
+                                                       unsigned long long* __restrict__ acc) {
+  uint64_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = best_key(s[i], i);
+    m = k > m ? k : m;
   }
-  bv[threadIdx.x] = v;
-  bi[threadIdx.x] = idx;
-  __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      const float v2 = bv[threadIdx.x + o];
-      const int64_t i2 = bi[threadIdx.x + o];
-      const float v1 = bv[threadIdx.x];
-      const int64_t i1 = bi[threadIdx.x];
-      bool take;
-      if (i2 < 0) take = false;
-      else if (i1 < 0) take = true;
-      else take = v2 > v1 || (v2 == v1 && i2 < i1);
-      if (take) {
-        bv[threadIdx.x] = v2;
-        bi[threadIdx.x] = i2;
-      }
-    }
-    __syncthreads();
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const uint64_t other = __shfl_xor(m, o, kWave);
+    m = other > m ? other : m;
   }
-  if (threadIdx.x == 0) *best = bi[0] < 0 ? 0 : bi[0];
+  if (lane_id() == 0 && m != 0) atomicMax(acc, (unsigned long long)m);
+}
+
+__global__ void best_final_kernel(int64_t* __restrict__ best) {
+  const uint64_t k = (uint64_t)*best;
+  *best = (int64_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
 }
 
 }  // namespace
 
 // --------------------------------------------------------------- launchers
 
-// Workspace header: [0, 1024) doubles of partial sums, then the centring
-// constant (one float) -- see the planner's header size.
+// Series header: 1024 doubles of partial sums, then the centring constant.
 hipError_t launch_mean(const float* x, int64_t n, void* ws, hipStream_t st) {
   double* part = reinterpret_cast<double*>(ws);
   float* c = reinterpret_cast<float*>(part + kMeanBlocks);
@@ -685,20 +730,18 @@ hipError_t launch_mean(const float* x, int64_t n, void* ws, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws,
-                       int64_t out_off, int center, hipStream_t st) {
+hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws, int64_t out_off,
+                       int center, hipStream_t st) {
   const int tpb = 256;
   const int64_t blocks = (n + tpb - 1) / tpb;
   if (is_int) {
     int32_t* out = reinterpret_cast<int32_t*>(ws) + out_off;
-    prep_u8_kernel<<<blocks, tpb, 0, st>>>(
-        reinterpret_cast<const uint8_t*>(series), n, out);
+    prep_u8_kernel<<<blocks, tpb, 0, st>>>(reinterpret_cast<const uint8_t*>(series), n, out);
   } else {
-    const float* c = reinterpret_cast<const float*>(
-        reinterpret_cast<const double*>(ws) + kMeanBlocks);
+    const float* c = reinterpret_cast<const float*>(reinterpret_cast<const double*>(ws) + kMeanBlocks);
     float* out = reinterpret_cast<float*>(ws) + out_off;
-    prep_f32_kernel<<<blocks, tpb, 0, st>>>(
-        reinterpret_cast<const float*>(series), n, c, center, out);
+    prep_f32_kernel<<<blocks, tpb, 0, st>>>(reinterpret_cast<const float*>(series), n, c, center,
+                                            out);
   }
   return hipGetLastError();
 }
@@ -719,43 +762,79 @@ hipError_t launch_halve(void* ws, int is_int, int64_t in_off,
 }
 
 template <bool INT, int EMAX>
-hipError_t launch_pass_t(const Tile* tiles, int64_t n_tiles, int lds_bytes, void* ws, float* snr,
-                         int32_t* width, void* profiles, int64_t trial_base, int mode,
-                         const int32_t* wtab, const double* sqrtw, SelectKnobs kn, hipStream_t st) {
-  static const hipError_t attr =
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&ffa_pass_kernel<INT, EMAX>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-  if (attr != hipSuccess) return attr;
-  ffa_pass_kernel<INT, EMAX><<<(unsigned)n_tiles, kThreads, lds_bytes, st>>>(
-      tiles, ws, snr, width, profiles, trial_base, mode, wtab, sqrtw, kn);
+const void* tile_fn() {
+  return reinterpret_cast<const void*>(&ffa_tile_kernel<INT, EMAX>);
+}
+
+const void* pick_tile_fn(int is_int, int max_P0) {
+  if (is_int) {
+    if (max_P0 <= 512) return tile_fn<true, 8>();
+    if (max_P0 <= 1024) return tile_fn<true, 16>();
+    return tile_fn<true, 32>();
+  }
+  if (max_P0 <= 512) return tile_fn<false, 8>();
+  if (max_P0 <= 1024) return tile_fn<false, 16>();
+  return tile_fn<false, 32>();
+}
+
+bool tiles_fit(int is_int, int max_P0, int lds_bytes) {
+  // Static LDS of the variant plus the request must fit one workgroup; the
+  // answer depends on the device and the variant only, so it is cached.
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> static_lds;
+  const void* fn = pick_tile_fn(is_int, max_P0);
+  int dev = -1, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  int fixed = -1;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = static_lds.find({dev, fn});
+    if (it != static_lds.end()) {
+      fixed = it->second;
+    } else {
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+      (void)hipGetLastError();
+      hipFuncAttributes fa{};
+      if (hipFuncGetAttributes(&fa, fn) != hipSuccess) return false;
+      fixed = (int)fa.sharedSizeBytes;
+      static_lds[{dev, fn}] = fixed;
+    }
+  }
+  return lds_bytes >= 0 && (size_t)lds_bytes <= kLdsBytes && fixed + lds_bytes <= max_lds;
+}
+
+hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
+                        void* ws, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7fffffff || max_P0 > 2 * kMaxBinsMin || !tiles_fit(is_int, max_P0, lds_bytes))
+    return hipErrorInvalidValue;
+  TileArgs b = a;
+  b.select_cand = a.select_cand < 1 ? 1 : (a.select_cand > kWave ? kWave : a.select_cand);
+  const unsigned g = (unsigned)ntiles;
+#define FFA_LAUNCH(I, EM) ffa_tile_kernel<I, EM><<<g, kThreads, (unsigned)lds_bytes, st>>>(b, ws)
+  if (is_int) {
+    if (max_P0 <= 512) FFA_LAUNCH(true, 8);
+    else if (max_P0 <= 1024) FFA_LAUNCH(true, 16);
+    else FFA_LAUNCH(true, 32);
+  } else {
+    if (max_P0 <= 512) FFA_LAUNCH(false, 8);
+    else if (max_P0 <= 1024) FFA_LAUNCH(false, 16);
+    else FFA_LAUNCH(false, 32);
+  }
+#undef FFA_LAUNCH
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const Tile* tiles, int64_t n_tiles, int lds_bytes, int max_P0,
-                       int is_int, void* ws, float* snr, int32_t* width,
-                       void* profiles, int64_t trial_base, int mode,
-                       const int32_t* wtab, const double* sqrtw,
-                       int select_iters, int select_cand, hipStream_t st) {
-  const SelectKnobs kn{select_iters, select_cand < 1 ? 1 : (select_cand > kWave ? kWave : select_cand)};
-  if (n_tiles <= 0) return hipSuccess;
-  if ((size_t)lds_bytes > kLdsBytes || max_P0 > 2 * kMaxBinsMin) return hipErrorInvalidValue;
-#define FFA_LAUNCH(I, EM) \
-  launch_pass_t<I, EM>(tiles, n_tiles, lds_bytes, ws, snr, width, profiles, trial_base, mode, wtab, \
-                       sqrtw, kn, st)
-  if (is_int) {
-    if (max_P0 <= 512) return FFA_LAUNCH(true, 8);
-    if (max_P0 <= 1024) return FFA_LAUNCH(true, 16);
-    return FFA_LAUNCH(true, 32);
-  }
-  if (max_P0 <= 512) return FFA_LAUNCH(false, 8);
-  if (max_P0 <= 1024) return FFA_LAUNCH(false, 16);
-  return FFA_LAUNCH(false, 32);
-#undef FFA_LAUNCH
-}
-
-hipError_t launch_best(const float* snr, int64_t n, int64_t* best,
-                       hipStream_t st) {
-  best_kernel<<<1, 1024, 0, st>>>(snr, n, best);
+hipError_t launch_best(const float* snr, int64_t n, int64_t* best, hipStream_t st) {
+  if (n < 1 || n > 0xffffffffll) return hipErrorInvalidValue;
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(best);
+  const int tpb = 256;
+  const int64_t blocks = std::min<int64_t>((n + tpb * 8 - 1) / (tpb * 8), 2048);
+  best_init_kernel<<<1, 1, 0, st>>>(acc);
+  best_max_kernel<<<(unsigned)blocks, tpb, 0, st>>>(snr, n, acc);
+  best_final_kernel<<<1, 1, 0, st>>>(best);
   return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-// Search planning: steps, pass split, work tiles, workspace layout.
+// Search planning: steps, pass split, work-queue phases, workspace layout.
 //
 // A plan is built on the host only; its device tables are uploaded on first
 // use on a GPU (device_tables), so plans can be made and inspected without a
@@ -15,6 +15,9 @@ namespace ffa {
 namespace {
 
 thread_local std::string g_last_error;
+
+// Largest intermediate ring of a plan (bytes); the launches shrink to fit it.
+constexpr int64_t kRingBudget = int64_t(2048) << 20;
 
 int32_t next_pow2(int64_t m) {
   int32_t M = 1;
@@ -54,7 +57,6 @@ void step_widths(const std::vector<int32_t>& user, int32_t P0,
 // min(2^(d-1), P0) bins for the shifted butterfly reads; the last pass also
 // needs P0 + wmax + 1 entries for the boxcar prefix sums.
 int32_t halo_of(int32_t P0, int32_t d) { return std::min<int32_t>(int32_t(1) << (d - 1), P0); }
-constexpr int32_t kMaxHalo = 1 << 30;  // no limit on the halo
 int32_t stride_of(const Step& s, int32_t d, bool last) {
   const int32_t h = halo_of(s.P0, d);
   return s.P0 + std::max<int32_t>(h, last ? s.wmax + 1 : 0);
@@ -63,11 +65,9 @@ int64_t lds_of(const Step& s, int32_t d, bool last) {
   return (int64_t(1) << d) * stride_of(s, d, last) * 4 + (last ? (int64_t)kScratchBytes : 0);
 }
 
-void split_passes(Step* s) {
+void split_passes(Step* s, int64_t lds_budget) {
   int32_t dfin = 1, dmid = 1;
-  auto fits = [&](int32_t d, bool last) {
-    return lds_of(*s, d, last) <= (int64_t)kLdsBytes && (halo_of(s->P0, d) <= kMaxHalo || s->P0 <= kMaxHalo);
-  };
+  auto fits = [&](int32_t d, bool last) { return lds_of(*s, d, last) <= lds_budget; };
   while (dfin < 24 && fits(dfin + 1, true)) ++dfin;
   while (dmid < 24 && fits(dmid + 1, false)) ++dmid;
   if (s->L <= dfin) {
@@ -82,59 +82,90 @@ void split_passes(Step* s) {
   s->n_passes = np + 1;
 }
 
-size_t chunk_budget_elems() {
-  int64_t mb = 128;
-  if (const char* e = std::getenv("FFA_CHUNK_MB")) {
-    const long v = std::strtol(e, nullptr, 10);
-    if (v > 0 && v < (1 << 20)) mb = v;
+int64_t env_int(const char* name, int64_t def, int64_t lo, int64_t hi) {
+  if (const char* e = std::getenv(name)) {
+    const long long v = std::strtoll(e, nullptr, 10);
+    if (v >= lo && v <= hi) return v;
   }
-  return (size_t)mb * 1024 * 1024 / 4;
+  return def;
 }
 
-// Every tile's reads and writes must stay inside the buffers of its step:
-// the octave series (first pass), the step's intermediate buffers, its own
-// trial range, and the LDS of one workgroup.  Checked once per plan, before
-// anything can be launched.
-bool tiles_in_bounds(const ffa_plan_s* p) {
-  const int64_t inter_end = p->inter_off + p->inter_elems;
-  for (const Step& s : p->steps) {
-    const int64_t MP = (int64_t)s.M * s.P0;
-    if (s.n_passes >= 2 && (s.buf_off[0] < p->inter_off || s.buf_off[0] + MP > inter_end)) return false;
-    if (s.n_passes >= 3 && (s.buf_off[1] < s.buf_off[0] + MP || s.buf_off[1] + MP > inter_end)) return false;
+// Every tile a phase can produce must read and write inside its buffers (the
+// octave series, its step's two intermediate buffers in a ring slot, its own
+// trials, one workgroup's LDS), and every tile it reads must come from an
+// earlier launch.  Checked once per plan, before anything can be launched.
+bool phases_valid(const ffa_plan_s* p) {
+  const size_t ns = p->steps.size();
+  std::vector<int32_t> first_win(ns, -1), last_win(ns, -1);
+  std::vector<int32_t> pass_win(ns * kMaxPasses, -1);
+  int64_t expect = 0;
+  int32_t prev_launch = 0;
+  for (size_t i = 0; i < p->phases.size(); ++i) {
+    const Phase& ph = p->phases[i];
+    if (ph.tile0 != expect || ph.ntiles < 1) return false;
+    expect += ph.ntiles;
+    if (ph.step < 0 || ph.step >= (int32_t)ns) return false;
+    if (ph.launch < prev_launch || ph.launch >= (int32_t)p->launches.size()) return false;
+    prev_launch = ph.launch;
+    const Launch& w = p->launches[(size_t)ph.launch];
+    if (ph.tile0 < w.tile0 || ph.tile0 + ph.ntiles > w.tile0 + w.ntiles) return false;
+    const Step& s = p->steps[ph.step];
+    const int32_t dp = ph.depth;
+    if (ph.pass < 0 || ph.pass >= s.n_passes || dp != s.depth[ph.pass] || dp < 1 || dp > 24) return false;
     int32_t D = 0;
-    for (int32_t pass = 0; pass < s.n_passes; ++pass) {
-      const int32_t dp = s.depth[pass];
-      const bool last = pass == s.n_passes - 1;
-      if (dp < 1 || dp > 24) return false;
-      for (int64_t ti = s.tile_begin[pass]; ti < s.tile_end[pass]; ++ti) {
-        const Tile& t = p->tiles[ti];
-        const int64_t rows = int64_t(1) << dp;
-        if (t.P0 != s.P0 || t.depth != dp || t.valid < 1 || t.valid > rows) return false;
-        if (t.halo < 1 || t.halo > s.P0 || t.halo < std::min<int64_t>(rows / 2, s.P0)) return false;
-        if (t.halo > kMaxHalo && s.P0 > kMaxHalo) return false;
-        if (t.stride < s.P0 + t.halo || t.stride < s.P0 + (last ? s.wmax + 1 : 0)) return false;
-        if (rows * t.stride * 4 + (last ? (int64_t)kScratchBytes : 0) > (int64_t)kLdsBytes) return false;
-        if (t.nw != s.nw || t.wofs != s.wofs) return false;
-        int64_t lo, hi;
-        if (pass == 0) {
-          lo = p->oct_off[s.octave];
-          hi = lo + (int64_t)s.m * s.P0;
-        } else {
-          lo = s.buf_off[(pass - 1) % 2];
-          hi = lo + MP;
-        }
-        if (t.src < lo || t.src + (int64_t)t.valid * s.P0 > hi) return false;
-        if (!last) {
-          const int64_t b = s.buf_off[pass % 2];
-          if (t.final_ || t.dst < b || t.dst + (rows - 1) * (int64_t)t.dst_step + s.P0 > b + MP) return false;
-          if (t.dst_step < s.P0) return false;
-        } else {
-          if (!t.final_ || t.dst < s.first_trial || t.dst + rows > s.first_trial + s.M) return false;
-        }
+    for (int32_t j = 0; j < ph.pass; ++j) D += s.depth[j];
+    const bool last = ph.pass == s.n_passes - 1;
+    if (ph.D != D || ph.last != (int32_t)last || ph.P0 != s.P0 || ph.M != s.M) return false;
+    const int64_t R = int64_t(1) << dp;
+    const int64_t Q = int64_t(1) << D;
+    const int64_t MP = (int64_t)s.M * s.P0;
+    if ((int64_t)ph.ntiles != Q * ph.ng || ph.ng < 1 || ph.vin < 1) return false;
+    if (ph.halo < std::min<int64_t>(R / 2, s.P0) || ph.halo > s.P0) return false;
+    if (ph.stride < s.P0 + ph.halo || (last && ph.stride < s.P0 + s.wmax + 1)) return false;
+    const int64_t lds = R * ph.stride * 4 + (last ? (int64_t)kScratchBytes : 0);
+    if (lds > (int64_t)kLdsBytes || lds > w.lds_bytes || ph.P0 > w.max_P0) return false;
+    if (ph.wofs != s.wofs || ph.nw != s.nw || (last && s.nw < 1)) return false;
+    if (s.n_passes > 1 && MP * (s.n_passes > 2 ? 2 : 1) > p->slot_elems) return false;
+    const int64_t Gin = (int64_t)s.M >> D;
+    for (int64_t k = 0; k < ph.ntiles; ++k) {
+      if (p->tile_phase[(size_t)(ph.tile0 + k)] != (int32_t)i) return false;
+      const int64_t q = k / ph.ng, h = k % ph.ng;
+      const int64_t valid = std::min<int64_t>(R, ph.vin - (h << dp));
+      if (valid < 1) return false;
+      const int64_t src = (q * Gin + (h << dp)) * s.P0;  // relative to the input buffer
+      if (ph.pass == 0) {
+        if (ph.oct_off != p->oct_off[s.octave]) return false;
+        if (src < 0 || src + valid * s.P0 > (int64_t)s.m * s.P0) return false;
+        if (ph.oct_off + (int64_t)s.m * s.P0 > p->series_elems) return false;
+      } else if (src < 0 || src + valid * s.P0 > MP) {
+        return false;
       }
-      D += dp;
+      if (!last) {
+        const int64_t Gout = Gin >> dp;
+        const int64_t dst = ((q << dp) * Gout + h) * s.P0;
+        if (Gout < 1 || dst < 0 || dst + (R - 1) * Gout * s.P0 + s.P0 > MP) return false;
+      } else if ((q << dp) + R > s.M) {
+        return false;
+      }
     }
-    if (D != s.L) return false;
+    // the previous pass of the step ran in an earlier launch
+    if (ph.pass > 0 && !(pass_win[(size_t)ph.step * kMaxPasses + ph.pass - 1] >= 0 &&
+                         pass_win[(size_t)ph.step * kMaxPasses + ph.pass - 1] < ph.launch))
+      return false;
+    pass_win[(size_t)ph.step * kMaxPasses + ph.pass] = ph.launch;
+    if (ph.pass == 0) first_win[(size_t)ph.step] = ph.launch;
+    if (last) last_win[(size_t)ph.step] = ph.launch;
+  }
+  if (expect != p->n_tiles || (int64_t)p->tile_phase.size() != p->n_tiles) return false;
+  // ring: a multi-pass step starts after the previous multi-pass user of its
+  // slot has finished
+  std::vector<int32_t> slot_last(std::max<int32_t>(p->n_slots, 1), -1);
+  for (size_t si = 0; si < ns; ++si) {
+    if (first_win[si] < 0 || last_win[si] < 0) return false;
+    if (p->steps[si].n_passes < 2) continue;
+    int32_t& prev = slot_last[si % (size_t)p->n_slots];
+    if (prev >= 0 && last_win[(size_t)prev] >= first_win[si]) return false;
+    prev = (int32_t)si;
   }
   return true;
 }
@@ -169,18 +200,30 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
                                          std::to_string(prop.sharedMemPerBlock) + " B)");
   DeviceTables t;
   t.device = dev;
-  const size_t tb = p->tiles.size() * sizeof(Tile);
+  const size_t pb = p->phases.size() * sizeof(Phase);
+  const size_t fb = p->fold_phases.size() * sizeof(Phase);
+  const size_t tb = p->tile_phase.size() * sizeof(int32_t);
   const size_t wb = std::max<size_t>(p->wtab.size(), 1) * sizeof(int32_t);
   const size_t sb = std::max<size_t>(p->sqrtw.size(), 1) * sizeof(double);
-  if (hipMalloc(&t.tiles, std::max<size_t>(tb, 64)) != hipSuccess ||
-      hipMalloc(&t.widths, wb) != hipSuccess || hipMalloc(&t.sqrtw, sb) != hipSuccess) {
-    if (t.tiles) (void)hipFree(t.tiles);
+  auto free_all = [&] {
+    if (t.phases) (void)hipFree(t.phases);
+    if (t.fold_phases) (void)hipFree(t.fold_phases);
+    if (t.tile_phase) (void)hipFree(t.tile_phase);
     if (t.widths) (void)hipFree(t.widths);
     if (t.sqrtw) (void)hipFree(t.sqrtw);
+  };
+  if (hipMalloc(&t.phases, pb) != hipSuccess || hipMalloc(&t.fold_phases, fb) != hipSuccess ||
+      hipMalloc(&t.tile_phase, tb) != hipSuccess || hipMalloc(&t.widths, wb) != hipSuccess || hipMalloc(&t.sqrtw, sb) != hipSuccess) {
+    free_all();
     return fail(FFA_ERR_NOMEM, "device tables: hipMalloc failed");
   }
-  ffa_status st = FFA_OK;
-  if (tb) st = check_hip(hipMemcpy(t.tiles, p->tiles.data(), tb, hipMemcpyHostToDevice), "upload tiles");
+  ffa_status st = check_hip(hipMemcpy(t.phases, p->phases.data(), pb, hipMemcpyHostToDevice), "upload phases");
+  if (st == FFA_OK)
+    st = check_hip(hipMemcpy(t.fold_phases, p->fold_phases.data(), fb, hipMemcpyHostToDevice),
+                   "upload fold phases");
+  if (st == FFA_OK)
+    st = check_hip(hipMemcpy(t.tile_phase, p->tile_phase.data(), tb, hipMemcpyHostToDevice),
+                   "upload tile map");
   if (st == FFA_OK && !p->wtab.empty())
     st = check_hip(hipMemcpy(t.widths, p->wtab.data(), p->wtab.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice), "upload widths");
@@ -188,9 +231,7 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
     st = check_hip(hipMemcpy(t.sqrtw, p->sqrtw.data(), p->sqrtw.size() * sizeof(double),
                              hipMemcpyHostToDevice), "upload sqrt widths");
   if (st != FFA_OK) {
-    (void)hipFree(t.tiles);
-    (void)hipFree(t.widths);
-    (void)hipFree(t.sqrtw);
+    free_all();
     return st;
   }
   p->dev.push_back(t);
@@ -228,6 +269,10 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   p->desc = *d;
   p->user_widths.assign(d->widths, d->widths + d->n_widths);
   p->desc.widths = nullptr;
+
+  // LDS per tile: the whole workgroup LDS by default; a smaller budget gives
+  // smaller tiles (more passes) at higher occupancy.
+  const int64_t lds_budget = env_int("FFA_TILE_LDS", (int64_t)kLdsBytes, 16384, (int64_t)kLdsBytes);
 
   // --- steps (octave f = 2^o; P0 in [B, 2B) with pmin <= P0*f*tsamp < pmax)
   const int64_t B = d->bins_min;
@@ -269,7 +314,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
         p->wtab.push_back(w);
         p->sqrtw.push_back(std::sqrt((double)w));
       }
-      split_passes(&s);
+      split_passes(&s, lds_budget);
       if (s.n_passes > kMaxPasses) {
         delete p;
         return fail(FFA_ERR_UNSUPPORTED, "step needs too many passes");
@@ -284,8 +329,11 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     return fail(FFA_ERR_INVALID, "the period range holds no step");
   }
   p->n_trials = trials;
+  // 1/sqrt(width) after the sqrt(width) values (used to rank widths)
+  const int32_t nsq = (int32_t)p->sqrtw.size();
+  for (int32_t i = 0; i < nsq; ++i) p->sqrtw.push_back(1.0 / p->sqrtw[i]);
 
-  // --- workspace: header | octave series | intermediate region
+  // --- series region: header | octave series
   p->hdr_elems = 2112;  // 1024 partial sums (double) + centring constant, 8448 B
   p->n_octaves = max_oct + 1;
   int64_t cur = p->hdr_elems;
@@ -294,103 +342,143 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     p->oct_len.push_back(d->N >> o);
     cur = round_up(cur + (d->N >> o), 64);
   }
-  p->inter_off = cur;
+  p->series_elems = cur;
 
-  // --- chunks of steps whose intermediates fit the budget together
-  int64_t max_need = 0;
-  for (auto& s : p->steps) {
-    const int64_t need = (int64_t)(s.n_passes >= 2 ? 1 : 0) * s.M * s.P0 +
-                         (int64_t)(s.n_passes >= 3 ? 1 : 0) * s.M * s.P0;
-    max_need = std::max(max_need, round_up(need, 64) + 128);
-  }
-  const int64_t budget = std::max<int64_t>((int64_t)chunk_budget_elems(), max_need);
-  {
-    Chunk c{};
-    c.step_begin = 0;
-    int64_t used = 0;
-    for (int32_t si = 0; si < (int32_t)p->steps.size(); ++si) {
-      Step& s = p->steps[si];
-      const int64_t a = s.n_passes >= 2 ? round_up((int64_t)s.M * s.P0, 64) : 0;
-      const int64_t b = s.n_passes >= 3 ? round_up((int64_t)s.M * s.P0, 64) : 0;
-      if (used + a + b > budget && si > c.step_begin) {
-        c.step_end = si;
-        p->chunks.push_back(c);
-        c = Chunk{};
-        c.step_begin = si;
-        used = 0;
+  // --- phases: one per (step, pass), tiles Q * ng
+  struct Key {
+    int64_t key;
+    int32_t pass, step, cls;
+  };
+  std::vector<Key> order;
+  std::vector<Phase> nat;  // natural order: step, then pass
+  int64_t tiles_total = 0;
+  for (int32_t si = 0; si < (int32_t)p->steps.size(); ++si) {
+    Step& s = p->steps[si];
+    int32_t D = 0;
+    s.total_tiles = 0;
+    s.lds_bytes = 0;
+    s.fold_phase0 = (int32_t)nat.size();
+    for (int32_t pass = 0; pass < s.n_passes; ++pass) {
+      const int32_t dp = s.depth[pass];
+      const bool last = pass == s.n_passes - 1;
+      const int64_t vin = ((int64_t)s.m + (int64_t(1) << D) - 1) >> D;
+      const int64_t ng = (vin + (int64_t(1) << dp) - 1) >> dp;
+      const int64_t nt = (int64_t(1) << D) * ng;
+      if (nt > (int64_t(1) << 30)) {
+        delete p;
+        return fail(FFA_ERR_UNSUPPORTED, "step too large");
       }
-      s.buf_off[0] = p->inter_off + used;
-      s.buf_off[1] = p->inter_off + used + a;
-      used += a + b;
-      s.chunk = (int32_t)p->chunks.size();
-      p->inter_elems = std::max(p->inter_elems, used);
+      Phase ph{};
+      ph.oct_off = p->oct_off[s.octave];
+      ph.first_trial = s.first_trial;
+      ph.ntiles = (int32_t)nt;
+      ph.ng = (int32_t)ng;
+      ph.step = si;
+      ph.pass = pass;
+      ph.last = last ? 1 : 0;
+      ph.P0 = s.P0;
+      ph.M = s.M;
+      ph.depth = dp;
+      ph.D = D;
+      ph.vin = (int32_t)vin;
+      ph.stride = stride_of(s, dp, last);
+      ph.halo = halo_of(s.P0, dp);
+      ph.wofs = s.wofs;
+      ph.nw = s.nw;
+      ph.isqrt_ofs = nsq + s.wofs;
+      s.tiles[pass] = (int32_t)nt;
+      s.total_tiles += (int32_t)nt;
+      s.lds_bytes = std::max<int32_t>(s.lds_bytes, (int32_t)lds_of(s, dp, last));
+      nat.push_back(ph);
+      D += dp;
     }
-    c.step_end = (int32_t)p->steps.size();
-    p->chunks.push_back(c);
+    tiles_total += s.total_tiles;
+    p->max_passes = std::max(p->max_passes, s.n_passes);
+    p->lds_bytes = std::max(p->lds_bytes, s.lds_bytes);
+    p->max_P0 = std::max(p->max_P0, s.P0);
+    if (s.n_passes > 1) p->slot_elems = std::max<int64_t>(p->slot_elems, (int64_t)(s.n_passes > 2 ? 2 : 1) * s.M * s.P0);
   }
-
-  // --- tiles: chunk, then pass, then step, then problem q, then group h
-  for (auto& c : p->chunks) {
-    c.n_passes = 0;
-    c.max_P0 = 0;
-    for (int32_t si = c.step_begin; si < c.step_end; ++si) {
-      c.n_passes = std::max(c.n_passes, p->steps[si].n_passes);
-      c.max_P0 = std::max(c.max_P0, p->steps[si].P0);
+  p->n_tiles = tiles_total;
+  if (tiles_total >= (int64_t(1) << 31)) {
+    delete p;
+    return fail(FFA_ERR_UNSUPPORTED, "too many tiles in one search");
+  }
+  // Queue order: pass p of step s at key s + p*lookahead; a window is
+  // `lookahead` consecutive keys (about FFA_WINDOW_TILES tiles) and runs as
+  // one launch per occupancy class.  The previous pass of a step is then
+  // always in an earlier window.  Ring slot s mod n_slots holds step s's
+  // intermediates from its first pass (window s / lookahead) to its last (at
+  // most max_passes - 1 windows later), so n_slots = max_passes * lookahead
+  // keeps two steps of one slot from overlapping.
+  const double avg = (double)tiles_total / (double)p->steps.size();
+  const int64_t target = env_int("FFA_WINDOW_TILES", 16384, 1, 1 << 24);
+  int64_t la = std::max<int64_t>(1, (int64_t)std::ceil((double)target / avg));
+  if (p->max_passes > 1) {
+    // keep the ring within kRingBudget bytes
+    const int64_t slot_bytes = round_up(p->slot_elems, 64) * 4;
+    const int64_t budget = env_int("FFA_RING_MB", kRingBudget >> 20, 1, int64_t(1) << 20) << 20;
+    la = std::min<int64_t>(la, std::max<int64_t>(1, budget / (slot_bytes * p->max_passes)));
+  }
+  la = std::min<int64_t>(la, 4096);
+  la = env_int("FFA_LOOKAHEAD", la, 1, 4096);
+  p->lookahead = (int32_t)la;
+  p->n_slots = p->max_passes > 1 ? p->max_passes * p->lookahead : 1;
+  // occupancy class: workgroups per CU that the phase's LDS footprint allows
+  const bool split = env_int("FFA_SPLIT_OCCUPANCY", 1, 0, 1) != 0;
+  auto occ_class = [&](const Phase& ph) {
+    if (!split) return (int32_t)0;
+    const int64_t lds = lds_of(p->steps[ph.step], ph.depth, ph.last != 0);
+    return (int32_t)std::min<int64_t>(4, (int64_t)kLdsBytes / std::max<int64_t>(lds, 1));
+  };
+  for (size_t i = 0; i < nat.size(); ++i)
+    order.push_back({(int64_t)nat[i].step + (int64_t)nat[i].pass * p->lookahead, nat[i].pass,
+                     nat[i].step, occ_class(nat[i])});
+  const int64_t LA = p->lookahead;
+  std::stable_sort(order.begin(), order.end(), [LA](const Key& a, const Key& b) {
+    if (a.key / LA != b.key / LA) return a.key / LA < b.key / LA;
+    if (a.cls != b.cls) return a.cls < b.cls;
+    return a.key != b.key ? a.key < b.key : a.pass < b.pass;
+  });
+  int64_t t0 = 0, cur_win = -1;
+  int32_t cur_cls = -1;
+  p->tile_phase.reserve((size_t)tiles_total);
+  for (const Key& k : order) {
+    Phase ph = nat[p->steps[k.step].fold_phase0 + k.pass];
+    if (k.key / LA != cur_win || k.cls != cur_cls) {
+      p->launches.push_back(Launch{t0, 0, 0, 0});
+      cur_win = k.key / LA;
+      cur_cls = k.cls;
     }
-    for (int32_t pass = 0; pass < c.n_passes; ++pass) {
-      c.tile_begin[pass] = (int64_t)p->tiles.size();
-      c.lds_bytes[pass] = 0;
-      for (int32_t si = c.step_begin; si < c.step_end; ++si) {
-        Step& s = p->steps[si];
-        if (pass >= s.n_passes) continue;
-        s.tile_begin[pass] = (int64_t)p->tiles.size();
-        int32_t D = 0;
-        for (int32_t i = 0; i < pass; ++i) D += s.depth[i];
-        const int32_t dp = s.depth[pass];
-        const int64_t Q = int64_t(1) << D;
-        const int64_t Gin = (int64_t)s.M >> D;
-        const int64_t vin = ((int64_t)s.m + (int64_t(1) << D) - 1) >> D;
-        const int64_t ng = (vin + (int64_t(1) << dp) - 1) >> dp;
-        const bool last = pass == s.n_passes - 1;
-        const int64_t src_base = pass == 0 ? p->oct_off[s.octave] : s.buf_off[(pass - 1) % 2];
-        const int32_t stride = stride_of(s, dp, last);
-        s.lds_bytes[pass] = (int32_t)lds_of(s, dp, last);
-        c.lds_bytes[pass] = std::max(c.lds_bytes[pass], s.lds_bytes[pass]);
-        for (int64_t q = 0; q < Q; ++q) {
-          for (int64_t h = 0; h < ng; ++h) {
-            Tile t{};
-            t.P0 = s.P0;
-            t.depth = dp;
-            t.src = src_base + (q * Gin + (h << dp)) * s.P0;
-            t.valid = (int32_t)std::min<int64_t>(int64_t(1) << dp, vin - (h << dp));
-            t.stride = stride;
-            t.halo = halo_of(s.P0, dp);
-            t.wofs = s.wofs;
-            t.nw = s.nw;
-            t.step = si;
-            if (!last) {
-              const int64_t Gout = Gin >> dp;
-              t.dst = s.buf_off[pass % 2] + ((q << dp) * Gout + h) * s.P0;
-              t.dst_step = (int32_t)(Gout * s.P0);
-              t.h = (int32_t)h;
-              t.final_ = 0;
-            } else {
-              t.dst = s.first_trial + (q << dp);
-              t.final_ = 1;
-            }
-            p->tiles.push_back(t);
-          }
-        }
-        s.tile_end[pass] = (int64_t)p->tiles.size();
-      }
-      c.tile_end[pass] = (int64_t)p->tiles.size();
+    Launch& ln = p->launches.back();
+    ph.launch = (int32_t)(p->launches.size() - 1);
+    ph.tile0 = t0;
+    ln.ntiles += ph.ntiles;
+    ln.lds_bytes = std::max<int32_t>(ln.lds_bytes, (int32_t)lds_of(p->steps[ph.step], ph.depth, ph.last != 0));
+    ln.max_P0 = std::max(ln.max_P0, ph.P0);
+    const int32_t idx = (int32_t)p->phases.size();
+    for (int32_t j = 0; j < ph.ntiles; ++j) p->tile_phase.push_back(idx);
+    t0 += ph.ntiles;
+    p->phases.push_back(ph);
+  }
+  // fold order: each step's passes in order, tiles counted from the step's start
+  for (const Step& s : p->steps) {
+    int64_t f0 = 0;
+    for (int32_t pass = 0; pass < s.n_passes; ++pass) {
+      Phase ph = nat[s.fold_phase0 + pass];
+      ph.tile0 = f0;
+      ph.launch = pass;
+      f0 += ph.ntiles;
+      p->fold_phases.push_back(ph);
     }
   }
-  p->ws_bytes = (size_t)round_up((p->inter_off + p->inter_elems) * 4, (int64_t)kWsAlign);
+  // workspace: series region, then the ring
+  p->ring_off = round_up(p->series_elems, 64);
+  p->slot_elems = round_up(p->slot_elems, 64);
+  p->ws_bytes = (size_t)round_up((p->ring_off + (int64_t)p->n_slots * p->slot_elems) * 4, (int64_t)kWsAlign);
   // test knobs: force the selection's fallback paths
   if (const char* e = std::getenv("FFA_SELECT_ITERS")) p->select_iters = std::max(0, std::atoi(e));
   if (const char* e = std::getenv("FFA_SELECT_CAND")) p->select_cand = std::min(64, std::max(1, std::atoi(e)));
-  if (!tiles_in_bounds(p)) {
+  if (!phases_valid(p)) {
     delete p;
     return fail(FFA_ERR_INVALID, "internal planning error: a tile reaches outside its buffers");
   }
@@ -404,7 +492,9 @@ extern "C" ffa_status ffa_plan_destroy(ffa_plan p) {
   (void)hipGetDevice(&cur);
   for (auto& t : p->dev) {
     if (t.device != cur) (void)hipSetDevice(t.device);
-    (void)hipFree(t.tiles);
+    (void)hipFree(t.phases);
+    (void)hipFree(t.fold_phases);
+    (void)hipFree(t.tile_phase);
     (void)hipFree(t.widths);
     (void)hipFree(t.sqrtw);
     if (t.device != cur && cur >= 0) (void)hipSetDevice(cur);
@@ -453,4 +543,37 @@ extern "C" ffa_status ffa_plan_periods(ffa_plan p, double* out) {
       out[s.first_trial + k] = scale * ((double)s.P0 + (double)k / (double)(s.M - 1));
   }
   return FFA_OK;
+}
+
+// Test hooks (not in the public header): the plan's queue-ordered phases and
+// its workspace layout and launches, so host tests can check the kernel's
+// index arithmetic against the buffers without a GPU.
+extern "C" int64_t ffa_debug_phases(ffa_plan p, void* out, int64_t cap) {
+  if (!p) return -1;
+  const int64_t n = (int64_t)p->phases.size();
+  if (out && cap >= n) std::memcpy(out, p->phases.data(), (size_t)n * sizeof(Phase));
+  return n;
+}
+
+extern "C" int64_t ffa_debug_layout(ffa_plan p, int64_t* out, int64_t cap) {
+  if (!p) return -1;
+  const int64_t nw = (int64_t)p->launches.size();
+  const int64_t need = 8 + 4 * nw;
+  if (!out || cap < need) return need;
+  out[0] = p->ring_off;
+  out[1] = p->slot_elems;
+  out[2] = p->n_slots;
+  out[3] = p->n_tiles;
+  out[4] = p->lds_bytes;
+  out[5] = p->max_P0;
+  out[6] = (int64_t)p->ws_bytes;
+  out[7] = p->lookahead;
+  for (int64_t i = 0; i < nw; ++i) {
+    const Launch& w = p->launches[(size_t)i];
+    out[8 + 4 * i] = w.tile0;
+    out[9 + 4 * i] = w.ntiles;
+    out[10 + 4 * i] = w.lds_bytes;
+    out[11 + 4 * i] = w.max_P0;
+  }
+  return need;
 }

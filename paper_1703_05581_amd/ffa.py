@@ -40,7 +40,8 @@ FFA_SNR_ALG2_OFFPULSE = 2
 # every symbol include/ffa.h declares
 EXPORTS = (
     "ffa_plan_create", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
-    "ffa_plan_periods", "ffa_search", "ffa_fold", "ffa_best", "ffa_batch_workspace",
+    "ffa_plan_periods", "ffa_prepare", "ffa_search_prepared", "ffa_search", "ffa_fold", "ffa_best",
+    "ffa_batch_workspace",
     "ffa_search_batch", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
     "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
 )
@@ -74,6 +75,8 @@ _lib.ffa_plan_step.argtypes = [_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32)
 _lib.ffa_plan_passes.argtypes = [_vp, _i32, _P(_i32), _P(_i32)]
 _lib.ffa_plan_periods.argtypes = [_vp, _P(ctypes.c_double)]
 _lib.ffa_search.argtypes = [_vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.ffa_prepare.argtypes = [_vp, _vp, _vp, _sz, _vp]
+_lib.ffa_search_prepared.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp]
 _lib.ffa_fold.argtypes = [_vp, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.ffa_best.argtypes = [_vp, _i64, _vp, _vp]
 _lib.ffa_batch_workspace.argtypes = [_i32, _P(_vp), _P(_sz)]
@@ -220,6 +223,25 @@ class Plan:
                                avail, _stream_ptr(stream)), "ffa_search")
         return snr, width
 
+    def prepare(self, series, ws, stream=None):
+        """ffa_prepare: octave series of ``series`` into ``ws`` (from workspace())."""
+        self._check_series(series)
+        base = self._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        _check(_lib.ffa_prepare(self._h, series.data_ptr(), base, avail, _stream_ptr(stream)),
+               "ffa_prepare")
+
+    def search_prepared(self, snr, width, ws, stream=None):
+        """ffa_search_prepared: every FFA pass and the scoring, on the octave
+        series the last prepare() left in ``ws``."""
+        if snr.numel() != self.n_trials or width.numel() != self.n_trials:
+            raise ValueError("outputs must hold n_trials entries")
+        base = self._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        _check(_lib.ffa_search_prepared(self._h, snr.data_ptr(), width.data_ptr(), base, avail,
+                                        _stream_ptr(stream)), "ffa_search_prepared")
+        return snr, width
+
     def fold(self, series, step: int, out=None, ws=None, stream=None):
         """Raw profiles (M, P0) of step ``step`` (f32 or exact int32)."""
         import torch
@@ -247,10 +269,46 @@ class Plan:
             raise ValueError("series must be on the GPU")
 
 
-def best(snr, stream=None) -> int:
-    """Index of the best trial of a periodogram (first on ties), computed on the GPU."""
+def best(snr, stream=None, out=None):
+    """Index of the best trial of a periodogram (first on ties), computed on the
+    GPU.  Returns it as an int, or, given ``out`` (a one-element int64 cuda
+    tensor), writes it there asynchronously and returns ``out``."""
     import torch
 
-    out = torch.empty(1, dtype=torch.int64, device=snr.device)
-    _check(_lib.ffa_best(snr.data_ptr(), snr.numel(), out.data_ptr(), _stream_ptr(stream)), "ffa_best")
-    return int(out.item())
+    res = out if out is not None else torch.empty(1, dtype=torch.int64, device=snr.device)
+    _check(_lib.ffa_best(snr.data_ptr(), snr.numel(), res.data_ptr(), _stream_ptr(stream)), "ffa_best")
+    return out if out is not None else int(res.item())
+
+
+def batch_workspace_bytes(plans) -> int:
+    arr = (_vp * len(plans))(*[p.handle for p in plans])
+    ws = _sz()
+    _check(_lib.ffa_batch_workspace(len(plans), arr, ctypes.byref(ws)), "ffa_batch_workspace")
+    return ws.value
+
+
+def search_batch(plans, series, ws=None, outs=None, stream=None):
+    """Periodograms of many series (cuda tensors), one plan each, in one
+    persistent launch.  Returns a list of (snr, width) tensors."""
+    import torch
+
+    n = len(plans)
+    if n != len(series) or n == 0:
+        raise ValueError("need one plan per series")
+    for p, x in zip(plans, series):
+        p._check_series(x)
+    dev = series[0].device
+    if outs is None:
+        outs = [(torch.empty(p.n_trials, dtype=torch.float32, device=dev),
+                 torch.empty(p.n_trials, dtype=torch.int32, device=dev)) for p in plans]
+    need = batch_workspace_bytes(plans)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    base = Plan._aligned(ws)
+    avail = ws.numel() - (base - ws.data_ptr())
+    ph = (_vp * n)(*[p.handle for p in plans])
+    sp = (_vp * n)(*[x.data_ptr() for x in series])
+    so = (_vp * n)(*[o[0].data_ptr() for o in outs])
+    wo = (_vp * n)(*[o[1].data_ptr() for o in outs])
+    _check(_lib.ffa_search_batch(n, ph, sp, so, wo, base, avail, _stream_ptr(stream)), "ffa_search_batch")
+    return outs

@@ -115,3 +115,21 @@ def test_null_arguments_rejected_before_gpu():
     assert lib.ffa_search(p.handle, 1, 2, 3, 256, 16, None) == ffa.FFA_ERR_INVALID
     assert lib.ffa_search(p.handle, 1, 2, 3, 257, p.ws_bytes, None) == ffa.FFA_ERR_INVALID
     assert lib.ffa_fold(p.handle, 1, p.n_steps, 3, 256, p.ws_bytes, None) == ffa.FFA_ERR_INVALID
+
+
+def test_batch_workspace():
+    """One workspace region per batch stream (at most 4), each the largest
+    plan's workspace; any mix of sample types; an empty batch is refused."""
+    a = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2], "u8")
+    b = ffa.Plan(200000, 1e-3, 0.5, 1.0, 500, [1, 2], "f32")
+    ws = ctypes.c_size_t()
+    lib = ffa.lib()
+    for plans, regions in (([a], 1), ([a, b], 2), ([a, b, a, b, a, b], 4)):
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+        assert lib.ffa_batch_workspace(len(plans), arr, ctypes.byref(ws)) == ffa.FFA_OK
+        region = -(-max(p.ws_bytes for p in plans) // 256) * 256
+        assert ws.value == regions * region
+    arr = (ctypes.c_void_p * 1)(a.handle)
+    assert lib.ffa_batch_workspace(0, arr, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_batch_workspace(1, None, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_search_batch(1, arr, None, None, None, None, 0, None) == ffa.FFA_ERR_INVALID

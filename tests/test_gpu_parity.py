@@ -169,13 +169,33 @@ def test_deterministic(torch_cuda, ffa):
     assert torch_cuda.equal(a[0], b[0]) and torch_cuda.equal(a[1], b[1])
 
 
+def _first_max(v):
+    """Index of the largest non-NaN value, first on ties (-0 == +0); 0 if all NaN."""
+    ok = ~np.isnan(v)
+    if not ok.any():
+        return 0
+    m = v[ok].max()
+    return int(np.nonzero(ok & (v == m))[0][0])
+
+
 def test_best(torch_cuda, ffa):
     g = np.random.default_rng(3)
-    for n in (1, 5, 1000, 300001):
+    for n in (1, 5, 1000, 300001, 1835008):
         v = g.standard_normal(n).astype(np.float32)
         v[g.integers(0, n, size=3)] = 9.0  # ties: first wins
         t = torch_cuda.from_numpy(v).cuda()
-        assert ffa.best(t) == int(np.argmax(v))
+        assert ffa.best(t) == int(np.argmax(v)) == _first_max(v)
+    cases = [
+        np.array([np.nan, 1.0, np.nan, 1.0], np.float32),
+        np.array([np.nan, np.nan], np.float32),
+        np.array([-0.0, 0.0, -0.0], np.float32),
+        np.array([0.0, -0.0], np.float32),
+        np.array([-np.inf, np.nan, -np.inf], np.float32),
+        np.array([-3.0, -1.0, -2.0, -1.0], np.float32),
+        np.array([np.nan] * 70000 + [5.0, np.inf, 7.0, np.inf], np.float32),
+    ]
+    for v in cases:
+        assert ffa.best(torch_cuda.from_numpy(v).cuda()) == _first_max(v), v[:8]
 
 
 @pytest.mark.parametrize("knob", [("FFA_SELECT_ITERS", "0"), ("FFA_SELECT_CAND", "1"),
@@ -194,3 +214,25 @@ def test_selection_paths(torch_cuda, ffa, oracle_mod, knob, dtype, monkeypatch):
     xs = (x // 16 * 16) if dtype == "u8" else np.round(x * 4) / 4  # many ties
     run_case(torch_cuda, ffa, oracle_mod, xs.astype(x.dtype), N, 1e-3, 0.2, 0.52, 200, W10, dtype,
              steps_max=6)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype, monkeypatch):
+    """The periodogram does not depend on how the queue is cut into launches:
+    one key per launch, three, and the default agree bit for bit."""
+    from paper_1703_05581_amd import synth
+
+    N = 300000
+    x = torch_cuda.from_numpy(synth.random_series(77, N, dtype)).cuda()
+    outs = []
+    for la in ("1", "3", None):
+        if la is None:
+            monkeypatch.delenv("FFA_LOOKAHEAD", raising=False)
+        else:
+            monkeypatch.setenv("FFA_LOOKAHEAD", la)
+        plan = ffa.Plan(N, 1e-3, 0.2, 2.0, 100, W10, dtype)
+        print("lookahead", la, flush=True)
+        outs.append([t.clone() for t in plan.search(x)])
+        torch_cuda.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch_cuda.equal(o[0], outs[0][0]) and torch_cuda.equal(o[1], outs[0][1])

@@ -1,0 +1,34 @@
+"""Host-side check of the FFA kernel's addressing and launch order (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_1703_05581_amd import ffa, synth
+from tile_emu import check
+
+
+@pytest.mark.parametrize("wl", [1, 2])
+def test_workload_plans(wl):
+    check(ffa.Plan.from_args(synth.plan_args(wl)))
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_random_plans(dtype):
+    g = np.random.default_rng(42)
+    W10 = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+    for i in range(7):
+        N = int(g.choice([20000, 65536, 150000, 300000]))
+        B = int(g.choice([64, 100, 256, 500]))
+        pmin = B * 1e-3 * float(g.uniform(1.0, 1.5))
+        pmax = pmin * float(g.uniform(2.0, 12.0))
+        check(ffa.Plan(N, 1e-3, pmin, pmax, B, None if i % 3 == 0 else W10, dtype))
+
+
+def test_three_pass_and_small_windows(monkeypatch):
+    # one key per window stresses the ring reuse and pass order checks
+    monkeypatch.setenv("FFA_LOOKAHEAD", "1")
+    p = ffa.Plan(600000, 1e-3, 1.990, 2.010, 1000, [1, 2, 4, 8])
+    assert max(len(p.passes(s)) for s in range(p.n_steps)) >= 3
+    L = check(p)
+    assert L["lookahead"] == 1
+    monkeypatch.setenv("FFA_LOOKAHEAD", "3")
+    check(ffa.Plan(300000, 1e-3, 0.2, 2.0, 100, None))
