@@ -52,7 +52,7 @@ def parse():
                     help="FFA executions the oracle times for the CPU baseline")
     ap.add_argument("--check", action="store_true", help="check sampled trials against the oracle")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--pmc-summary", metavar="DB")
+    ap.add_argument("--pmc-summary", metavar="DB", nargs="+")
     ap.add_argument("--searches", type=int, default=0,
                     help="with --pmc-summary: searches the profiled run made")
     return ap.parse_args()
@@ -97,24 +97,46 @@ def stored_traffic():
     return float(b.group(1))
 
 
-def pmc_summary(db_path: str, searches: int) -> None:
+def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def pmc_summary(db_paths, searches: int) -> None:
+    """Per-kernel counter means of rocprofv3 databases.  With FETCH_SIZE and
+    WRITE_SIZE present (each from its own run with --calibrate-copy), also the
+    FFA kernel's HBM bytes per search, each counter scaled by what it reads
+    for the 256 MiB device copy."""
     import sqlite3
 
-    db = sqlite3.connect(db_path)
-    rows = db.execute("select kernel_name, counter_name, count(*), sum(value) from counters_collection "
-                      "group by kernel_name, counter_name").fetchall()
     print(f"kernel_source_sha256_16: {source_hash()}")
     print("| kernel | counter | dispatches | mean per dispatch | total |")
     print("|---|---|---|---|---|")
-    tot = {}
-    for name, ctr, n, total in sorted(rows, key=lambda r: -r[3]):
-        short = re.sub(r"\(.*", "", name)[:60]
-        print(f"| {short} | {ctr} | {n} | {total / n:.6g} | {total:.6g} |")
-        tot[(short, ctr)] = (n, total)
-    if searches:
-        for (short, ctr), (n, total) in tot.items():
-            if "ffa_tile_kernel" in short:
-                print(f"{ctr}_KiB_per_search: {total / searches:.6g}")
+    per_search = {}
+    scale = {}
+    for path in db_paths:
+        db = sqlite3.connect(path)
+        rows = db.execute("select kernel_name, counter_name, count(*), sum(value) from counters_collection "
+                          "group by kernel_name, counter_name").fetchall()
+        for name, ctr, n, total in sorted(rows, key=lambda r: -r[3]):
+            print(f"| {_short(name)} | {ctr} | {n} | {total / n:.6g} | {total:.6g} |")
+            if "ffa_tile_kernel" in name and searches:
+                per_search[ctr] = per_search.get(ctr, 0.0) + total / searches
+        # calibration: the copies that moved COPY_BYTES
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = [v for (v,) in db.execute(
+                "select value from counters_collection where kernel_name like '%copyBuffer%' "
+                "and counter_name = ? and grid_size = ?", (ctr, COPY_BYTES // 2048))]
+            if vals:
+                scale[ctr] = (COPY_BYTES / 1024) / (sum(vals) / len(vals))
+    for ctr, v in sorted(per_search.items()):
+        unit = "_KiB" if ctr.endswith("_SIZE") else ""
+        print(f"{ctr}{unit}_per_search: {v:.6g}")
+    for ctr, f in sorted(scale.items()):
+        print(f"{ctr}_scale_from_copy: {f:.4f}")
+    if searches and "FETCH_SIZE" in per_search and "WRITE_SIZE" in per_search and len(scale) == 2:
+        t = 1024 * (per_search["FETCH_SIZE"] * scale["FETCH_SIZE"] + per_search["WRITE_SIZE"] * scale["WRITE_SIZE"])
+        print(f"traffic_bytes_per_search: {t:.6g}")
 
 
 def main():
