@@ -55,6 +55,13 @@ def parse():
     ap.add_argument("--pmc-summary", metavar="DB", nargs="+")
     ap.add_argument("--searches", type=int, default=0,
                     help="with --pmc-summary: searches the profiled run made")
+    ap.add_argument("--mode", choices=["search", "batch", "served"], default="search",
+                    help="search: the headline line (default); batch: batched against plain "
+                         "searches over workload-4 series; served: the request server under "
+                         "Poisson arrivals of workload-5 requests")
+    ap.add_argument("--series", type=int, default=32, help="batch: series in the batch")
+    ap.add_argument("--requests", type=int, default=400, help="served: timed requests")
+    ap.add_argument("--load", type=float, default=0.7, help="served: offered load / capacity")
     return ap.parse_args()
 
 
@@ -139,6 +146,127 @@ def pmc_summary(db_paths, searches: int) -> None:
         print(f"traffic_bytes_per_search: {t:.6g}")
 
 
+def trial_samples(plan) -> int:
+    return sum(plan.step(s).M * plan.step(s).m * plan.step(s).P0 for s in range(plan.n_steps))
+
+
+def run_batch(a) -> dict:
+    """Batched (ffa_search_batch over library streams) against plain
+    (ffa_search per series, one stream) on the first --series series of
+    workload 4; same outputs, checked equal."""
+    import torch
+
+    from paper_1703_05581_amd import ffa, synth
+
+    series = [synth.workload4(i) for i in range(a.series)]
+    plans = [ffa.Plan.from_args(s.plan) for s in series]
+    xs = [torch.from_numpy(s.data).cuda() for s in series]
+    outs = [(torch.empty(p.n_trials, dtype=torch.float32, device="cuda"),
+             torch.empty(p.n_trials, dtype=torch.int32, device="cuda")) for p in plans]
+    wsb = torch.empty(ffa.batch_workspace_bytes(plans) + 256, dtype=torch.uint8, device="cuda")
+    ws1 = torch.empty(max(p.ws_bytes for p in plans) + 256, dtype=torch.uint8, device="cuda")
+    ts = sum(trial_samples(p) for p in plans)
+
+    def plain():
+        for p, x, o in zip(plans, xs, outs):
+            p.search(x, o[0], o[1], ws1)
+
+    def batched():
+        ffa.search_batch(plans, xs, ws=wsb, outs=outs)
+
+    res = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / a.steps / 1e3
+        res[name + "_out"] = [(o[0].clone(), o[1].clone()) for o in outs]
+    same = all(torch.equal(x[0], y[0]) and torch.equal(x[1], y[1])
+               for x, y in zip(res["plain_out"], res["batched_out"]))
+    return {"metric": "FFA trial*samples/s, batched search (workload 4 series)",
+            "value": ts / res["batched"], "unit": "trial*samples/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": res["batched"] * 1e3, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic (seeded; workload 4 of paper_1703_05581_amd.synth)",
+            "config": {"workload": f"first {a.series} series of workload 4 (f32, 2^18..2^22 samples, "
+                                   "own period ranges)", "trial_samples": ts},
+            "plain_value": ts / res["plain"], "plain_ms": res["plain"] * 1e3,
+            "speedup": res["plain"] / res["batched"], "outputs_equal": same}
+
+
+def run_served(a) -> dict:
+    """Request server under Poisson arrivals at --load x its measured
+    capacity; latency = submit to the end of the search on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_1703_05581_amd import ffa, synth
+
+    pool = [synth.workload5(i) for i in range(16)]
+    plans = {}
+    for s in pool:
+        if s.plan.N not in plans:
+            plans[s.plan.N] = ffa.Plan.from_args(s.plan)
+    srv = ffa.Server(16 << 30, 4)
+    reqs = [pool[i % len(pool)] for i in range(a.requests + 100)]
+    # capacity: a closed burst of the same mix
+    t0 = time.perf_counter()
+    ts = [srv.submit(plans[r.plan.N], r.data) for r in reqs[:64]]
+    for t in ts:
+        srv.wait(t)
+    cap = 64 / (time.perf_counter() - t0)
+    rate = a.load * cap
+    arrivals = synth.poisson_arrivals(7, rate, len(reqs))
+    import threading
+
+    lat, done = [], []
+    tickets = []
+    lock = threading.Lock()
+
+    def collector():
+        i = 0
+        while i < len(reqs):
+            with lock:
+                have = len(tickets)
+            if i >= have:
+                time.sleep(1e-4)
+                continue
+            _, _, l = srv.wait(tickets[i])
+            if i >= 100:
+                lat.append(l)
+            done.append(time.perf_counter())
+            i += 1
+
+    th = threading.Thread(target=collector)
+    th.start()
+    start = time.perf_counter()
+    for r, at in zip(reqs, arrivals):
+        now = time.perf_counter() - start
+        if at > now:
+            time.sleep(at - now)
+        t = srv.submit(plans[r.plan.N], r.data)
+        with lock:
+            tickets.append(t)
+    th.join()
+    srv.close()
+    span = done[-1] - done[100]
+    served_ts = sum(trial_samples(plans[r.plan.N]) for r in reqs[101:])
+    lat = np.array(lat)
+    return {"metric": "FFA served requests: submit-to-result latency (workload 5)",
+            "value": float(np.percentile(lat, 50)), "unit": "s", "higher_is_better": False,
+            "n_gpus": 1, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "requests": a.requests, "warmup_requests": 100, "offered_rate_hz": rate,
+            "capacity_hz": cap, "load": a.load, "served_trial_samples_per_s": served_ts / span,
+            "dtype": "f32", "data": "synthetic (seeded; workload 5 of paper_1703_05581_amd.synth)",
+            "config": {"workload": "Poisson arrivals of f32 requests, 2^20..2^23 samples, "
+                                   "P0 256..511 at f=1,2,4; 16 GiB pool, 4 streams"}}
+
+
 def main():
     a = parse()
     if a.pmc_summary:
@@ -148,6 +276,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(no multi-GPU path is built)"}))
         sys.exit(2)
+    if a.mode != "search":
+        import torch
+
+        torch.cuda.init()
+        print(json.dumps(run_batch(a) if a.mode == "batch" else run_served(a)))
+        return
     import numpy as np
     import torch
 

@@ -174,32 +174,44 @@ ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,
                             int32_t* const* d_width, void* d_ws,
                             size_t ws_bytes, void* stream);
 
-/* Search server: continuous batching of requests that arrive over time.
- * The server keeps device buffers in a pool of at most hbm_budget_bytes,
- * admits a request when its footprint (series + workspace + periodogram)
- * fits in what is free, and runs each scheduling round as one batched
- * launch over every admitted request.  Requests arriving while a round runs
- * join the next round.  n_streams > 1 overlaps host-device copies with
- * compute.  All server calls are thread-safe. */
+/* Search server: continuous batching of requests that arrive over time
+ * (Sec. 4 searches many dedispersed series of one observation).
+ *
+ * ffa_server_create allocates one device pool of hbm_budget_bytes on the
+ * current GPU and n_streams streams (1..16, default priority).  A scheduler
+ * thread admits pending requests in arrival order whenever the head
+ * request's footprint -- series copy (host input only) + the plan's
+ * ws_bytes + the periodogram (8 B per trial) -- fits in what is free, and
+ * enqueues it on the least-loaded stream, next to the requests already
+ * running.  A request keeps its memory until it is waited on.  All server
+ * calls are thread-safe; ffa_server_destroy must not race with the others.
+ * Errors: FFA_ERR_INVALID, FFA_ERR_NOMEM (pool allocation), FFA_ERR_DEVICE. */
 ffa_status ffa_server_create(size_t hbm_budget_bytes, int32_t n_streams,
                              ffa_server* out);
 
-/* Submit a search of `series` (host memory if is_device == 0, else a device
- * pointer that must stay valid until the request completes) with `plan`.
- * The plan must outlive the request.  Returns a ticket.  Errors:
+/* Submit a search of `series` with `plan`.  Host input (is_device == 0) is
+ * copied at the call, so the caller may reuse its buffer at once; a device
+ * pointer (is_device != 0) must stay valid until the request completes.
+ * The plan must outlive the request.  Returns a ticket (> 0).  Errors:
  * FFA_ERR_INVALID, FFA_ERR_UNSUPPORTED (footprint above the whole budget),
- * FFA_ERR_BUSY (admission queue full). */
+ * FFA_ERR_BUSY (65536 requests pending), FFA_ERR_NOMEM. */
 ffa_status ffa_server_submit(ffa_server s, ffa_plan plan, const void* series,
                              int is_device, int64_t* ticket);
 
-/* Wait for a ticket (timeout_us < 0: forever).  Copies the periodogram to the
- * host arrays (n_trials entries each; either may be NULL) and reports the
- * submit-to-completion latency in seconds.  A ticket can be waited on once.
- * Errors: FFA_ERR_INVALID (unknown ticket), FFA_ERR_TIMEOUT, FFA_ERR_DEVICE
- * (the request's launch failed; other requests are unaffected). */
+/* Wait for a ticket (timeout_us < 0: forever; 0: poll).  Copies the
+ * periodogram to the host arrays (n_trials entries each; either may be NULL),
+ * releases the request's device memory, and reports its latency: submit to
+ * the end of its search on the GPU (the result copy is not included).  A
+ * ticket can be waited on once.  Errors: FFA_ERR_INVALID (unknown or already
+ * collected ticket), FFA_ERR_TIMEOUT (the request stays pending),
+ * FFA_ERR_DEVICE (the request's launch failed; other requests are
+ * unaffected). */
 ffa_status ffa_server_wait(ffa_server s, int64_t ticket, int64_t timeout_us,
                            float* host_snr, int32_t* host_width,
                            double* latency_s);
+
+/* Stops admitting, lets the running requests finish, frees the pool and the
+ * streams.  Requests not yet collected are dropped. */
 ffa_status ffa_server_destroy(ffa_server s);
 
 const char* ffa_status_str(ffa_status st);

@@ -312,3 +312,62 @@ def search_batch(plans, series, ws=None, outs=None, stream=None):
     wo = (_vp * n)(*[o[1].data_ptr() for o in outs])
     _check(_lib.ffa_search_batch(n, ph, sp, so, wo, base, avail, _stream_ptr(stream)), "ffa_search_batch")
     return outs
+
+
+class Server:
+    """Continuous-batching search server (ffa_server_*): one HBM pool of
+    ``hbm_budget_bytes`` on the current GPU and ``n_streams`` streams."""
+
+    def __init__(self, hbm_budget_bytes: int, n_streams: int = 4):
+        h = _vp()
+        _check(_lib.ffa_server_create(ctypes.c_size_t(hbm_budget_bytes), n_streams, ctypes.byref(h)),
+               "ffa_server_create")
+        self._h = h.value
+        self._plans = {}
+
+    def submit(self, plan: Plan, series) -> int:
+        """Queue a search of ``series``: a numpy array (copied now) or a cuda
+        tensor (read when the request runs).  Returns the ticket."""
+        import numpy as np
+
+        want = np.uint8 if plan.dtype == "u8" else np.float32
+        t = _i64()
+        if isinstance(series, np.ndarray):
+            if series.dtype != want or series.size != plan.N:
+                raise ValueError(f"series must hold {plan.N} {np.dtype(want).name} samples")
+            arr = np.ascontiguousarray(series)
+            st = _lib.ffa_server_submit(self._h, plan.handle, arr.ctypes.data, 0, ctypes.byref(t))
+        else:
+            plan._check_series(series)
+            st = _lib.ffa_server_submit(self._h, plan.handle, series.data_ptr(), 1, ctypes.byref(t))
+        _check(st, "ffa_server_submit")
+        self._plans[t.value] = (plan, series)  # keep both alive until the wait
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float | None = None):
+        """Block until ``ticket`` is done.  Returns (snr, width, latency_s) as
+        numpy arrays and seconds.  Raises FFAError(FFA_ERR_TIMEOUT) on time-out."""
+        import numpy as np
+
+        plan, _ = self._plans[ticket]
+        snr = np.empty(plan.n_trials, np.float32)
+        wid = np.empty(plan.n_trials, np.int32)
+        lat = ctypes.c_double()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        st = _lib.ffa_server_wait(self._h, ticket, us, snr.ctypes.data, wid.ctypes.data, ctypes.byref(lat))
+        if st != FFA_ERR_TIMEOUT:
+            self._plans.pop(ticket, None)
+        _check(st, "ffa_server_wait")
+        return snr, wid, lat.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.ffa_server_destroy(self._h)
+            self._h = None
+            self._plans.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

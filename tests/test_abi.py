@@ -133,3 +133,17 @@ def test_batch_workspace():
     assert lib.ffa_batch_workspace(0, arr, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
     assert lib.ffa_batch_workspace(1, None, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
     assert lib.ffa_search_batch(1, arr, None, None, None, None, 0, None) == ffa.FFA_ERR_INVALID
+
+
+def test_server_argument_errors_before_gpu():
+    """Bad server arguments are refused on the host, before any device call."""
+    lib = ffa.lib()
+    h = ctypes.c_void_p()
+    assert lib.ffa_server_create(1 << 30, 4, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(1 << 30, 0, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(1 << 30, 17, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(100, 2, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    t = ctypes.c_int64()
+    assert lib.ffa_server_submit(None, None, None, 0, ctypes.byref(t)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_wait(None, 1, 0, None, None, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_destroy(None) == ffa.FFA_ERR_INVALID
