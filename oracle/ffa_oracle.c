@@ -25,9 +25,12 @@
  *
  * Parity status: plan, downsampling, fold and Alg. 1 are pinned by the
  * `-m "not gpu"` tests (worked example, closed forms, invariants, library
- * routines, impulse response, injected-pulse recovery).  Alg. 2's exclusion
- * window placement and its ddof are readings with no printed example:
- * "parity unpinned" beyond the checks of its limiting cases.
+ * routines, impulse response, injected-pulse recovery).  Alg. 2 is pinned to
+ * its stated readings (window of round(P0/5) boxcar positions starting
+ * floor(n_ex/2) before the first maximum, wrapping; population sigma) by
+ * hand-worked examples, invariances and the top-hat S/N level; the paper
+ * prints no example that fixes those readings, so against the paper itself
+ * Alg. 2 is "parity unpinned".
  */
 #include <math.h>
 #include <stdint.h>

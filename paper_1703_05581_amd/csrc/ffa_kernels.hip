@@ -22,6 +22,12 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Index of this wave in its workgroup, as a wave-uniform (scalar) value: the
+// per-wave loops and their index arithmetic then run on the scalar unit.
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
 // Position of partial t after d in-place levels: its d-bit reversal.
 __device__ __forceinline__ int bitrev(int t, int d) {
   return d == 0 ? 0 : (int)(__brev((unsigned)t) >> (32 - d));
@@ -132,7 +138,7 @@ constexpr uint32_t kPadKey = 0xffffffffu;  // above every real key
 template <typename T>
 __device__ __forceinline__ void butterfly(T* lds, int S, int P0, int H, int d) {
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int nwaves = blockDim.x / kWave;
   const int R = 1 << d;
   for (int l = 1; l <= d; ++l) {
@@ -530,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void ffa_tile_kernel(TileArgs a, void* __
   T* ws = reinterpret_cast<T*>(ws_raw);
   const SelectKnobs kn{a.select_iters, a.select_cand};
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int nwaves = blockDim.x / kWave;
 
   const int64_t t = a.tile0 + blockIdx.x;

@@ -65,7 +65,7 @@ int64_t lds_of(const Step& s, int32_t d, bool last) {
   return (int64_t(1) << d) * stride_of(s, d, last) * 4 + (last ? (int64_t)kScratchBytes : 0);
 }
 
-void split_passes(Step* s, int64_t lds_budget) {
+void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
   int32_t dfin = 1, dmid = 1;
   auto fits = [&](int32_t d, bool last) { return lds_of(*s, d, last) <= lds_budget; };
   while (dfin < 24 && fits(dfin + 1, true)) ++dfin;
@@ -75,11 +75,50 @@ void split_passes(Step* s, int64_t lds_budget) {
     s->depth[0] = s->L;
     return;
   }
-  const int32_t rest = s->L - dfin;
-  const int32_t np = (rest + dmid - 1) / dmid;
-  for (int32_t i = 0; i < np; ++i) s->depth[i] = rest / np + (i < rest % np ? 1 : 0);
-  s->depth[np] = dfin;
-  s->n_passes = np + 1;
+  if (mode == 0) {  // deepest last pass, the rest shared by the earlier ones
+    const int32_t rest = s->L - dfin;
+    const int32_t np = (rest + dmid - 1) / dmid;
+    for (int32_t i = 0; i < np; ++i) s->depth[i] = rest / np + (i < rest % np ? 1 : 0);
+    s->depth[np] = dfin;
+    s->n_passes = np + 1;
+    return;
+  }
+  // fewest passes, depths as equal as the LDS allows (mode 1: deeper passes
+  // first, mode 2: deeper passes last)
+  int32_t np = 2;
+  for (;; ++np) {
+    int32_t left = s->L, ok = 1;
+    for (int32_t i = np - 1; i >= 0; --i) {
+      const int32_t cap = i == np - 1 ? dfin : dmid;
+      const int32_t d = std::min(cap, left - i);  // leave >= 1 level per earlier pass
+      if (d < 1) ok = 0;
+      left -= d;
+    }
+    if (ok && left <= 0) break;
+  }
+  int32_t dep[kMaxPasses + 8];
+  for (int32_t i = 0; i < np; ++i) dep[i] = s->L / np + (i < s->L % np ? 1 : 0);
+  if (mode == 2) std::reverse(dep, dep + np);
+  // respect the caps: move levels from a pass above its cap to others
+  for (int iter = 0; iter < 64; ++iter) {
+    bool moved = false;
+    for (int32_t i = 0; i < np; ++i) {
+      const int32_t cap = i == np - 1 ? dfin : dmid;
+      if (dep[i] <= cap) continue;
+      for (int32_t j = 0; j < np; ++j) {
+        const int32_t cj = j == np - 1 ? dfin : dmid;
+        if (j != i && dep[j] < cj) {
+          --dep[i];
+          ++dep[j];
+          moved = true;
+          break;
+        }
+      }
+    }
+    if (!moved) break;
+  }
+  for (int32_t i = 0; i < np; ++i) s->depth[i] = dep[i];
+  s->n_passes = np;
 }
 
 int64_t env_int(const char* name, int64_t def, int64_t lo, int64_t hi) {
@@ -273,6 +312,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   // LDS per tile: the whole workgroup LDS by default; a smaller budget gives
   // smaller tiles (more passes) at higher occupancy.
   const int64_t lds_budget = env_int("FFA_TILE_LDS", (int64_t)kLdsBytes, 16384, (int64_t)kLdsBytes);
+  const int32_t split_mode = (int32_t)env_int("FFA_SPLIT_MODE", 1, 0, 2);
 
   // --- steps (octave f = 2^o; P0 in [B, 2B) with pmin <= P0*f*tsamp < pmax)
   const int64_t B = d->bins_min;
@@ -314,7 +354,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
         p->wtab.push_back(w);
         p->sqrtw.push_back(std::sqrt((double)w));
       }
-      split_passes(&s, lds_budget);
+      split_passes(&s, lds_budget, split_mode);
       if (s.n_passes > kMaxPasses) {
         delete p;
         return fail(FFA_ERR_UNSUPPORTED, "step needs too many passes");

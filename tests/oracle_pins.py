@@ -246,6 +246,63 @@ def pin_default_widths(o):
     assert o.default_widths(5) == [1, 2]
 
 
+# --------------------------------------------------------------- Alg. 2
+
+def pin_alg2_worked_examples(o):
+    """Hand-worked Algorithm 2 profiles (Sec. 2.2.2, Eq. 5) that fix the
+    window placement, its wrap-around, its rounding and the population
+    sigma of the stated readings."""
+    g = _golden("alg2_worked_example.json")
+    for case in g["cases"]:
+        x = np.array(case["profile"], dtype=np.float64)
+        v, w = o.alg2(x, case["widths"])
+        assert abs(v - case["score"]) < 1e-12 and w == case["best_width"], (case["profile"], v, w)
+        for ws, expect in case["per_width"].items():
+            v1, w1 = o.alg2(x, [int(ws)])
+            assert abs(v1 - expect) < 1e-12 and w1 == int(ws), (ws, v1, expect)
+        vi, wi = o.alg2(x.astype(np.int64), case["widths"])
+        assert abs(vi - case["score"]) < 1e-12 and wi == case["best_width"]
+
+
+def pin_alg2_invariants(o):
+    """The score of Eq. 5 does not change under a positive scale, an offset or
+    a rotation of the profile (circular boxcars, window centred on the peak);
+    one width alone gives that width's term (the paper's fixed-width "Ref")."""
+    g = np.random.default_rng(21)
+    for n in (40, 255, 512):
+        x = g.standard_normal(n)
+        x[(int(g.integers(0, n)) + np.arange(6)) % n] += 3.0
+        wl = [1, 2, 4, 8, 16]
+        base = o.alg2(x, wl)
+        for y in (3.5 * x + 100.0, np.roll(x, 17), np.roll(x, n - 1)):
+            r = o.alg2(y, wl)
+            assert abs(r[0] - base[0]) < 1e-9 * abs(base[0]) and r[1] == base[1], (n, r, base)
+        terms = [o.alg2(x, [w])[0] for w in wl]
+        assert abs(max(terms) - base[0]) < 1e-12 and wl[int(np.argmax(terms))] == base[1]
+
+
+def pin_alg2_sigma_zero(o):
+    """A flat off-pulse region has sigma = 0: score 0 by the stated reading."""
+    x = np.full(30, 4.0)
+    x[12] = 50.0
+    assert o.alg2(x, [1])[0] == 0.0
+
+
+def pin_alg2_snr_level(o):
+    """A top-hat of height S and width w in unit white noise scores about
+    S*sqrt(w) (Eq. 10) with the matched width in the set, averaged over 30
+    profiles."""
+    g = np.random.default_rng(22)
+    P, w, S = 1024, 16, 2.0
+    vals = []
+    for _ in range(30):
+        x = g.standard_normal(P)
+        x[(int(g.integers(0, P)) + np.arange(w)) % P] += S
+        vals.append(o.alg2(x, [1, 2, 4, 8, 16, 32, 64])[0])
+    ratio = float(np.mean(vals)) / (S * math.sqrt(w))
+    assert 0.85 < ratio < 1.2, ratio
+
+
 # ---------------------------------------------------- plan / downsample
 
 def pin_downsample(o):
@@ -313,6 +370,10 @@ ALL_PINS = [
     pin_alg1_integer_path,
     pin_alg1_mad_zero,
     pin_alg1_snr_level,
+    pin_alg2_worked_examples,
+    pin_alg2_invariants,
+    pin_alg2_sigma_zero,
+    pin_alg2_snr_level,
     pin_default_widths,
     pin_downsample,
     pin_plan,

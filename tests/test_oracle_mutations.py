@@ -30,6 +30,12 @@ MUTATIONS = [
     ("rows_ceil", "int64_t m = Nf / P0;", "int64_t m = (Nf + P0 - 1) / P0;"),
     ("pad_one_more", "while (M < m) M <<= 1;", "while (M <= m) M <<= 1;"),
     ("default_width_rule", "if (5 * v > P0) break;", "if (5 * v >= P0) break;"),
+    ("alg2_window_late", "int32_t start = jmax - n_ex / 2;", "int32_t start = jmax - n_ex / 2 + 1;"),
+    ("alg2_sample_sigma", "double sd = sqrt(v / cnt);", "double sd = sqrt(v / (cnt - 1));"),
+    ("alg2_window_floor", "int32_t n_ex = (2 * P0 + 5) / 10;", "int32_t n_ex = P0 / 5;"),
+    ("alg2_window_no_wrap", "for (int32_t i = 0; i < n_ex; ++i) excl[((start + i) % P0 + P0) % P0] = 1;",
+     "for (int32_t i = 0; i < n_ex; ++i) if (start + i >= 0 && start + i < P0) excl[start + i] = 1;"),
+    ("alg2_last_max", "if (bx[j] > bx[jmax]) jmax = j;", "if (bx[j] >= bx[jmax]) jmax = j;"),
 ]
 
 
