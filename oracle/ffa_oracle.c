@@ -350,7 +350,10 @@ double oracle_alg1_i64(const int64_t* F, int32_t P0, const int32_t* widths,
  * Readings (the paper does not fix them): the window is placed in the
  * boxcar-output index space, covers n_ex = round(P0/5) positions starting
  * floor(n_ex/2) before the first maximum, wraps around the profile, and sigma
- * is the population standard deviation.  sigma = 0 gives score 0.
+ * is the population standard deviation.  sigma = 0 gives score 0.  A width
+ * equal to P0 makes every boxcar the whole profile: the output is constant,
+ * sigma is exactly 0 and so is the score (summing in floating point would
+ * leave only rounding noise to divide by).
  * The "Ref" variant of Sec. 2.2.2 / Sec. 2.4 is this with one width. */
 double oracle_alg2_f64(const double* F, int32_t P0, const int32_t* widths,
                        int32_t nw, int32_t* best_w) {
@@ -379,7 +382,7 @@ double oracle_alg2_f64(const double* F, int32_t P0, const int32_t* widths,
         ++cnt;
       }
     double a = 0.0;
-    if (cnt > 0) {
+    if (cnt > 0 && w < P0) {
       double mean = s / cnt;
       double v = 0.0;
       for (int32_t j = 0; j < P0; ++j)

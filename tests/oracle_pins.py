@@ -282,10 +282,16 @@ def pin_alg2_invariants(o):
 
 
 def pin_alg2_sigma_zero(o):
-    """A flat off-pulse region has sigma = 0: score 0 by the stated reading."""
+    """A flat off-pulse region has sigma = 0: score 0 by the stated reading.
+    So does a width equal to the profile length, whose boxcar output is the
+    profile total at every position, whatever the profile."""
     x = np.full(30, 4.0)
     x[12] = 50.0
     assert o.alg2(x, [1])[0] == 0.0
+    g = np.random.default_rng(23)
+    for n in (7, 32, 100):
+        y = g.standard_normal(n) * 13.7 + 0.1
+        assert o.alg2(y, [n]) == (0.0, n)
 
 
 def pin_alg2_snr_level(o):

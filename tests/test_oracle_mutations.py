@@ -36,6 +36,7 @@ MUTATIONS = [
     ("alg2_window_no_wrap", "for (int32_t i = 0; i < n_ex; ++i) excl[((start + i) % P0 + P0) % P0] = 1;",
      "for (int32_t i = 0; i < n_ex; ++i) if (start + i >= 0 && start + i < P0) excl[start + i] = 1;"),
     ("alg2_last_max", "if (bx[j] > bx[jmax]) jmax = j;", "if (bx[j] >= bx[jmax]) jmax = j;"),
+    ("alg2_full_width_noise", "if (cnt > 0 && w < P0) {", "if (cnt > 0) {"),
 ]
 
 
