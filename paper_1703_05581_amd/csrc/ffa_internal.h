@@ -74,6 +74,7 @@ struct TileArgs {
   int64_t trial_base;         // fold: trial index of output row 0
   int32_t n_slots;
   int32_t mode;
+  int32_t alg;                // profile score: 1 = Algorithm 1, 2 = Algorithm 2
   int32_t select_iters;
   int32_t select_cand;
 };
@@ -166,7 +167,7 @@ hipError_t launch_halve(void* ws, int is_int, int64_t in_off, int64_t n_out, int
                         hipStream_t st);
 // Checks that the kernel variant for max_P0 fits lds_bytes of dynamic LDS on
 // the current device (static LDS included); caches the answer.
-bool tiles_fit(int is_int, int max_P0, int lds_bytes);
+bool tiles_fit(int is_int, int max_P0, int lds_bytes, int alg);
 hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
                         void* ws, hipStream_t st);
 hipError_t launch_best(const float* snr, int64_t n, int64_t* best, hipStream_t st);

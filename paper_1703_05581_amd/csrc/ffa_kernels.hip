@@ -107,6 +107,43 @@ __device__ __forceinline__ float wave_scan(float v) {
 
 __device__ __forceinline__ int wave_count(bool p) { return __popcll(__ballot(p)); }
 
+// DPP of a 64-bit value (both halves moved the same way; masked rows give 0).
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = dpp<CTRL, ROWMASK>(0u, (uint32_t)v);
+  const uint32_t hi = dpp<CTRL, ROWMASK>(0u, (uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  return ((uint64_t)readlane((uint32_t)(v >> 32), l) << 32) | readlane((uint32_t)v, l);
+}
+
+// Sum of one value per lane over the wave (a fixed reduction tree, so the
+// result is deterministic); wave-uniform.
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+  uint64_t u = (uint64_t)v;
+  u += dpp64<kDppXor1>(u);
+  u += dpp64<kDppXor2>(u);
+  u += dpp64<kDppHalfMirror>(u);
+  u += dpp64<kDppRowMirror>(u);
+  u += dpp64<kDppBcast15, 0xA>(u);
+  u += dpp64<kDppBcast31, 0xC>(u);
+  return (int64_t)readlane64(u, 63);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  auto add = [](double a, uint64_t b) { return a + __longlong_as_double((long long)b); };
+  auto bits = [](double a) { return (uint64_t)__double_as_longlong(a); };
+  v = add(v, dpp64<kDppXor1>(bits(v)));
+  v = add(v, dpp64<kDppXor2>(bits(v)));
+  v = add(v, dpp64<kDppHalfMirror>(bits(v)));
+  v = add(v, dpp64<kDppRowMirror>(bits(v)));
+  v = add(v, dpp64<kDppBcast15, 0xA>(bits(v)));
+  v = add(v, dpp64<kDppBcast31, 0xC>(bits(v)));
+  return __longlong_as_double((long long)readlane64(bits(v), 63));
+}
+
 // Order-preserving 32-bit keys: integer sums (non-negative, < 2^31) are their
 // own keys; a finite float maps to an unsigned integer with the same order.
 __device__ __forceinline__ uint32_t fkey(float f) {
@@ -337,6 +374,146 @@ struct Types<false> {
   using A = float;
 };
 
+// Circular prefix sums of the profile in `row`, in place: afterwards row[k] =
+// C[k] = sum_{i<k} F[i mod P0] for k <= P0 + wmax, and cex[r] holds C[j] of
+// the lane's bin j = 64r + lane.  A box of width w starting at j is then
+// C[j + w] - C[j] (modular arithmetic is exact for the integer sums).
+template <int E, bool INT>
+__device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int P0, int wmax,
+                                                typename Types<INT>::A (&cex)[E]) {
+  using T = typename Types<INT>::T;
+  using A = typename Types<INT>::A;
+  const int lane = lane_id();
+  A xv[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = r * kWave + lane;
+    xv[r] = e < P0 ? (A)row[e] : (A)0;
+  }
+  wave_lds_sync();
+  A carry = (A)0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = r * kWave + lane;
+    const A s = wave_scan(xv[r]);
+    cex[r] = carry + s - xv[r];
+    if (e < P0) row[e + 1] = (T)(carry + s);
+    if constexpr (INT) carry += readlane(s, 63);
+    else carry += __uint_as_float(readlane(__float_as_uint(s), 63));
+  }
+  if (lane == 0) row[0] = (T)0;
+  wave_lds_sync();
+  const A total = carry;
+  for (int i = lane; i < wmax; i += kWave) row[P0 + 1 + i] = (T)(total + (A)row[1 + i]);
+  wave_lds_sync();
+}
+
+// Score one folded profile with Algorithm 2 (paper Sec. 2.2.2, Eq. 5): for
+// each width, the circular boxcar B_w of the raw profile, its maximum I_max at
+// the first position j*, and the mean I_av and population sigma of B_w
+// outside a window of n_ex = round(P0/5) positions starting floor(n_ex/2)
+// before j* (wrapping); score = max_w (I_max - I_av) / sigma, the first width
+// on ties, 0 when sigma = 0 (also for w = P0, where the boxcar is constant).  Integer boxes and their sum are exact; the
+// mean, the variance and the score are in double.
+template <int E, bool INT>
+__device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, int wmax,
+                                           const int32_t* widths, int nw, float* snr_out,
+                                           int32_t* width_out) {
+  using A = typename Types<INT>::A;
+  const int lane = lane_id();
+  // Up to 16 boxes per lane are held in registers; longer profiles re-read
+  // them from the prefix sums in LDS in each sweep, in a plain loop.
+  constexpr bool kRegs = E <= 16;
+  constexpr int ER = kRegs ? E : 1;
+  A cex[ER];
+  {
+    A cex_all[E];
+    circular_prefix<E, INT>(row, P0, wmax, cex_all);
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) cex[r] = cex_all[r];
+    }
+  }
+  const int n_ex = (2 * P0 + 5) / 10;
+  const int cnt = P0 - n_ex;
+  auto key_of = [](A v) -> uint32_t {
+    if constexpr (INT) return (uint32_t)v;
+    else return fkey(v);
+  };
+  auto as_double = [](A v) -> double {
+    if constexpr (INT) return (double)(uint32_t)v;
+    else return (double)v;
+  };
+  double best = 0.0;
+  int32_t bw = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int32_t w = widths[i];
+    A breg[ER];
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) breg[r] = (A)row[r * kWave + lane + w] - cex[r];
+    }
+    // f(e, box) for each bin e of this lane, ascending
+    auto visit = [&](auto&& f) {
+      if constexpr (kRegs) {
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+          if (r * kWave + lane < P0) f(r * kWave + lane, breg[r]);
+      } else {
+        for (int e = lane; e < P0; e += kWave) f(e, (A)row[e + w] - (A)row[e]);
+      }
+    };
+    // maximum and its first position
+    uint32_t mk = 0u, jf = 0xffffffffu;
+    visit([&](int e, A b) {
+      const uint32_t kv = key_of(b);
+      if (kv > mk) {
+        mk = kv;
+        jf = (uint32_t)e;
+      }
+    });
+    const uint32_t pk = wave_umax(mk);
+    const int jstar = (int)wave_umin(mk == pk ? jf : 0xffffffffu);
+    int start = jstar - n_ex / 2;
+    start += start < 0 ? P0 : 0;
+    auto kept = [&](int e) {  // (e - start) mod P0 >= n_ex
+      int dj = e - start;
+      dj += dj < 0 ? P0 : 0;
+      return dj >= n_ex;
+    };
+    double S;
+    if constexpr (INT) {
+      int64_t ss = 0;
+      visit([&](int e, A b) { ss += kept(e) ? (int64_t)(uint32_t)b : 0; });
+      S = (double)wave_sum(ss);
+    } else {
+      double ss = 0.0;
+      visit([&](int e, A b) { ss += kept(e) ? (double)b : 0.0; });
+      S = wave_sum(ss);
+    }
+    const double mean = S / (double)cnt;
+    double v = 0.0;
+    visit([&](int e, A b) {
+      const double t = as_double(b) - mean;
+      v += kept(e) ? t * t : 0.0;
+    });
+    const double sd = sqrt(wave_sum(v) / (double)cnt);
+    double peak;
+    if constexpr (INT) peak = (double)pk;
+    else peak = (double)fval(pk);
+    // w = P0: every box is the whole profile, so sigma is exactly 0
+    const double a = (sd > 0.0 && w < P0) ? (peak - mean) / sd : 0.0;
+    if (i == 0 || a > best) {
+      best = a;
+      bw = w;
+    }
+  }
+  if (lane == 0) {
+    *snr_out = (float)best;
+    *width_out = bw;
+  }
+}
+
 // Score one folded profile with Algorithm 1 (paper Sec. 2.2.1): median and
 // MAD of the profile (Eqs. 3-4), circular boxcars of every width, score =
 // max_w (max_j box_w[j] - w*median) / (K*MAD*sqrt(w)).  The wave works on one
@@ -417,30 +594,8 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     return;
   }
 
-  // circular prefix sums C[k] = sum_{i<k} F[i mod P0], k <= P0 + wmax
-  A xv[E];
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int e = r * kWave + lane;
-    xv[r] = e < P0 ? (A)row[e] : (A)0;
-  }
-  wave_lds_sync();
-  A carry = (A)0;
   A cex[E];  // C[j] (exclusive prefix) of this lane's bins
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int e = r * kWave + lane;
-    const A s = wave_scan(xv[r]);
-    cex[r] = carry + s - xv[r];
-    if (e < P0) row[e + 1] = (T)(carry + s);
-    if constexpr (INT) carry += readlane(s, 63);
-    else carry += __uint_as_float(readlane(__float_as_uint(s), 63));
-  }
-  if (lane == 0) row[0] = (T)0;
-  wave_lds_sync();
-  const A total = carry;
-  for (int i = lane; i < wmax; i += kWave) row[P0 + 1 + i] = (T)(total + (A)row[1 + i]);
-  wave_lds_sync();
+  circular_prefix<E, INT>(row, P0, wmax, cex);
 
   // Each width: largest boxcar sum, then its score num_w / ((K*MAD)*sqrt(w)).
   // The divisor scale is the same for every width, so widths are ranked by
@@ -498,12 +653,17 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 
 // EMAX bounds the registers per lane the kernel is compiled for; profiles of
 // P0 <= 64*EMAX are scored (the launcher picks EMAX from the largest P0).
-template <bool INT, int EMAX>
+template <bool INT, int EMAX, int ALG>
 __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
                                const int32_t* widths, const double* sqrtw, const double* isqrtw,
                                int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
-#define FFA_SCORE(EE) \
-  score_profile<EE, INT>(row, scratch, P0, wmax, widths, sqrtw, isqrtw, nw, kn, snr_out, width_out)
+#define FFA_SCORE(EE)                                                                              \
+  do {                                                                                             \
+    if constexpr (ALG == 2)                                                                        \
+      score_alg2<EE, INT>(row, P0, wmax, widths, nw, snr_out, width_out);                          \
+    else                                                                                           \
+      score_profile<EE, INT>(row, scratch, P0, wmax, widths, sqrtw, isqrtw, nw, kn, snr_out, width_out); \
+  } while (0)
   if (P0 <= 64) FFA_SCORE(1);
   else if (P0 <= 128) FFA_SCORE(2);
   else if (P0 <= 192) FFA_SCORE(3);
@@ -528,7 +688,7 @@ __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint
 // One workgroup per tile.  A launch covers tiles whose inputs were all
 // written by earlier launches on the stream (the planner's windows), so
 // workgroups never wait on one another.
-template <bool INT, int EMAX>
+template <bool INT, int EMAX, int ALG>
 __global__ __launch_bounds__(kThreads) void ffa_tile_kernel(TileArgs a, void* __restrict__ ws_raw) {
   using T = typename Types<INT>::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -629,7 +789,7 @@ __global__ __launch_bounds__(kThreads) void ffa_tile_kernel(TileArgs a, void* __
     for (int tt = wave; tt < R; tt += nwaves) {
       T* row = lds + (size_t)bitrev(tt, d) * S;
       const int64_t trial = trial0 + tt;
-      score_dispatch<INT, EMAX>(row, scratch, P0, wmax, widths, sw, isw, ph.nw, kn,
+      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, widths, sw, isw, ph.nw, kn,
                                 a.snr + trial, a.width + trial);
     }
   }
@@ -767,28 +927,33 @@ hipError_t launch_halve(void* ws, int is_int, int64_t in_off,
   return hipGetLastError();
 }
 
-template <bool INT, int EMAX>
+template <bool INT, int EMAX, int ALG>
 const void* tile_fn() {
-  return reinterpret_cast<const void*>(&ffa_tile_kernel<INT, EMAX>);
+  return reinterpret_cast<const void*>(&ffa_tile_kernel<INT, EMAX, ALG>);
 }
 
-const void* pick_tile_fn(int is_int, int max_P0) {
+template <int ALG>
+const void* pick_tile_fn_alg(int is_int, int max_P0) {
   if (is_int) {
-    if (max_P0 <= 512) return tile_fn<true, 8>();
-    if (max_P0 <= 1024) return tile_fn<true, 16>();
-    return tile_fn<true, 32>();
+    if (max_P0 <= 512) return tile_fn<true, 8, ALG>();
+    if (max_P0 <= 1024) return tile_fn<true, 16, ALG>();
+    return tile_fn<true, 32, ALG>();
   }
-  if (max_P0 <= 512) return tile_fn<false, 8>();
-  if (max_P0 <= 1024) return tile_fn<false, 16>();
-  return tile_fn<false, 32>();
+  if (max_P0 <= 512) return tile_fn<false, 8, ALG>();
+  if (max_P0 <= 1024) return tile_fn<false, 16, ALG>();
+  return tile_fn<false, 32, ALG>();
 }
 
-bool tiles_fit(int is_int, int max_P0, int lds_bytes) {
+const void* pick_tile_fn(int is_int, int max_P0, int alg) {
+  return alg == 2 ? pick_tile_fn_alg<2>(is_int, max_P0) : pick_tile_fn_alg<1>(is_int, max_P0);
+}
+
+bool tiles_fit(int is_int, int max_P0, int lds_bytes, int alg) {
   // Static LDS of the variant plus the request must fit one workgroup; the
   // answer depends on the device and the variant only, so it is cached.
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, int> static_lds;
-  const void* fn = pick_tile_fn(is_int, max_P0);
+  const void* fn = pick_tile_fn(is_int, max_P0, alg);
   int dev = -1, max_lds = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -814,21 +979,28 @@ bool tiles_fit(int is_int, int max_P0, int lds_bytes) {
 hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
                         void* ws, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  if (ntiles > 0x7fffffff || max_P0 > 2 * kMaxBinsMin || !tiles_fit(is_int, max_P0, lds_bytes))
+  if (ntiles > 0x7fffffff || max_P0 > 2 * kMaxBinsMin || (a.alg != 1 && a.alg != 2) ||
+      !tiles_fit(is_int, max_P0, lds_bytes, a.alg))
     return hipErrorInvalidValue;
   TileArgs b = a;
   b.select_cand = a.select_cand < 1 ? 1 : (a.select_cand > kWave ? kWave : a.select_cand);
   const unsigned g = (unsigned)ntiles;
-#define FFA_LAUNCH(I, EM) ffa_tile_kernel<I, EM><<<g, kThreads, (unsigned)lds_bytes, st>>>(b, ws)
-  if (is_int) {
-    if (max_P0 <= 512) FFA_LAUNCH(true, 8);
-    else if (max_P0 <= 1024) FFA_LAUNCH(true, 16);
-    else FFA_LAUNCH(true, 32);
-  } else {
-    if (max_P0 <= 512) FFA_LAUNCH(false, 8);
-    else if (max_P0 <= 1024) FFA_LAUNCH(false, 16);
-    else FFA_LAUNCH(false, 32);
-  }
+#define FFA_LAUNCH(I, EM, AL) ffa_tile_kernel<I, EM, AL><<<g, kThreads, (unsigned)lds_bytes, st>>>(b, ws)
+#define FFA_LAUNCH_ALG(AL)                             \
+  do {                                                 \
+    if (is_int) {                                      \
+      if (max_P0 <= 512) FFA_LAUNCH(true, 8, AL);      \
+      else if (max_P0 <= 1024) FFA_LAUNCH(true, 16, AL); \
+      else FFA_LAUNCH(true, 32, AL);                   \
+    } else {                                           \
+      if (max_P0 <= 512) FFA_LAUNCH(false, 8, AL);     \
+      else if (max_P0 <= 1024) FFA_LAUNCH(false, 16, AL); \
+      else FFA_LAUNCH(false, 32, AL);                  \
+    }                                                  \
+  } while (0)
+  if (a.alg == 2) FFA_LAUNCH_ALG(2);
+  else FFA_LAUNCH_ALG(1);
+#undef FFA_LAUNCH_ALG
 #undef FFA_LAUNCH
   return hipGetLastError();
 }

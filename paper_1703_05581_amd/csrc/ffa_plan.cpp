@@ -294,7 +294,6 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   if (d->dtype != FFA_IN_F32 && d->dtype != FFA_IN_U8) return fail(FFA_ERR_INVALID, "bad dtype");
   if (d->snr != FFA_SNR_ALG1_MAD && d->snr != FFA_SNR_ALG2_OFFPULSE)
     return fail(FFA_ERR_INVALID, "bad snr algorithm");
-  if (d->snr == FFA_SNR_ALG2_OFFPULSE) return fail(FFA_ERR_UNSUPPORTED, "Algorithm 2 not built");
   if (d->n_widths < 0 || d->n_widths > kMaxWidths) return fail(FFA_ERR_INVALID, "n_widths must be in [0, 32]");
   if (d->n_widths > 0 && !d->widths) return fail(FFA_ERR_INVALID, "widths is NULL");
   if (d->max_octaves < 0) return fail(FFA_ERR_INVALID, "max_octaves must be >= 0");

@@ -147,3 +147,11 @@ def test_server_argument_errors_before_gpu():
     assert lib.ffa_server_submit(None, None, None, 0, ctypes.byref(t)) == ffa.FFA_ERR_INVALID
     assert lib.ffa_server_wait(None, 1, 0, None, None, None) == ffa.FFA_ERR_INVALID
     assert lib.ffa_server_destroy(None) == ffa.FFA_ERR_INVALID
+
+
+def test_alg2_plans():
+    """Algorithm 2 plans build like Algorithm 1 plans (same steps, same
+    workspace)."""
+    a = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2, 4], "f32", snr=ffa.FFA_SNR_ALG1_MAD)
+    b = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2, 4], "f32", snr=ffa.FFA_SNR_ALG2_OFFPULSE)
+    assert (a.n_trials, a.n_steps, a.ws_bytes) == (b.n_trials, b.n_steps, b.ws_bytes)

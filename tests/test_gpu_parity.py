@@ -37,19 +37,21 @@ def _sample_steps(plan_o, count: int) -> list[int]:
 
 
 def run_case(torch, ffa, oracle, x, N, tsamp, pmin, pmax, B, widths, dtype, steps_max=None,
-             check_fold=0, max_octaves=0):
-    exact = dtype == "u8"
-    print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype}", flush=True)
-    plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, max_octaves=max_octaves)
+             check_fold=0, max_octaves=0, alg=1):
+    # Algorithm 2's variance is summed in a different order than the oracle's,
+    # so it is compared within the float tolerance also for uint8 input.
+    exact = dtype == "u8" and alg == 1
+    print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype} alg{alg}", flush=True)
+    plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, snr=alg, max_octaves=max_octaves)
     xt = torch.from_numpy(x).cuda()
     snr, wid = plan.search(xt)
     torch.cuda.synchronize()
     snr_g, w_g = snr.cpu().numpy(), wid.cpu().numpy()
     op = oracle.plan(N, tsamp, pmin, pmax, B, max_octaves)
     steps = list(range(op.n_steps)) if steps_max is None else _sample_steps(op, steps_max)
-    snr_o, w_o = oracle.search(x, op, widths, steps=steps)
+    snr_o, w_o = oracle.search(x, op, widths, alg=alg, steps=steps)
     idx = step_trials(op, steps)
-    summary = check_periodogram(oracle, x, op, widths, snr_g, w_g, snr_o, w_o, idx, exact)
+    summary = check_periodogram(oracle, x, op, widths, snr_g, w_g, snr_o, w_o, idx, exact, alg=alg)
     for s in steps[:: max(1, len(steps) // max(check_fold, 1))][:check_fold]:
         prof = plan.fold(xt, s).cpu().numpy()
         ref = oracle.fold_step(x, int(op.f[s]), int(op.P0[s]), int(op.m[s]), int(op.M[s]))
@@ -236,3 +238,42 @@ def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype, monkeypatch):
         torch_cuda.cuda.synchronize()
     for o in outs[1:]:
         assert torch_cuda.equal(o[0], outs[0][0]) and torch_cuda.equal(o[1], outs[0][1])
+
+
+# ------------------------------------------------------------- Algorithm 2
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"N{c[0]}_B{c[4]}" for c in SMALL])
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_alg2_small(torch_cuda, ffa, oracle_mod, case, dtype):
+    """Algorithm 2 (off-pulse window) on the small cases: every register class,
+    one to two passes, widths above P0."""
+    from paper_1703_05581_amd import synth
+
+    N, tsamp, pmin, pmax, B, widths = case
+    x = synth.random_series(11 + N, N, dtype)
+    run_case(torch_cuda, ffa, oracle_mod, x, N, tsamp, pmin, pmax, B, widths, dtype,
+             steps_max=30, alg=2)
+
+
+def test_alg2_workload1_full_and_ref(torch_cuda, ffa, oracle_mod):
+    """Workload 1 with Algorithm 2 on every trial; then the fixed-width "Ref"
+    variant (one width matched to the pulse); both find the pulsar."""
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload1()
+    pa = s.plan
+    op = oracle_mod.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
+    for widths in (list(pa.widths), [24]):
+        _, summ = run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax,
+                           pa.bins_min, widths, "f32", alg=2)
+        best_p = op.periods()[summ["best_trial"]] / pa.tsamp
+        assert abs(best_p - 733.3) < 0.1 and summ["best_snr"] > 8, (widths, best_p, summ)
+
+
+def test_alg2_workload2_sampled(torch_cuda, ffa, oracle_mod):
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload2()
+    pa = s.plan
+    run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
+             list(pa.widths), "u8", steps_max=16, alg=2)
