@@ -67,6 +67,20 @@ typedef enum { FFA_SNR_ALG1_MAD = 1, FFA_SNR_ALG2_OFFPULSE = 2 } ffa_snr;
  *              f = 2^o (Sec. 2.3.1).  2 <= B <= 1024.
  *   max_octaves  0 = as many as pmax needs, else at most this many octaves.
  *   dtype      ffa_dtype;   snr  ffa_snr.
+ *   dered_window  dynamic running-median dereddening (Sec. 2.3.1): 0 = off;
+ *              -1 = the paper's default window, the smaller of 2*pmax and
+ *              4*pmin in samples (rounded); > 0 = that many samples.  Every
+ *              octave series is filtered with the same number of its own
+ *              samples, so the window doubles relative to the input with
+ *              each downsampling.  The filter: at knots every dered_stride
+ *              samples, the median of the window's samples starting
+ *              window/2 before the knot (clipped to the series; an even
+ *              count takes the mean of the middle two); the baseline is the
+ *              linear interpolation between knots (the last knot's median
+ *              after it) and is subtracted.  A dereddened search runs in
+ *              float32 also for uint8 input.
+ *   dered_stride  knot spacing: 0 = window/8 (at least 1); 1 = the plain
+ *              per-sample running median.
  *
  * Steps: for each octave f = 1, 2, 4, ... and each integer P0 in [B, 2B)
  * with pmin <= P0*f*tsamp < pmax, one FFA execution folds m = floor(N_f/P0)
@@ -87,6 +101,8 @@ typedef struct {
   int32_t max_octaves;
   int32_t dtype;
   int32_t snr;
+  int32_t dered_window;
+  int32_t dered_stride;
 } ffa_plan_desc;
 
 /* Build a plan: step list, pass split of every step, device-side tables.
@@ -143,7 +159,8 @@ ffa_status ffa_search_prepared(ffa_plan plan, float* d_snr, int32_t* d_width,
 
 /* Raw folded profiles of step `step` (Sec. 2.1): M rows of P0 bins, row k is
  * trial k.  float32 series give float32 sums; uint8 series give exact int32
- * sums.  Not centred.  Errors as ffa_search. */
+ * sums, or float32 sums of the dereddened series when the plan dereddens.
+ * Not centred (apart from dereddening).  Errors as ffa_search. */
 ffa_status ffa_fold(ffa_plan plan, const void* d_series, int32_t step,
                     void* d_profiles, void* d_ws, size_t ws_bytes,
                     void* stream);

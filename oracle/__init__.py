@@ -12,6 +12,8 @@ from .oracle import (  # noqa: F401
     alg2,
     build,
     default_widths,
+    dered_default_window,
+    deredden,
     downsample,
     fold,
     fold_step,

@@ -401,6 +401,59 @@ double oracle_alg2_f64(const double* F, int32_t P0, const int32_t* widths,
   return have ? best : 0.0;
 }
 
+/* ------------------------------------------------------ dereddening */
+
+/* Default window of the dynamic running-median dereddening (Sec. 2.3.1): the
+ * smaller of twice the longest and four times the shortest period searched,
+ * in samples of the input series, rounded to the nearest sample. */
+int32_t oracle_dered_default_window(double tsamp, double pmin, double pmax) {
+  double w = 2.0 * pmax / tsamp;
+  double w4 = 4.0 * pmin / tsamp;
+  if (w4 < w) w = w4;
+  if (w < 1.0) w = 1.0;
+  if (w > 2147483647.0) w = 2147483647.0;
+  return (int32_t)llround(w);
+}
+
+/* Running-median dereddening of one series (Sec. 2.3.1), as read here:
+ *   - knots t_c = c*stride, c = 0 .. (n-1)/stride;
+ *   - at each knot, the median of the `window` samples starting window/2
+ *     before it, clipped to the series (an even count takes the mean of the
+ *     two middle values);
+ *   - the baseline between two knots is their linear interpolation; after the
+ *     last knot it is that knot's median;
+ *   - the output is the series minus the baseline.
+ * stride = 1 is the plain per-sample running median; stride 0 selects the
+ * default window/8 (at least 1).  Returns 0, or -1 on bad arguments. */
+int oracle_deredden_f64(const double* x, int64_t n, int32_t window, int32_t stride,
+                        double* out) {
+  if (n < 1 || window < 1 || stride < 0) return -1;
+  if (stride == 0) stride = window / 8 > 0 ? window / 8 : 1;
+  int64_t nk = (n - 1) / stride + 1;
+  double* med = (double*)malloc(sizeof(double) * (size_t)nk);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t c = 0; c < nk; ++c) {
+    int64_t t = c * stride;
+    int64_t lo = t - window / 2, hi = lo + window;
+    if (lo < 0) lo = 0;
+    if (hi > n) hi = n;
+    int64_t cnt = hi - lo;
+    double* buf = (double*)malloc(sizeof(double) * (size_t)cnt);
+    memcpy(buf, x + lo, sizeof(double) * (size_t)cnt);
+    qsort(buf, (size_t)cnt, sizeof(double), cmp_f64);
+    med[c] = cnt % 2 ? buf[cnt / 2] : 0.5 * (buf[cnt / 2 - 1] + buf[cnt / 2]);
+    free(buf);
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c = i / stride;
+    double b = med[c];
+    if (c + 1 < nk) b += (med[c + 1] - med[c]) * (double)(i - c * stride) / (double)stride;
+    out[i] = x[i] - b;
+  }
+  free(med);
+  return 0;
+}
+
 /* --------------------------------------------------------------- search */
 
 /* Score one profile with the chosen algorithm.  Integer profiles use the
@@ -446,10 +499,13 @@ int oracle_search(const void* series, int32_t dtype, int64_t N,
                   const int32_t* m_arr, const int32_t* M_arr,
                   const int64_t* first_arr, int32_t n_sel, const int32_t* sel,
                   const int32_t* widths, int32_t nw, int32_t alg,
-                  int32_t threads, float* snr, int32_t* width) {
+                  int32_t threads, int32_t dered_window, int32_t dered_stride,
+                  float* snr, int32_t* width) {
   if (dtype != ORACLE_IN_F32 && dtype != ORACLE_IN_U8) return -1;
   if (alg != ORACLE_ALG1 && alg != ORACLE_ALG2) return -1;
-  int is_int = dtype == ORACLE_IN_U8;
+  if (dered_window < 0 || dered_stride < 0) return -1;
+  /* dereddened series are real-valued: the integer path is used only without */
+  int is_int = dtype == ORACLE_IN_U8 && dered_window == 0;
   /* octave series: every octave a step uses, built by successive halving */
   int32_t max_oct = 0;
   for (int32_t s = 0; s < n_steps; ++s) {
@@ -463,6 +519,9 @@ int oracle_search(const void* series, int32_t dtype, int64_t N,
   if (is_int) {
     const uint8_t* u = (const uint8_t*)series;
     for (int64_t i = 0; i < N; ++i) ((int64_t*)oct[0])[i] = u[i];
+  } else if (dtype == ORACLE_IN_U8) {
+    const uint8_t* u = (const uint8_t*)series;
+    for (int64_t i = 0; i < N; ++i) ((double*)oct[0])[i] = u[i];
   } else {
     const float* x = (const float*)series;
     for (int64_t i = 0; i < N; ++i) ((double*)oct[0])[i] = x[i];
@@ -475,6 +534,19 @@ int oracle_search(const void* series, int32_t dtype, int64_t N,
     else
       halve_f64((const double*)oct[o - 1], len, (double*)oct[o]);
     len /= 2;
+  }
+  /* dynamic dereddening (Sec. 2.3.1): each octave series, built from the raw
+   * one above, is filtered with the same window in its own samples, i.e. a
+   * window that doubles relative to the input with each downsampling */
+  if (dered_window > 0) {
+    int64_t ln = N;
+    for (int32_t o = 0; o <= max_oct; ++o) {
+      double* tmp = (double*)malloc(sizeof(double) * (size_t)(ln > 0 ? ln : 1));
+      if (ln > 0) oracle_deredden_f64((const double*)oct[o], ln, dered_window, dered_stride, tmp);
+      free(oct[o]);
+      oct[o] = tmp;
+      ln /= 2;
+    }
   }
   int32_t total = n_sel > 0 && sel ? n_sel : n_steps;
 #ifdef _OPENMP
@@ -518,10 +590,32 @@ int oracle_search(const void* series, int32_t dtype, int64_t N,
 /* Folded profiles of one step straight from the input series (for checking
  * raw profiles).  Float input gives double profiles, uint8 gives int64. */
 int oracle_fold_step(const void* series, int32_t dtype, int64_t N, int32_t f,
-                     int32_t P0, int32_t m, int32_t M, void* out) {
+                     int32_t P0, int32_t m, int32_t M, int32_t dered_window,
+                     int32_t dered_stride, void* out) {
   if (dtype != ORACLE_IN_F32 && dtype != ORACLE_IN_U8) return -1;
+  if (dered_window < 0 || dered_stride < 0) return -1;
   int32_t o = 0;
   while ((1 << o) < f) ++o;
+  if (dered_window > 0) { /* the dereddened octave series (double profiles) */
+    double* x = (double*)malloc(sizeof(double) * (size_t)N);
+    if (dtype == ORACLE_IN_U8)
+      for (int64_t i = 0; i < N; ++i) x[i] = ((const uint8_t*)series)[i];
+    else
+      for (int64_t i = 0; i < N; ++i) x[i] = ((const float*)series)[i];
+    double* d = (double*)malloc(sizeof(double) * (size_t)N);
+    oracle_downsample_f64(x, N, o, d);
+    int64_t n = N >> o;
+    if ((int64_t)m * P0 > n) {
+      free(x);
+      free(d);
+      return -1;
+    }
+    oracle_deredden_f64(d, n, dered_window, dered_stride, x);
+    oracle_fold_f64(x, P0, m, M, (double*)out);
+    free(x);
+    free(d);
+    return 0;
+  }
   if (dtype == ORACLE_IN_U8) {
     int64_t* x = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
     const uint8_t* u = (const uint8_t*)series;

@@ -86,10 +86,16 @@ def _configure(lib):
     lib.oracle_search.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                   i32p, i32p, i32p, i32p, i64p, ctypes.c_int32, i32p,
                                   i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_float), i32p]
     lib.oracle_fold_step.restype = ctypes.c_int
     lib.oracle_fold_step.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
-                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, vp]
+    lib.oracle_dered_default_window.restype = ctypes.c_int32
+    lib.oracle_dered_default_window.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.oracle_deredden_f64.restype = ctypes.c_int
+    lib.oracle_deredden_f64.argtypes = [f64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, f64p]
     lib.oracle_mad_constant.restype = ctypes.c_double
     return lib
 
@@ -183,17 +189,20 @@ def fold(x: np.ndarray, P0: int, m: int, M: int) -> np.ndarray:
     return out
 
 
-def fold_step(series: np.ndarray, f: int, P0: int, m: int, M: int) -> np.ndarray:
-    """Profiles of one step straight from the raw series (uint8 -> int64, f32 -> f64)."""
+def fold_step(series: np.ndarray, f: int, P0: int, m: int, M: int, dered_window: int = 0,
+              dered_stride: int = 0) -> np.ndarray:
+    """Profiles of one step straight from the raw series (uint8 -> int64, f32 -> f64;
+    float64 whenever the series is dereddened)."""
     lib = _load()
     if series.dtype == np.uint8:
-        dt, out = IN_U8, np.zeros((M, P0), np.int64)
+        dt, out = IN_U8, np.zeros((M, P0), np.float64 if dered_window > 0 else np.int64)
     elif series.dtype == np.float32:
         dt, out = IN_F32, np.zeros((M, P0), np.float64)
     else:
         raise TypeError("series must be uint8 or float32")
     s = np.ascontiguousarray(series)
-    rc = lib.oracle_fold_step(s.ctypes.data, dt, s.size, f, P0, m, M, out.ctypes.data)
+    rc = lib.oracle_fold_step(s.ctypes.data, dt, s.size, f, P0, m, M, dered_window, dered_stride,
+                              out.ctypes.data)
     if rc != 0:
         raise ValueError("bad step")
     return out
@@ -231,11 +240,31 @@ def alg2(profile: np.ndarray, widths) -> tuple[float, int]:
     return _score(lib.oracle_alg2_f64, None, profile, widths)
 
 
+def dered_default_window(tsamp: float, pmin: float, pmax: float) -> int:
+    """The dereddening window the paper uses by default (Sec. 2.3.1), in
+    samples of the input series."""
+    return int(_load().oracle_dered_default_window(tsamp, pmin, pmax))
+
+
+def deredden(x: np.ndarray, window: int, stride: int = 0) -> np.ndarray:
+    """Running-median dereddening of one series (see oracle_deredden_f64)."""
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros_like(xd)
+    rc = _load().oracle_deredden_f64(_ptr(xd, ctypes.c_double), xd.size, window, stride,
+                                     _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("bad dereddening arguments")
+    return out
+
+
 def search(series: np.ndarray, p: Plan, widths=None, alg: int = ALG1, steps=None,
-           threads: int = 0) -> tuple[np.ndarray, np.ndarray]:
+           threads: int = 0, dered_window: int = 0, dered_stride: int = 0
+           ) -> tuple[np.ndarray, np.ndarray]:
     """Periodogram (S/N float32, width int32) over all trials of plan ``p``.
 
     ``steps`` selects a subset of step indices; entries of other steps are NaN / -1.
+    ``dered_window`` > 0 dereddens every octave series first (window in its
+    own samples; ``dered_stride`` 0 = window/8).
     """
     lib = _load()
     if series.dtype == np.uint8:
@@ -265,7 +294,7 @@ def search(series: np.ndarray, p: Plan, widths=None, alg: int = ALG1, steps=None
         nsel = sel_arr.size
     rc = lib.oracle_search(s.ctypes.data, dt, s.size, p.n_steps, _ptr(p.f, i32), _ptr(p.P0, i32),
                            _ptr(p.m, i32), _ptr(p.M, i32), _ptr(p.first, ctypes.c_int64),
-                           nsel, sel, _ptr(w, i32), nw, alg, threads,
+                           nsel, sel, _ptr(w, i32), nw, alg, threads, dered_window, dered_stride,
                            _ptr(snr, ctypes.c_float), _ptr(wid, i32))
     if rc != 0:
         raise ValueError("oracle_search failed")

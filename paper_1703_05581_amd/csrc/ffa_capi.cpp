@@ -40,26 +40,51 @@ namespace ffa {
 // start of `ws`.  Float input is centred on its mean when `center`.
 ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave, int center,
                          hipStream_t st) {
-  const int is_int = p->desc.dtype == FFA_IN_U8;
-  if (!is_int && center) {
-    ffa_status s = check_hip(launch_mean(reinterpret_cast<const float*>(series), p->desc.N, ws, st),
-                             "mean kernel");
+  const int int_sums = p->desc.dtype == FFA_IN_U8;
+  ffa_status s = FFA_OK;
+  if (p->dered_W > 0 && !int_sums) {
+    // float input, dereddened: raw octave series summed in double, then each
+    // used octave dereddened into its float32 series (one rounding)
+    s = check_hip(launch_prep_f64(reinterpret_cast<const float*>(series), p->desc.N, ws, p->raw_off[0], st),
+                  "prep kernel");
+    for (int32_t o = 1; o <= last_octave && s == FFA_OK; ++o)
+      s = check_hip(launch_halve_f64(ws, p->raw_off[o - 1], p->oct_len[o], p->raw_off[o], st),
+                    "downsample kernel");
+    for (int32_t o = p->dered_oct0; o <= last_octave && s == FFA_OK; ++o)
+      s = check_hip(launch_deredden(ws, 2, p->raw_off[o], p->oct_len[o], p->dered_W, p->dered_stride,
+                                    p->knots_off, p->oct_off[o], st),
+                    "dereddening kernels");
+    return s;
+  }
+  // uint8 input is summed exactly in int32; float input is centred on its mean
+  if (!int_sums && center) {
+    s = check_hip(launch_mean(reinterpret_cast<const float*>(series), p->desc.N, ws, st), "mean kernel");
     if (s != FFA_OK) return s;
   }
-  ffa_status s = check_hip(launch_prep(series, is_int, p->desc.N, ws, p->oct_off[0], center, st),
-                           "prep kernel");
+  s = check_hip(launch_prep(series, int_sums, p->desc.N, ws, p->oct_off[0], center, st), "prep kernel");
   if (s != FFA_OK) return s;
   for (int32_t o = 1; o <= last_octave; ++o) {
-    s = check_hip(launch_halve(ws, is_int, p->oct_off[o - 1], p->oct_len[o], p->oct_off[o], st),
+    s = check_hip(launch_halve(ws, int_sums, p->oct_off[o - 1], p->oct_len[o], p->oct_off[o], st),
                   "downsample kernel");
     if (s != FFA_OK) return s;
+  }
+  // dynamic dereddening (Sec. 2.3.1) of uint8 input: every octave a step
+  // folds, each from its exact int32 sums (all halvings are done), same
+  // window in its own samples, written over them as float32
+  if (p->dered_W > 0) {
+    for (int32_t o = p->dered_oct0; o <= last_octave; ++o) {
+      s = check_hip(launch_deredden(ws, 0, p->oct_off[o], p->oct_len[o], p->dered_W, p->dered_stride,
+                                    p->knots_off, p->oct_off[o], st),
+                    "dereddening kernels");
+      if (s != FFA_OK) return s;
+    }
   }
   return FFA_OK;
 }
 
 ffa_status run_launches(ffa_plan p, const DeviceTables* dt, float* snr, int32_t* width, void* ws,
                        hipStream_t st) {
-  const int is_int = p->desc.dtype == FFA_IN_U8;
+  const int is_int = p->acc_int;
   TileArgs a = base_args(p, dt);
   a.phases = dt->phases;
   a.tile_phase = dt->tile_phase;
@@ -119,7 +144,7 @@ extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, v
   s = build_octaves(p, d_series, d_ws, sp.octave, 0, st);
   if (s != FFA_OK) return s;
   // the step's passes in order, one launch each
-  const int is_int = p->desc.dtype == FFA_IN_U8;
+  const int is_int = p->acc_int;
   TileArgs a = base_args(p, dt);
   a.tile_phase = nullptr;
   a.profiles = d_profiles;

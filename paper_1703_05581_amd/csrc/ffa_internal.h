@@ -134,7 +134,13 @@ struct ffa_plan_s {
   std::vector<int64_t> oct_len;
   int64_t hdr_elems = 0;                // header (centring scratch) in elements
   int64_t series_elems = 0;             // header + octave series
-  int64_t ring_off = 0;                 // workspace: series region, then the ring
+  int32_t acc_int = 0;                  // folds in exact int32 (uint8 input, no dereddening)
+  int32_t dered_W = 0;                  // dereddening window in samples (0: off)
+  int32_t dered_stride = 1;             // knot spacing
+  int32_t dered_oct0 = 0;               // first octave a step uses (the ones below only feed halving)
+  int64_t knots_off = 0;                // workspace: knot medians (double) of one octave series
+  std::vector<int64_t> raw_off;         // float input, dereddened: raw octave series in double
+  int64_t ring_off = 0;                 // workspace: series region, knots, then the ring
   size_t ws_bytes = 0;
   int32_t select_iters = 64;            // counting rounds before key halving
   int32_t select_cand = 64;             // candidates handed to the in-lane select
@@ -165,6 +171,15 @@ hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws, int6
                        int center, hipStream_t st);
 hipError_t launch_halve(void* ws, int is_int, int64_t in_off, int64_t n_out, int64_t out_off,
                         hipStream_t st);
+// Running-median dereddening of the n-sample series at element src_off of
+// ws (src_type 0: int32 sums, 1: float, 2: double), written as float32 at
+// element out_off (may equal src_off for 4-byte sources); knot medians
+// (double) in ws[knots_off ..) (see ffa_plan_desc.dered_window).
+hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, int32_t window, int32_t stride,
+                           int64_t knots_off, int64_t out_off, hipStream_t st);
+// float32 -> double copy, and one halving of a double series (element offsets)
+hipError_t launch_prep_f64(const float* series, int64_t n, void* ws, int64_t out_off, hipStream_t st);
+hipError_t launch_halve_f64(void* ws, int64_t in_off, int64_t n_out, int64_t out_off, hipStream_t st);
 // Checks that the kernel variant for max_P0 fits lds_bytes of dynamic LDS on
 // the current device (static LDS included); caches the answer.
 bool tiles_fit(int is_int, int max_P0, int lds_bytes, int alg);

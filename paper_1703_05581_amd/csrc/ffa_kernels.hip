@@ -844,6 +844,109 @@ __global__ void prep_f32_kernel(const float* __restrict__ in, int64_t n,
   if (i < n) out[i] = center ? in[i] - *c : in[i];
 }
 
+// ------------------------------------------------------------ dereddening
+//
+// Running-median dereddening (paper Sec. 2.3.1): the median of the window at
+// every knot t_c = c*stride, then the linearly interpolated baseline is
+// subtracted.  One workgroup per knot finds the median by radix selection on
+// order-preserving keys: four passes of 8-bit digits, each counting the keys
+// that share the digits found so far into an LDS histogram.  The medians are
+// kept in double and the baseline is subtracted in double, so the series
+// (exact int32 sums for uint8 input, float otherwise) is rounded once, to the
+// float32 output written over it.
+
+constexpr int kKnotThreads = 256;
+
+__device__ __forceinline__ uint32_t series_key(int32_t v) { return (uint32_t)v; }  // sums are >= 0
+__device__ __forceinline__ uint32_t series_key(float v) { return fkey(v); }
+__device__ __forceinline__ uint64_t series_key(double v) {  // order-preserving, like fkey
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return b ^ ((b >> 63) ? ~0ull : 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_value(uint32_t k, int32_t) { return (double)k; }
+__device__ __forceinline__ double key_value(uint32_t k, float) { return (double)fval(k); }
+__device__ __forceinline__ double key_value(uint64_t k, double) {
+  return __longlong_as_double((long long)(k ^ ((k >> 63) ? 0x8000000000000000ull : ~0ull)));
+}
+
+// k-th smallest (0-based) key of x[lo..hi) (all threads return it).
+template <typename T>
+__device__ auto knot_select(const T* __restrict__ x, int64_t lo, int64_t hi, int64_t k, uint32_t* hist,
+                            uint32_t* s_digit, int64_t* s_below) {
+  using K = decltype(series_key(T()));
+  constexpr int kBits = 8 * (int)sizeof(K);
+  K prefix = 0;
+  for (int shift = kBits - 8; shift >= 0; shift -= 8) {
+    for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const K hmask = shift == kBits - 8 ? (K)0 : (K)(~(K)0 << (shift + 8));
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const K key = series_key(x[i]);
+      if ((key & hmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    // the digit whose bin holds rank k (a short serial scan by one thread)
+    if (threadIdx.x == 0) {
+      int64_t below = 0;
+      uint32_t dg = 255u;
+      for (uint32_t b = 0; b < 256u; ++b) {
+        if (k < below + (int64_t)hist[b]) {
+          dg = b;
+          break;
+        }
+        below += hist[b];
+      }
+      *s_digit = dg;
+      *s_below = below;
+    }
+    __syncthreads();
+    prefix |= (K)*s_digit << shift;
+    k -= *s_below;
+    __syncthreads();
+  }
+  return prefix;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kKnotThreads) void knot_median_kernel(const T* __restrict__ x, int64_t n,
+                                                                   int32_t window, int32_t stride,
+                                                                   double* __restrict__ med) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_digit;
+  __shared__ int64_t s_below;
+  const int64_t c = blockIdx.x;
+  const int64_t t = c * stride;
+  int64_t lo = t - window / 2, hi = lo + window;
+  lo = lo < 0 ? 0 : lo;
+  hi = hi > n ? n : hi;
+  const int64_t cnt = hi - lo;
+  const double v1 = key_value(knot_select(x, lo, hi, (cnt - 1) / 2, hist, &s_digit, &s_below), T());
+  double m = v1;
+  if (cnt % 2 == 0) m = 0.5 * (v1 + key_value(knot_select(x, lo, hi, cnt / 2, hist, &s_digit, &s_below), T()));
+  if (threadIdx.x == 0) med[c] = m;
+}
+
+// out[i] = x[i] - baseline(i), in double, rounded once to float32.  `out` may
+// alias `x` when both are 4-byte types (each thread reads its element first).
+template <typename T>
+__global__ void dered_subtract_kernel(const T* x, int64_t n, int32_t stride, int64_t nk,
+                                      const double* __restrict__ med, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = i / stride;
+  double b = med[c];
+  if (c + 1 < nk) b += (med[c + 1] - med[c]) * (double)(i - c * stride) / (double)stride;
+  const double v = (double)x[i] - b;
+  out[i] = (float)v;
+}
+
+// float input for a dereddened search: double copy, so the octave sums keep
+// the precision the baseline subtraction needs
+__global__ void prep_f64_kernel(const float* __restrict__ in, int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
 // One halving of the time resolution (paper Sec. 2.3.1): y[i] = x[2i]+x[2i+1].
 template <typename T>
 __global__ void halve_kernel(const T* __restrict__ in, int64_t n_out,
@@ -912,6 +1015,37 @@ hipError_t launch_prep(const void* series, int is_int, int64_t n, void* ws, int6
   return hipGetLastError();
 }
 
+hipError_t launch_prep_f64(const float* series, int64_t n, void* ws, int64_t out_off, hipStream_t st) {
+  const int tpb = 256;
+  prep_f64_kernel<<<(unsigned)((n + tpb - 1) / tpb), tpb, 0, st>>>(
+      series, n, reinterpret_cast<double*>(reinterpret_cast<float*>(ws) + out_off));
+  return hipGetLastError();
+}
+
+hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, int32_t window, int32_t stride,
+                           int64_t knots_off, int64_t out_off, hipStream_t st) {
+  if (n < 1) return hipSuccess;
+  if (window < 1 || stride < 1) return hipErrorInvalidValue;
+  float* w = reinterpret_cast<float*>(ws);
+  double* med = reinterpret_cast<double*>(w + knots_off);
+  float* out = w + out_off;
+  const int64_t nk = (n - 1) / stride + 1;
+  if (nk > 0x7fffffff) return hipErrorInvalidValue;
+  const int tpb = 256;
+  const unsigned gs = (unsigned)((n + tpb - 1) / tpb);
+#define FFA_DERED(TT)                                                                          \
+  do {                                                                                         \
+    const TT* x = reinterpret_cast<const TT*>(w + src_off);                                    \
+    knot_median_kernel<TT><<<(unsigned)nk, kKnotThreads, 0, st>>>(x, n, window, stride, med);  \
+    dered_subtract_kernel<TT><<<gs, tpb, 0, st>>>(x, n, stride, nk, med, out);                 \
+  } while (0)
+  if (src_type == 0) FFA_DERED(int32_t);
+  else if (src_type == 1) FFA_DERED(float);
+  else FFA_DERED(double);
+#undef FFA_DERED
+  return hipGetLastError();
+}
+
 hipError_t launch_halve(void* ws, int is_int, int64_t in_off,
                               int64_t n_out, int64_t out_off, hipStream_t st) {
   const int tpb = 256;
@@ -924,6 +1058,16 @@ hipError_t launch_halve(void* ws, int is_int, int64_t in_off,
     float* w = reinterpret_cast<float*>(ws);
     halve_kernel<float><<<blocks, tpb, 0, st>>>(w + in_off, n_out, w + out_off);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_halve_f64(void* ws, int64_t in_off, int64_t n_out, int64_t out_off, hipStream_t st) {
+  const int tpb = 256;
+  const int64_t blocks = (n_out + tpb - 1) / tpb;
+  if (n_out <= 0) return hipSuccess;
+  float* w = reinterpret_cast<float*>(ws);
+  halve_kernel<double><<<blocks, tpb, 0, st>>>(reinterpret_cast<const double*>(w + in_off), n_out,
+                                               reinterpret_cast<double*>(w + out_off));
   return hipGetLastError();
 }
 

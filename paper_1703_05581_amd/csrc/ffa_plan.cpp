@@ -299,7 +299,9 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   if (d->max_octaves < 0) return fail(FFA_ERR_INVALID, "max_octaves must be >= 0");
   for (int i = 0; i < d->n_widths; ++i)
     if (d->widths[i] < 1) return fail(FFA_ERR_INVALID, "widths must be >= 1");
-  if (d->dtype == FFA_IN_U8 && 255.0 * (double)d->N >= 2147483648.0)
+  if (d->dered_window < -1) return fail(FFA_ERR_INVALID, "dered_window must be -1, 0 or > 0");
+  if (d->dered_stride < 0) return fail(FFA_ERR_INVALID, "dered_stride must be >= 0");
+  if (d->dtype == FFA_IN_U8 && d->dered_window == 0 && 255.0 * (double)d->N >= 2147483648.0)
     return fail(FFA_ERR_UNSUPPORTED, "uint8 series longer than (2^31-1)/255 samples");
 
   ffa_plan_s* p = new (std::nothrow) ffa_plan_s();
@@ -372,7 +374,18 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   const int32_t nsq = (int32_t)p->sqrtw.size();
   for (int32_t i = 0; i < nsq; ++i) p->sqrtw.push_back(1.0 / p->sqrtw[i]);
 
-  // --- series region: header | octave series
+  // --- dereddening (Sec. 2.3.1): window in samples of every octave series
+  if (d->dered_window != 0) {
+    double w = d->dered_window > 0 ? (double)d->dered_window
+                                   : std::min(2.0 * d->pmax_s / d->tsamp_s, 4.0 * d->pmin_s / d->tsamp_s);
+    w = std::max(1.0, std::min(w, 2147483647.0));
+    p->dered_W = (int32_t)std::llround(w);
+    p->dered_stride = d->dered_stride > 0 ? d->dered_stride : std::max(1, p->dered_W / 8);
+  }
+  p->acc_int = d->dtype == FFA_IN_U8 && p->dered_W == 0;
+  p->dered_oct0 = p->steps.front().octave;
+
+  // --- series region: header | octave series | knot medians
   p->hdr_elems = 2112;  // 1024 partial sums (double) + centring constant, 8448 B
   p->n_octaves = max_oct + 1;
   int64_t cur = p->hdr_elems;
@@ -380,6 +393,15 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     p->oct_off.push_back(cur);
     p->oct_len.push_back(d->N >> o);
     cur = round_up(cur + (d->N >> o), 64);
+  }
+  p->knots_off = cur;
+  if (p->dered_W > 0) cur = round_up(cur + 2 * ((d->N - 1) / p->dered_stride + 1), 64);
+  if (p->dered_W > 0 && d->dtype == FFA_IN_F32) {
+    // float input: raw octave series in double, dereddened into the float ones
+    for (int32_t o = 0; o < p->n_octaves; ++o) {
+      p->raw_off.push_back(cur);
+      cur = round_up(cur + 2 * (d->N >> o), 64);
+    }
   }
   p->series_elems = cur;
 

@@ -59,6 +59,8 @@ class PlanDesc(ctypes.Structure):
         ("max_octaves", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
         ("snr", ctypes.c_int32),
+        ("dered_window", ctypes.c_int32),
+        ("dered_stride", ctypes.c_int32),
     ]
 
 
@@ -134,18 +136,21 @@ class Plan:
     """A search plan (ffa_plan_create).  ``dtype`` is "f32" or "u8"."""
 
     def __init__(self, N: int, tsamp: float, pmin: float, pmax: float, bins_min: int,
-                 widths=None, dtype: str = "f32", snr: int = FFA_SNR_ALG1_MAD, max_octaves: int = 0):
+                 widths=None, dtype: str = "f32", snr: int = FFA_SNR_ALG1_MAD, max_octaves: int = 0,
+                 dered_window: int = 0, dered_stride: int = 0):
         self._h = _vp()
         w = list(widths) if widths else []
         self._warr = (ctypes.c_int32 * max(len(w), 1))(*w)
         desc = PlanDesc(N=N, tsamp_s=tsamp, pmin_s=pmin, pmax_s=pmax,
                         widths=ctypes.cast(self._warr, _P(ctypes.c_int32)) if w else None,
                         n_widths=len(w), bins_min=bins_min, max_octaves=max_octaves,
-                        dtype=FFA_IN_U8 if dtype == "u8" else FFA_IN_F32, snr=snr)
+                        dtype=FFA_IN_U8 if dtype == "u8" else FFA_IN_F32, snr=snr,
+                        dered_window=dered_window, dered_stride=dered_stride)
         _check(_lib.ffa_plan_create(ctypes.byref(desc), ctypes.byref(self._h)), "ffa_plan_create")
         self.N = N
         self.tsamp = tsamp
         self.dtype = dtype
+        self.dered_window = dered_window
         nt, ns, ws = _i64(), _i32(), _sz()
         _check(_lib.ffa_plan_query(self._h, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(ws)),
                "ffa_plan_query")
@@ -155,7 +160,7 @@ class Plan:
     def from_args(cls, pa, snr: int = FFA_SNR_ALG1_MAD) -> "Plan":
         """From a ``synth.PlanArgs``."""
         return cls(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min, pa.widths, pa.dtype, snr,
-                   pa.max_octaves)
+                   pa.max_octaves, getattr(pa, "dered_window", 0), getattr(pa, "dered_stride", 0))
 
     @property
     def handle(self) -> int:
@@ -248,7 +253,7 @@ class Plan:
 
         self._check_series(series)
         info = self.step(step)
-        dt = torch.int32 if self.dtype == "u8" else torch.float32
+        dt = torch.int32 if self.dtype == "u8" and not self.dered_window else torch.float32
         if out is None:
             out = torch.empty((info.M, info.P0), dtype=dt, device=series.device)
         if ws is None:

@@ -15,11 +15,12 @@ them; the shapes follow Sec. 2.4 and Sec. 4 of the paper):
                 P0 in [256, 512) over octaves f = 1, 2, 4 (0.256-2.048 s), pulsars at
                 0.4, 0.9, 1.7 s with duty 2%, 3.5%, 5%, folded S/N about 15 each.
   3 "htru"    : f32[2^23], tsamp 0.512 ms (~71.6 min), white N(0,1) plus power-law red
-                noise (power spectral index -2, same rms as the white part), minus a
-                running median of 2 s, 0.5-30 s, P0 in [256, 512), 10 pulsars with
-                log-uniform periods, duty 1-10%, S/N 10-30.
+                noise (power spectral index -2, same rms as the white part), 0.5-30 s,
+                P0 in [256, 512), 10 pulsars with log-uniform periods, duty 1-10%,
+                S/N 10-30; the plan dereddens with the paper's default window.
   4 "batch"   : 256 f32 series, N from {2^18 .. 2^22}, tsamp 0.512 ms, Pmin U(0.2, 1) s,
-                Pmax U(5, 30) s, noise as workload 3, 30% with one pulsar of S/N 15.
+                Pmax U(5, 30) s, noise as workload 3 (dereddened by the plan), 30% with
+                one pulsar of S/N 15.
   5 "served"  : f32 series of N from {2^20 .. 2^23}, tsamp 1 ms, workload 2's plan and
                 noise model (unclipped floats), workload 2's pulsars in 30% of requests.
 """
@@ -45,6 +46,8 @@ class PlanArgs:
     widths: tuple = WIDTHS
     dtype: str = "f32"  # "f32" or "u8"
     max_octaves: int = 0
+    dered_window: int = 0  # 0: off, -1: the paper's default window, > 0: samples
+    dered_stride: int = 0
 
 
 @dataclass
@@ -97,23 +100,6 @@ def red_noise(n: int, g: np.random.Generator, index: float = -2.0) -> np.ndarray
     return out / np.sqrt(np.mean(out ** 2))
 
 
-def running_median_detrend(x: np.ndarray, window: int, stride: int = 256) -> np.ndarray:
-    """x minus its running median over ``window`` samples.  The median is taken
-    every ``stride`` samples (centred windows, clipped at the ends) and
-    linearly interpolated in between; input preparation only."""
-    n = x.size
-    centres = np.arange(0, n, stride, dtype=np.int64)
-    if centres[-1] != n - 1:
-        centres = np.append(centres, n - 1)
-    half = window // 2
-    meds = np.empty(centres.size)
-    for i, c in enumerate(centres):
-        lo, hi = max(0, c - half), min(n, c - half + window)
-        meds[i] = np.median(x[lo:hi])
-    trend = np.interp(np.arange(n, dtype=np.float64), centres.astype(np.float64), meds)
-    return x - trend
-
-
 # ------------------------------------------------------------- workloads
 
 def plan_args(workload: int) -> PlanArgs:
@@ -122,7 +108,7 @@ def plan_args(workload: int) -> PlanArgs:
     if workload == 2:
         return PlanArgs(N=1 << 20, tsamp=1e-3, pmin=0.256, pmax=2.048, bins_min=256, dtype="u8")
     if workload == 3:
-        return PlanArgs(N=1 << 23, tsamp=0.512e-3, pmin=0.5, pmax=30.0, bins_min=256)
+        return PlanArgs(N=1 << 23, tsamp=0.512e-3, pmin=0.5, pmax=30.0, bins_min=256, dered_window=-1)
     raise ValueError("workloads 4 and 5 have per-series plans")
 
 
@@ -172,8 +158,6 @@ def workload3(index: int = 0, n: int | None = None) -> Series:
                            float(g.random())))
     for p in psrs:
         x += pulse_train(pa.N, pa.tsamp, p, 1.0)
-    window = int(round(2.0 / pa.tsamp))
-    x = running_median_detrend(x, window)
     return Series(x.astype(np.float32), pa, psrs, seed)
 
 
@@ -187,14 +171,13 @@ def workload4(index: int, count: int = 256) -> Series:
     tsamp = 0.512e-3
     pmin = float(g.uniform(0.2, 1.0))
     pmax = float(g.uniform(5.0, 30.0))
-    pa = PlanArgs(N=N, tsamp=tsamp, pmin=pmin, pmax=pmax, bins_min=256)
+    pa = PlanArgs(N=N, tsamp=tsamp, pmin=pmin, pmax=pmax, bins_min=256, dered_window=-1)
     x = _htru_noise(N, tsamp, g)
     psrs = []
     if g.random() < 0.3:
         P = float(np.exp(g.uniform(np.log(pmin), np.log(pmax))))
         psrs.append(Pulsar(P, float(g.uniform(0.01, 0.10)), 15.0, float(g.random())))
         x += pulse_train(N, tsamp, psrs[0], 1.0)
-    x = running_median_detrend(x, int(round(2.0 / tsamp)))
     return Series(x.astype(np.float32), pa, psrs, seed)
 
 

@@ -309,6 +309,67 @@ def pin_alg2_snr_level(o):
     assert 0.85 < ratio < 1.2, ratio
 
 
+# ------------------------------------------------------- dereddening
+
+def pin_dered_ramp(o):
+    """A linear ramp a*i + b: a window of odd length centred on a knot has the
+    knot's own value as median, and linear interpolation of a line is exact,
+    so the interior of the output is 0.  An even window [t - W/2, t + W/2)
+    has median a*(t - 1/2) + b, so the interior is a/2."""
+    a, b = 0.37, -5.0
+    x = a * np.arange(5000) + b
+    for W, expect in ((101, 0.0), (100, a / 2)):
+        out = o.deredden(x, W, 10)
+        assert np.abs(out[60:4930] - expect).max() < 1e-9, (W, out[60:70])
+
+
+def pin_dered_library(o):
+    """Stride 1 is the plain running median: inside the series it equals
+    scipy's median filter (centred window of odd length)."""
+    from scipy.signal import medfilt
+
+    g = np.random.default_rng(24)
+    x = g.standard_normal(3000) + np.sin(np.arange(3000) / 150.0) * 3
+    for W in (5, 31, 201):
+        out = o.deredden(x, W, 1)
+        ref = x - medfilt(x, W)
+        h = W // 2
+        assert np.abs(out[h:-h] - ref[h:-h]).max() < 1e-12, W
+
+
+def pin_dered_default_window(o):
+    """Twice the longest or four times the shortest period, whichever is
+    smaller (Sec. 2.3.1): 0.5-30 s at 0.512 ms gives 3906 samples (2 s);
+    0.5-1 s at 1 ms gives 2000; 0.256-2.048 s at 1 ms gives 1024."""
+    assert o.dered_default_window(0.512e-3, 0.5, 30.0) == 3906
+    assert o.dered_default_window(1e-3, 0.5, 1.0) == 2000
+    assert o.dered_default_window(1e-3, 0.256, 2.048) == 1024
+
+
+def pin_dered_offset_and_constant(o):
+    g = np.random.default_rng(25)
+    x = g.standard_normal(777)
+    assert np.allclose(o.deredden(x + 1234.5, 64), o.deredden(x, 64), atol=1e-9)
+    assert np.abs(o.deredden(np.full(500, 3.25), 40, 3)).max() == 0.0
+
+
+def pin_dered_search_recovers(o):
+    """A pulsar on top of a strong slow baseline swing: after dynamic
+    dereddening (the paper's default window) it is the best trial."""
+    g = np.random.default_rng(26)
+    N, ts, pmin, pmax, B = 1 << 16, 1e-3, 0.5, 1.0, 500
+    t = np.arange(N)
+    x = g.standard_normal(N) + 40.0 * np.sin(2 * np.pi * t / 20000.0)
+    P = 733.3
+    x += 1.2 * np.exp(-0.5 * (((t % P) - 100.0) / 7.0) ** 2)
+    x = x.astype(np.float32)
+    p = o.plan(N, ts, pmin, pmax, B)
+    W = o.dered_default_window(ts, pmin, pmax)
+    snr, _ = o.search(x, p, [1, 2, 4, 8, 16, 32], dered_window=W)
+    best = p.periods()[int(np.argmax(snr))] / ts
+    assert abs(best - P) < 0.5, best
+
+
 # ---------------------------------------------------- plan / downsample
 
 def pin_downsample(o):
@@ -380,6 +441,11 @@ ALL_PINS = [
     pin_alg2_invariants,
     pin_alg2_sigma_zero,
     pin_alg2_snr_level,
+    pin_dered_ramp,
+    pin_dered_library,
+    pin_dered_default_window,
+    pin_dered_offset_and_constant,
+    pin_dered_search_recovers,
     pin_default_widths,
     pin_downsample,
     pin_plan,

@@ -29,7 +29,7 @@ def _trial_step(plan_o, trial: int) -> tuple[int, int]:
 
 
 def check_periodogram(oracle, series, plan_o, widths, snr_g, w_g, snr_o, w_o, idx, exact: bool,
-                      alg: int = 1) -> dict:
+                      alg: int = 1, dered_window: int = 0, dered_stride: int = 0) -> dict:
     """Assert parity on trials ``idx``; return a summary."""
     sg, so = snr_g[idx], snr_o[idx]
     wg, wo = w_g[idx], w_o[idx]
@@ -47,7 +47,8 @@ def check_periodogram(oracle, series, plan_o, widths, snr_g, w_g, snr_o, w_o, id
             t = int(idx[i])
             s, k = _trial_step(plan_o, t)
             prof = oracle.fold_step(series, int(plan_o.f[s]), int(plan_o.P0[s]), int(plan_o.m[s]),
-                                    int(plan_o.M[s]))[k]
+                                    int(plan_o.M[s]), dered_window=dered_window,
+                                    dered_stride=dered_stride)[k]
             fn = oracle.alg1 if alg == 1 else oracle.alg2
             at_gpu = fn(prof, [int(wg[i])])[0]
             assert abs(at_gpu - float(so[i])) <= TIE_ATOL, (t, int(wg[i]), int(wo[i]), at_gpu, so[i])

@@ -84,6 +84,8 @@ def _desc(**kw):
     (dict(bins_min=2000), ffa.FFA_ERR_INVALID),
     (dict(dtype=7), ffa.FFA_ERR_INVALID),
     (dict(snr=9), ffa.FFA_ERR_INVALID),
+    (dict(dered_window=-2), ffa.FFA_ERR_INVALID),
+    (dict(dered_stride=-1), ffa.FFA_ERR_INVALID),
     (dict(n_widths=40), ffa.FFA_ERR_INVALID),
     (dict(n_widths=3), ffa.FFA_ERR_INVALID),           # NULL widths
     (dict(pmin_s=50.0, pmax_s=60.0), ffa.FFA_ERR_INVALID),  # no step
@@ -155,3 +157,18 @@ def test_alg2_plans():
     a = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2, 4], "f32", snr=ffa.FFA_SNR_ALG1_MAD)
     b = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2, 4], "f32", snr=ffa.FFA_SNR_ALG2_OFFPULSE)
     assert (a.n_trials, a.n_steps, a.ws_bytes) == (b.n_trials, b.n_steps, b.ws_bytes)
+
+
+def test_dered_plans():
+    """Dereddening moves a uint8 plan to float folding, so the uint8 length
+    bound no longer applies; the workspace grows by the knot medians."""
+    big = dict(N=1 << 24, dtype=1, pmin_s=0.5, pmax_s=1.0, bins_min=500)
+    d = _desc(**big)
+    h = ctypes.c_void_p()
+    assert ffa.lib().ffa_plan_create(ctypes.byref(d), ctypes.byref(h)) == ffa.FFA_ERR_UNSUPPORTED
+    d = _desc(dered_window=-1, **big)
+    assert ffa.lib().ffa_plan_create(ctypes.byref(d), ctypes.byref(h)) == ffa.FFA_OK
+    ffa.lib().ffa_plan_destroy(h)
+    a = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2], "u8")
+    b = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2], "u8", dered_window=-1)
+    assert b.ws_bytes > a.ws_bytes and a.n_trials == b.n_trials

@@ -59,7 +59,8 @@ def test_batch_equals_single(env, oracle_mod, dtype):
 
 def test_batch_workload4_subset(env, oracle_mod):
     """Eight series of the batched workload (lengths 2^18..2^22, own period
-    ranges, red noise): batch equals single, sampled steps equal the oracle."""
+    ranges, red noise, dereddened by their plans): batch equals single,
+    sampled steps equal the oracle."""
     torch, ffa, synth = env
     series = [synth.workload4(i) for i in range(8)]
     plans = [ffa.Plan.from_args(s.plan) for s in series]
@@ -74,9 +75,11 @@ def test_batch_workload4_subset(env, oracle_mod):
     pa = s.plan
     op = oracle_mod.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
     steps = sorted(set(np.linspace(0, op.n_steps - 1, 5).round().astype(int).tolist()))
-    so, wo = oracle_mod.search(s.data, op, list(pa.widths), steps=steps)
+    W = oracle_mod.dered_default_window(pa.tsamp, pa.pmin, pa.pmax)
+    so, wo = oracle_mod.search(s.data, op, list(pa.widths), steps=steps, dered_window=W)
     check_periodogram(oracle_mod, s.data, op, list(pa.widths), outs[1][0].cpu().numpy(),
-                      outs[1][1].cpu().numpy(), so, wo, step_trials(op, steps), exact=False)
+                      outs[1][1].cpu().numpy(), so, wo, step_trials(op, steps), exact=False,
+                      dered_window=W)
 
 
 def test_batch_mixed_types_and_prepared(env):

@@ -37,24 +37,31 @@ def _sample_steps(plan_o, count: int) -> list[int]:
 
 
 def run_case(torch, ffa, oracle, x, N, tsamp, pmin, pmax, B, widths, dtype, steps_max=None,
-             check_fold=0, max_octaves=0, alg=1):
+             check_fold=0, max_octaves=0, alg=1, dered_window=0, dered_stride=0):
     # Algorithm 2's variance is summed in a different order than the oracle's,
-    # so it is compared within the float tolerance also for uint8 input.
-    exact = dtype == "u8" and alg == 1
-    print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype} alg{alg}", flush=True)
-    plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, snr=alg, max_octaves=max_octaves)
+    # and a dereddened series is real-valued, so both are compared within the
+    # float tolerance also for uint8 input.
+    exact = dtype == "u8" and alg == 1 and dered_window == 0
+    print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype} alg{alg} "
+          f"dered={dered_window}/{dered_stride}", flush=True)
+    plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, snr=alg, max_octaves=max_octaves,
+                    dered_window=dered_window, dered_stride=dered_stride)
+    W = oracle.dered_default_window(tsamp, pmin, pmax) if dered_window == -1 else dered_window
     xt = torch.from_numpy(x).cuda()
     snr, wid = plan.search(xt)
     torch.cuda.synchronize()
     snr_g, w_g = snr.cpu().numpy(), wid.cpu().numpy()
     op = oracle.plan(N, tsamp, pmin, pmax, B, max_octaves)
     steps = list(range(op.n_steps)) if steps_max is None else _sample_steps(op, steps_max)
-    snr_o, w_o = oracle.search(x, op, widths, alg=alg, steps=steps)
+    snr_o, w_o = oracle.search(x, op, widths, alg=alg, steps=steps, dered_window=W,
+                               dered_stride=dered_stride)
     idx = step_trials(op, steps)
-    summary = check_periodogram(oracle, x, op, widths, snr_g, w_g, snr_o, w_o, idx, exact, alg=alg)
+    summary = check_periodogram(oracle, x, op, widths, snr_g, w_g, snr_o, w_o, idx, exact, alg=alg,
+                                dered_window=W, dered_stride=dered_stride)
     for s in steps[:: max(1, len(steps) // max(check_fold, 1))][:check_fold]:
         prof = plan.fold(xt, s).cpu().numpy()
-        ref = oracle.fold_step(x, int(op.f[s]), int(op.P0[s]), int(op.m[s]), int(op.M[s]))
+        ref = oracle.fold_step(x, int(op.f[s]), int(op.P0[s]), int(op.m[s]), int(op.M[s]),
+                               dered_window=W, dered_stride=dered_stride)
         check_profiles(prof, ref, exact)
     return plan, summary
 
@@ -150,14 +157,15 @@ def test_workload2_sampled(torch_cuda, ffa, oracle_mod):
 
 
 def test_workload3_sampled(torch_cuda, ffa, oracle_mod):
-    """2^23 float32 samples with red noise, 0.5-30 s: sampled steps, including
-    the three-pass ones."""
+    """2^23 float32 samples with red noise, 0.5-30 s, dereddened with the
+    paper's default window: sampled steps, including the three-pass ones."""
     from paper_1703_05581_amd import synth
 
     s = synth.workload3()
     pa = s.plan
     run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
-             list(pa.widths), "f32", steps_max=10, check_fold=2)
+             list(pa.widths), "f32", steps_max=10, check_fold=2, dered_window=pa.dered_window,
+             dered_stride=pa.dered_stride)
 
 
 def test_deterministic(torch_cuda, ffa):

@@ -37,6 +37,11 @@ MUTATIONS = [
      "for (int32_t i = 0; i < n_ex; ++i) if (start + i >= 0 && start + i < P0) excl[start + i] = 1;"),
     ("alg2_last_max", "if (bx[j] > bx[jmax]) jmax = j;", "if (bx[j] >= bx[jmax]) jmax = j;"),
     ("alg2_full_width_noise", "if (cnt > 0 && w < P0) {", "if (cnt > 0) {"),
+    ("dered_window_late", "int64_t lo = t - window / 2, hi = lo + window;", "int64_t lo = t, hi = lo + window;"),
+    ("dered_even_upper", "med[c] = cnt % 2 ? buf[cnt / 2] : 0.5 * (buf[cnt / 2 - 1] + buf[cnt / 2]);",
+     "med[c] = buf[cnt / 2];"),
+    ("dered_no_interp", "if (c + 1 < nk) b += (med[c + 1] - med[c])", "if (c + 1 < 0) b += (med[c + 1] - med[c])"),
+    ("dered_default_2x", "double w4 = 4.0 * pmin / tsamp;", "double w4 = 2.0 * pmin / tsamp;"),
 ]
 
 
@@ -49,11 +54,12 @@ def test_mutation_is_caught(oracle_mod, tmp_path, name, old, new):
     so = tmp_path / f"lib{name}.so"
     subprocess.run(["gcc", "-O1", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(mut), "-lm"],
                    check=True)
-    caught = []
+    caught = None
     with oracle_mod.library(str(so)):
         for pin in ALL_PINS:
             try:
                 pin(oracle_mod)
             except Exception:  # noqa: BLE001 - any failure counts as caught
-                caught.append(pin.__name__)
+                caught = pin.__name__
+                break
     assert caught, f"planted mistake {name} passed every pin"
