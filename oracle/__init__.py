@@ -8,6 +8,7 @@ from .oracle import (  # noqa: F401
     ALG2,
     IN_F32,
     IN_U8,
+    Plan,
     alg1,
     alg2,
     build,
@@ -21,4 +22,5 @@ from .oracle import (  # noqa: F401
     mad_constant,
     plan,
     search,
+    sift,
 )

@@ -648,4 +648,139 @@ int oracle_fold_step(const void* series, int32_t dtype, int64_t N, int32_t f,
   return 0;
 }
 
+/* ------------------------------------------------------- candidates */
+
+/* Candidate sifting of a periodogram, after the paper's ffa2best (Sec. 2.3.3;
+ * settings used in Sec. 4).  The paper names three thresholds, grouping of a
+ * strong pulsar's smeared response and harmonic matching by the fractions
+ * n/x (x prime, 0 < n < x) within a tolerance, but not their exact rules.
+ * Readings taken here:
+ *
+ *  peaks: trials are scanned in plan order (period non-decreasing).  A trial
+ *    with S/N >= min_snr opens a candidate when none is open; while one is
+ *    open, a higher S/N moves it there; once the S/N has fallen from it by at
+ *    least frac_fall * its S/N and by at least abs_fall, the candidate closes,
+ *    and so does any S/N below min_snr (NaN counts as below).
+ *  grouping (group_widths > 0): in S/N order (ties: lower trial first), a
+ *    surviving candidate c removes each weaker one d with
+ *    |P_d - P_c| <= group_widths * W_c * P_c / T_c, W_c = its boxcar width in
+ *    seconds and T_c its folded span m*P0*f*tsamp: the period offset at which
+ *    its pulse drifts by group_widths widths across the data.
+ *  harmonics (harmonic_primes >= 2): in the same order, a surviving c removes
+ *    each weaker surviving d with |P_d - r*P_c| <= tol * r*P_c for
+ *    r = n/x or x/n, x prime <= harmonic_primes, 0 < n < x.
+ *
+ * Outputs the surviving candidates in S/N order (trial index, period, S/N,
+ * width); returns their count, or -1 on bad arguments.  Each output array
+ * needs room for every peak (at most n_trials). */
+static int64_t sift_step_of(const int64_t* first, int32_t n_steps, int64_t t) {
+  int32_t lo = 0, hi = n_steps - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) / 2;
+    if (first[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+typedef struct {
+  int64_t trial;
+  double period, span, wsec;
+  float snr;
+  int32_t width;
+  int alive;
+} sift_cand;
+
+static int cmp_cand(const void* a, const void* b) {
+  const sift_cand* x = (const sift_cand*)a;
+  const sift_cand* y = (const sift_cand*)b;
+  if (x->snr != y->snr) return x->snr > y->snr ? -1 : 1;
+  return (x->trial > y->trial) - (x->trial < y->trial);
+}
+
+int64_t oracle_sift(const float* snr, const int32_t* width, int64_t n_trials, int32_t n_steps,
+                    const int32_t* f_arr, const int32_t* P0_arr, const int32_t* m_arr,
+                    const int32_t* M_arr, const int64_t* first_arr, double tsamp,
+                    float min_snr, float frac_fall, float abs_fall, float group_widths,
+                    int32_t harmonic_primes, float harmonic_tol, int64_t* out_trial,
+                    double* out_period, float* out_snr, int32_t* out_width) {
+  if (n_trials < 0 || n_steps < 1 || !(tsamp > 0.0)) return -1;
+  sift_cand* c = (sift_cand*)malloc(sizeof(sift_cand) * (size_t)(n_trials > 0 ? n_trials : 1));
+  int64_t nc = 0;
+  int open = 0;
+  for (int64_t t = 0; t < n_trials; ++t) {
+    float s = snr[t];
+    if (!(s >= min_snr)) {
+      open = 0;
+      continue;
+    }
+    if (!open) {
+      c[nc].trial = t;
+      c[nc].snr = s;
+      ++nc;
+      open = 1;
+      continue;
+    }
+    sift_cand* cur = &c[nc - 1];
+    if (s > cur->snr) {
+      cur->trial = t;
+      cur->snr = s;
+    } else if (cur->snr - s >= frac_fall * cur->snr && cur->snr - s >= abs_fall) {
+      open = 0;
+    }
+  }
+  for (int64_t i = 0; i < nc; ++i) {
+    int64_t s = sift_step_of(first_arr, n_steps, c[i].trial);
+    int64_t k = c[i].trial - first_arr[s];
+    double fts = (double)f_arr[s] * tsamp;
+    c[i].period = fts * ((double)P0_arr[s] + (double)k / (double)(M_arr[s] - 1));
+    c[i].span = fts * (double)m_arr[s] * (double)P0_arr[s];
+    c[i].width = width[c[i].trial];
+    c[i].wsec = fts * (double)c[i].width;
+    c[i].alive = 1;
+  }
+  qsort(c, (size_t)nc, sizeof(sift_cand), cmp_cand);
+  if (group_widths > 0.0f) {
+    for (int64_t i = 0; i < nc; ++i) {
+      if (!c[i].alive) continue;
+      double lim = (double)group_widths * c[i].wsec * c[i].period / c[i].span;
+      for (int64_t j = i + 1; j < nc; ++j)
+        if (c[j].alive && fabs(c[j].period - c[i].period) <= lim) c[j].alive = 0;
+    }
+  }
+  if (harmonic_primes >= 2) {
+    for (int64_t i = 0; i < nc; ++i) {
+      if (!c[i].alive) continue;
+      for (int64_t j = i + 1; j < nc; ++j) {
+        if (!c[j].alive) continue;
+        int related = 0;
+        for (int32_t x = 2; x <= harmonic_primes && !related; ++x) {
+          int prime = 1;
+          for (int32_t q = 2; q * q <= x; ++q)
+            if (x % q == 0) prime = 0;
+          if (!prime) continue;
+          for (int32_t nn = 1; nn < x && !related; ++nn) {
+            double r1 = c[i].period * (double)nn / (double)x;
+            double r2 = c[i].period * (double)x / (double)nn;
+            if (fabs(c[j].period - r1) <= (double)harmonic_tol * r1) related = 1;
+            if (fabs(c[j].period - r2) <= (double)harmonic_tol * r2) related = 1;
+          }
+        }
+        if (related) c[j].alive = 0;
+      }
+    }
+  }
+  int64_t k = 0;
+  for (int64_t i = 0; i < nc; ++i) {
+    if (!c[i].alive) continue;
+    out_trial[k] = c[i].trial;
+    out_period[k] = c[i].period;
+    out_snr[k] = c[i].snr;
+    out_width[k] = c[i].width;
+    ++k;
+  }
+  free(c);
+  return k;
+}
+
 double oracle_mad_constant(void) { return ORACLE_K; }

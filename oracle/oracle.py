@@ -96,6 +96,12 @@ def _configure(lib):
     lib.oracle_dered_default_window.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oracle_deredden_f64.restype = ctypes.c_int
     lib.oracle_deredden_f64.argtypes = [f64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, f64p]
+    lib.oracle_sift.restype = ctypes.c_int64
+    lib.oracle_sift.argtypes = [ctypes.POINTER(ctypes.c_float), i32p, ctypes.c_int64, ctypes.c_int32,
+                                i32p, i32p, i32p, i32p, i64p, ctypes.c_double,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_int32, ctypes.c_float, i64p, f64p,
+                                ctypes.POINTER(ctypes.c_float), i32p]
     lib.oracle_mad_constant.restype = ctypes.c_double
     return lib
 
@@ -299,3 +305,31 @@ def search(series: np.ndarray, p: Plan, widths=None, alg: int = ALG1, steps=None
     if rc != 0:
         raise ValueError("oracle_search failed")
     return snr, wid
+
+
+SIFT_DTYPE = np.dtype([("trial", "<i8"), ("period", "<f8"), ("snr", "<f4"), ("width", "<i4")])
+
+
+def sift(snr: np.ndarray, width: np.ndarray, p: Plan, min_snr: float = 9.0, frac_fall: float = 0.1,
+         abs_fall: float = 1.0, group_widths: float = 0.0, harmonic_primes: int = 0,
+         harmonic_tol: float = 1e-5) -> np.ndarray:
+    """Candidates of a periodogram (see oracle_sift), strongest first."""
+    lib = _load()
+    s = np.ascontiguousarray(snr, dtype=np.float32)
+    w = np.ascontiguousarray(width, dtype=np.int32)
+    n = s.size
+    tr = np.zeros(max(n, 1), np.int64)
+    pe = np.zeros(max(n, 1), np.float64)
+    sn = np.zeros(max(n, 1), np.float32)
+    wi = np.zeros(max(n, 1), np.int32)
+    i32 = ctypes.c_int32
+    k = lib.oracle_sift(_ptr(s, ctypes.c_float), _ptr(w, i32), n, p.n_steps, _ptr(p.f, i32),
+                        _ptr(p.P0, i32), _ptr(p.m, i32), _ptr(p.M, i32), _ptr(p.first, ctypes.c_int64),
+                        p.tsamp, min_snr, frac_fall, abs_fall, group_widths, harmonic_primes,
+                        harmonic_tol, _ptr(tr, ctypes.c_int64), _ptr(pe, ctypes.c_double),
+                        _ptr(sn, ctypes.c_float), _ptr(wi, i32))
+    if k < 0:
+        raise ValueError("bad sift arguments")
+    out = np.zeros(k, SIFT_DTYPE)
+    out["trial"], out["period"], out["snr"], out["width"] = tr[:k], pe[:k], sn[:k], wi[:k]
+    return out

@@ -370,6 +370,80 @@ def pin_dered_search_recovers(o):
     assert abs(best - P) < 0.5, best
 
 
+# ------------------------------------------------ candidate sifting
+
+def _one_step_plan(o, P0, m, M, f=1, tsamp=1e-3):
+    return o.Plan(np.array([f], np.int32), np.array([P0], np.int32), np.array([m], np.int32),
+                  np.array([M], np.int32), np.array([0], np.int64), tsamp)
+
+
+def pin_sift_thresholds(o):
+    """The three thresholds of ffa2best (Sec. 2.3.3), traced by hand: with
+    min 9, fractional fall 10% and absolute fall 1, the periodogram below
+    gives candidates at trials 2 (12), 6 (13), 10 (20) and 15 (9.1).  Trial
+    4 has fallen 1.5 from 12 (past both), trial 7 drops below 9, trial 11
+    falls only 1 from 20 (not 10%), trial 13 drops below 9."""
+    snr = np.array([0, 10, 12, 11.5, 10.5, 11, 13, 5, 9.5, 9.4, 20, 19, 19.5, 3, 9, 9.1], np.float32)
+    wid = np.full(16, 3, np.int32)
+    p = _one_step_plan(o, 100, 16, 16)
+    c = o.sift(snr, wid, p, min_snr=9.0, frac_fall=0.1, abs_fall=1.0)
+    assert list(c["trial"]) == [10, 6, 2, 15], list(c["trial"])
+    assert list(c["snr"]) == [20.0, 13.0, 12.0, np.float32(9.1)]
+    P = 1e-3 * (100 + np.array([10, 6, 2, 15]) / 15.0)
+    assert np.allclose(c["period"], P, rtol=1e-15, atol=0)
+
+
+def pin_sift_grouping(o):
+    """A strong candidate of width 10 bins (10 ms) at P ~ 0.5 s folded over
+    500 s smears by one width when the period is off by 10 ms * 0.5 / 500 =
+    1e-5 s, about 10.2 trials of 1/1023 ms: a weaker peak 8 trials away is
+    grouped into it, one 15 trials away is not."""
+    M = 1024
+    snr = np.zeros(M, np.float32)
+    wid = np.full(M, 10, np.int32)
+    snr[100], snr[108], snr[115] = 30.0, 12.0, 12.5
+    p = _one_step_plan(o, 500, 1000, M)
+    c = o.sift(snr, wid, p, min_snr=9.0, group_widths=1.0)
+    assert list(c["trial"]) == [100, 115], list(c["trial"])
+    c0 = o.sift(snr, wid, p, min_snr=9.0, group_widths=0.0)
+    assert list(c0["trial"]) == [100, 115, 108]
+
+
+def pin_sift_harmonics(o):
+    """Harmonic matching with the fractions n/x, x prime (Sec. 2.3.3): the
+    strongest period 0.6 s removes 0.3 (x1/2), 0.4 (x2/3), 1.8 (x3/1) and
+    3/7 s (x5/7, only with primes up to 7); 0.55 s (11/12) stays."""
+    # one step per period, trial k = 0 (or k = 4 of M = 8 for 428 + 4/7 ms)
+    f = np.array([1, 1, 1, 1, 1, 4], np.int32)
+    P0 = np.array([300, 400, 428, 550, 600, 450], np.int32)
+    M = np.full(6, 8, np.int32)
+    first = np.arange(6, dtype=np.int64) * 8
+    p = o.Plan(f, P0, M.copy(), M, first, 1e-3)
+    snr = np.zeros(48, np.float32)
+    wid = np.full(48, 2, np.int32)
+    for step, k, v in ((0, 0, 15.0), (1, 0, 14.0), (2, 4, 13.0), (3, 0, 12.0), (4, 0, 30.0), (5, 0, 11.0)):
+        snr[first[step] + k] = v
+    c7 = o.sift(snr, wid, p, min_snr=9.0, harmonic_primes=7, harmonic_tol=1e-5)
+    assert np.allclose(c7["period"], [0.6, 0.55]), c7
+    c5 = o.sift(snr, wid, p, min_snr=9.0, harmonic_primes=5, harmonic_tol=1e-5)
+    assert np.allclose(sorted(c5["period"]), sorted([0.6, 3.0 / 7.0, 0.55])), c5
+    c0 = o.sift(snr, wid, p, min_snr=9.0)
+    assert c0.size == 6
+
+
+def pin_sift_recovers_pulsar(o):
+    """Workload-1 style search: the injected 733.3-sample pulsar is the top
+    candidate after thresholds, grouping and harmonic matching."""
+    g = np.random.default_rng(27)
+    N, ts = 65536, 1e-3
+    t = np.arange(N)
+    x = g.standard_normal(N) + 0.45 * np.exp(-0.5 * (((t % 733.3) - 300.0) / 9.0) ** 2)
+    p = o.plan(N, ts, 0.5, 1.0, 500)
+    snr, wid = o.search(x.astype(np.float32), p, [1, 2, 4, 8, 16, 32])
+    c = o.sift(snr, wid, p, min_snr=6.0, group_widths=1.0, harmonic_primes=31, harmonic_tol=1e-5)
+    assert abs(c["period"][0] / ts - 733.3) < 0.5, c[:3]
+
+
 # ---------------------------------------------------- plan / downsample
 
 def pin_downsample(o):
@@ -446,6 +520,10 @@ ALL_PINS = [
     pin_dered_default_window,
     pin_dered_offset_and_constant,
     pin_dered_search_recovers,
+    pin_sift_thresholds,
+    pin_sift_grouping,
+    pin_sift_harmonics,
+    pin_sift_recovers_pulsar,
     pin_default_widths,
     pin_downsample,
     pin_plan,

@@ -42,6 +42,13 @@ MUTATIONS = [
      "med[c] = buf[cnt / 2];"),
     ("dered_no_interp", "if (c + 1 < nk) b += (med[c + 1] - med[c])", "if (c + 1 < 0) b += (med[c + 1] - med[c])"),
     ("dered_default_2x", "double w4 = 4.0 * pmin / tsamp;", "double w4 = 2.0 * pmin / tsamp;"),
+    ("sift_fall_either", "} else if (cur->snr - s >= frac_fall * cur->snr && cur->snr - s >= abs_fall) {",
+     "} else if (cur->snr - s >= frac_fall * cur->snr || cur->snr - s >= abs_fall) {"),
+    ("sift_no_climb", "    if (s > cur->snr) {\n      cur->trial = t;", "    if (0) {\n      cur->trial = t;"),
+    ("sift_low_keeps_open", "    if (!(s >= min_snr)) {\n      open = 0;\n      continue;",
+     "    if (!(s >= min_snr)) {\n      continue;"),
+    ("sift_group_no_span", "c[i].wsec * c[i].period / c[i].span;", "c[i].wsec;"),
+    ("sift_harm_one_side", "if (fabs(c[j].period - r2) <= (double)harmonic_tol * r2) related = 1;", ""),
 ]
 
 
