@@ -174,6 +174,51 @@ ffa_status ffa_fold(ffa_plan plan, const void* d_series, int32_t step,
 ffa_status ffa_best(const float* d_snr, int64_t n_trials, int64_t* d_best,
                     void* stream);
 
+/* Candidate sifting of a periodogram on the GPU, after the paper's ffa2best
+ * (Sec. 2.3.3; the settings of Sec. 4 are min_snr 9, primes up to 31,
+ * tolerance 1e-5 for Algorithm 1 and 1e-4 for Algorithm 2).  The paper does
+ * not give the exact rules; the ones used:
+ *   peaks: trials in plan order (period non-decreasing); a trial with
+ *     S/N >= min_snr opens a candidate when none is open; a higher S/N moves
+ *     the open candidate there; it closes once the S/N has fallen from it by
+ *     at least frac_fall * its S/N and by at least abs_fall, or below min_snr
+ *     (NaN counts as below).
+ *   grouping (group_widths > 0): strongest first (ties: lower trial), a
+ *     surviving candidate removes weaker ones whose period differs by at most
+ *     group_widths * W * P / T, W its boxcar width in seconds and T the
+ *     folded span m*P0*f*tsamp of its step (the smear of one pulse width
+ *     per group_widths across the data).
+ *   harmonics (harmonic_primes >= 2): strongest first, a surviving candidate
+ *     removes weaker ones within a relative harmonic_tol of P*n/x or P*x/n,
+ *     x prime <= harmonic_primes, 0 < n < x. */
+typedef struct {
+  float min_snr;
+  float frac_fall;
+  float abs_fall;
+  float group_widths;
+  int32_t harmonic_primes;
+  float harmonic_tol;
+} ffa_sift_params;
+
+typedef struct {
+  int64_t trial;     /* index in the periodogram */
+  double period_s;   /* f*tsamp*(P0 + k/(M-1)) */
+  float snr;
+  int32_t width;     /* boxcar width in bins of the step's octave */
+} ffa_candidate;
+
+/* Sift the periodogram (d_snr, d_width: n_trials entries of `plan`) into
+ * d_cands (device, room for max_cands), strongest first.  *d_n_cands
+ * (device) receives the number of candidates found (only the first max_cands
+ * are written), or -1 when more than 16384 peaks pass the thresholds (raise
+ * min_snr).  The plan's workspace is used as scratch (its contents are not
+ * needed after a search).  Asynchronous on `stream`.  Errors:
+ * FFA_ERR_INVALID (bad parameter, small workspace), FFA_ERR_DEVICE. */
+ffa_status ffa_sift(ffa_plan plan, const float* d_snr, const int32_t* d_width,
+                    const ffa_sift_params* params, ffa_candidate* d_cands,
+                    int32_t max_cands, int32_t* d_n_cands, void* d_ws,
+                    size_t ws_bytes, void* stream);
+
 /* Batched search: the periodograms of n series, each with its own plan (any
  * mix of sample types).  The series are spread over a few streams that the
  * library owns on the current GPU, which wait for earlier work on `stream`

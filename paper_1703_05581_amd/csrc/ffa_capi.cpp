@@ -1,4 +1,5 @@
 // C ABI entry points that enqueue GPU work: prepare, search, fold, best.
+#include <cmath>
 #include <cstdint>
 
 #include "ffa_internal.h"
@@ -159,6 +160,28 @@ extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, v
     if (s != FFA_OK) return s;
   }
   return FFA_OK;
+}
+
+extern "C" ffa_status ffa_sift(ffa_plan p, const float* d_snr, const int32_t* d_width,
+                               const ffa_sift_params* prm, ffa_candidate* d_cands, int32_t max_cands,
+                               int32_t* d_n_cands, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!p || !d_snr || !d_width || !prm || !d_n_cands || (max_cands > 0 && !d_cands))
+    return fail(FFA_ERR_INVALID, "null argument");
+  if (max_cands < 0) return fail(FFA_ERR_INVALID, "max_cands must be >= 0");
+  if (!std::isfinite(prm->min_snr) || !(prm->frac_fall >= 0.0f && prm->frac_fall <= 1.0f) ||
+      !(prm->abs_fall >= 0.0f) || !std::isfinite(prm->abs_fall) || !(prm->group_widths >= 0.0f) ||
+      !std::isfinite(prm->group_widths) || prm->harmonic_primes > 1000 || !(prm->harmonic_tol >= 0.0f) ||
+      !std::isfinite(prm->harmonic_tol))
+    return fail(FFA_ERR_INVALID, "bad sift parameters");
+  ffa_status s = check_ws(p->ws_bytes, d_ws, ws_bytes);
+  if (s != FFA_OK) return s;
+  const DeviceTables* dt = nullptr;
+  s = device_tables(p, &dt);
+  if (s != FFA_OK) return s;
+  return check_hip(launch_sift(d_snr, d_width, p->n_trials, *prm, dt->steps, (int32_t)p->steps.size(),
+                               p->desc.tsamp_s, d_ws, p->ring_off, d_cands, max_cands, d_n_cands,
+                               reinterpret_cast<hipStream_t>(stream)),
+                   "sift kernels");
 }
 
 extern "C" ffa_status ffa_best(const float* d_snr, int64_t n_trials, int64_t* d_best, void* stream) {

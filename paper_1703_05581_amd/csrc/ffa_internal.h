@@ -99,9 +99,19 @@ struct Launch {
   int32_t max_P0;
 };
 
+// A step as the candidate sifting needs it (trial -> period).
+struct StepDev {
+  int64_t first_trial;
+  int32_t f, P0, m, M;
+};
+
+constexpr int32_t kSiftMaxPeaks = 16384;
+constexpr int kSiftBlock = 1024;  // trials per block of the compaction
+
 // Device copies of a plan's tables (made on first use on a device).
 struct DeviceTables {
   int device = -1;
+  StepDev* steps = nullptr;
   Phase* phases = nullptr;
   Phase* fold_phases = nullptr;
   int32_t* tile_phase = nullptr;
@@ -141,6 +151,7 @@ struct ffa_plan_s {
   int64_t knots_off = 0;                // workspace: knot medians (double) of one octave series
   std::vector<int64_t> raw_off;         // float input, dereddened: raw octave series in double
   int64_t ring_off = 0;                 // workspace: series region, knots, then the ring
+  int64_t sift_elems = 0;               // scratch of ffa_sift, from ring_off
   size_t ws_bytes = 0;
   int32_t select_iters = 64;            // counting rounds before key halving
   int32_t select_cand = 64;             // candidates handed to the in-lane select
@@ -186,5 +197,9 @@ bool tiles_fit(int is_int, int max_P0, int lds_bytes, int alg);
 hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
                         void* ws, hipStream_t st);
 hipError_t launch_best(const float* snr, int64_t n, int64_t* best, hipStream_t st);
+// Candidate sifting (ffa_sift); scratch at element `scratch` of ws.
+hipError_t launch_sift(const float* snr, const int32_t* width, int64_t n, const ffa_sift_params& prm,
+                       const StepDev* steps, int32_t n_steps, double tsamp, void* ws, int64_t scratch,
+                       ffa_candidate* out, int32_t max_out, int32_t* n_out, hipStream_t st);
 
 }  // namespace ffa

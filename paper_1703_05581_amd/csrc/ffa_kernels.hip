@@ -986,6 +986,243 @@ __global__ void best_final_kernel(int64_t* __restrict__ best) {
   *best = (int64_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
 }
 
+// ------------------------------------------------------ candidate sifting
+//
+// After the paper's ffa2best (Sec. 2.3.3), with the rules stated in ffa.h:
+// the trials at or above min_snr are compacted in order (count, scan, write),
+// one workgroup scans them for peaks, then one workgroup ranks the peaks and
+// applies grouping and harmonic matching.  Periods and limits are computed in
+// double with the operations in a fixed order (no contraction), so the
+// decisions do not depend on the compiler.
+
+__global__ __launch_bounds__(kSiftBlock) void sift_count_kernel(const float* __restrict__ snr, int64_t n,
+                                                                float min_snr, int32_t* __restrict__ counts) {
+  const int64_t t = (int64_t)blockIdx.x * kSiftBlock + threadIdx.x;
+  const bool keep = t < n && snr[t] >= min_snr;
+  const int c = __syncthreads_count(keep);
+  if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+// exclusive prefix of counts[0..nb) into offs[0..nb], offs[nb] = total
+__global__ __launch_bounds__(1024) void sift_scan_kernel(const int32_t* __restrict__ counts, int64_t nb,
+                                                         int32_t* __restrict__ offs) {
+  __shared__ int32_t buf[1024];
+  int32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = i < nb ? counts[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int32_t a = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < nb) offs[i] = carry + buf[threadIdx.x] - v;
+    carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) offs[nb] = carry;
+}
+
+__global__ __launch_bounds__(kSiftBlock) void sift_write_kernel(const float* __restrict__ snr, int64_t n,
+                                                                float min_snr, const int32_t* __restrict__ offs,
+                                                                int32_t* __restrict__ ctrial,
+                                                                float* __restrict__ csnr) {
+  __shared__ int32_t wsum[kSiftBlock / kWave];
+  const int64_t t = (int64_t)blockIdx.x * kSiftBlock + threadIdx.x;
+  const float v = t < n ? snr[t] : 0.0f;
+  const bool keep = t < n && v >= min_snr;
+  const uint64_t m = __ballot(keep);
+  const int w = threadIdx.x / kWave;
+  const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  if (lane_id() == 0) wsum[w] = __popcll(m);
+  __syncthreads();
+  int before = offs[blockIdx.x];
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  if (keep) {
+    ctrial[before + rank] = (int32_t)t;
+    csnr[before + rank] = v;
+  }
+}
+
+// Peaks of the compacted list (one workgroup; thread 0 scans chunks staged in
+// LDS).  info[0] = peaks found (more than kSiftMaxPeaks: -1).
+__global__ __launch_bounds__(1024) void sift_peaks_kernel(const int32_t* __restrict__ ctrial,
+                                                          const float* __restrict__ csnr,
+                                                          const int32_t* __restrict__ total_p, float frac_fall,
+                                                          float abs_fall, int32_t* __restrict__ ptrial,
+                                                          float* __restrict__ psnr, int32_t* __restrict__ info) {
+#pragma clang fp contract(off)
+  constexpr int kChunk = 4096;
+  __shared__ int32_t st[kChunk];
+  __shared__ float ss[kChunk];
+  const int32_t total = *total_p;
+  int32_t np = 0, prev = -2;
+  bool open = false, over = false;
+  int32_t cur_t = 0;
+  float cur_s = 0.0f;
+  for (int32_t base = 0; base < total; base += kChunk) {
+    const int32_t cnt = total - base < kChunk ? total - base : kChunk;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+      st[i] = ctrial[base + i];
+      ss[i] = csnr[base + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < cnt; ++i) {
+        const int32_t t = st[i];
+        const float s = ss[i];
+        if (t != prev + 1) {  // a trial below min_snr lies in between: close
+          if (open) {
+            if (np < kSiftMaxPeaks) {
+              ptrial[np] = cur_t;
+              psnr[np] = cur_s;
+            }
+            ++np;
+          }
+          open = false;
+        }
+        prev = t;
+        if (!open) {
+          open = true;
+          cur_t = t;
+          cur_s = s;
+        } else if (s > cur_s) {
+          cur_t = t;
+          cur_s = s;
+        } else {
+          const float fall = cur_s - s;
+          if (fall >= frac_fall * cur_s && fall >= abs_fall) {
+            if (np < kSiftMaxPeaks) {
+              ptrial[np] = cur_t;
+              psnr[np] = cur_s;
+            }
+            ++np;
+            open = false;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (open) {
+      if (np < kSiftMaxPeaks) {
+        ptrial[np] = cur_t;
+        psnr[np] = cur_s;
+      }
+      ++np;
+    }
+    over = np > kSiftMaxPeaks;
+    info[0] = over ? -1 : np;
+  }
+}
+
+__device__ __forceinline__ bool is_prime(int32_t x) {
+  if (x < 2) return false;
+  for (int32_t q = 2; q * q <= x; ++q)
+    if (x % q == 0) return false;
+  return true;
+}
+
+// Rank, group, match harmonics, write the survivors (one workgroup).
+__global__ __launch_bounds__(1024) void sift_final_kernel(
+    const int32_t* __restrict__ ptrial, const float* __restrict__ psnr, const int32_t* __restrict__ info,
+    const int32_t* __restrict__ width, const StepDev* __restrict__ steps, int32_t n_steps, double tsamp,
+    float group_widths, int32_t harmonic_primes, float harmonic_tol, double* __restrict__ period,
+    double* __restrict__ lim, int32_t* __restrict__ order, int32_t* __restrict__ alive,
+    ffa_candidate* __restrict__ out, int32_t max_out, int32_t* __restrict__ n_out) {
+#pragma clang fp contract(off)
+  const int32_t np = info[0];
+  if (np < 0) {
+    if (threadIdx.x == 0) *n_out = -1;
+    return;
+  }
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const int64_t t = ptrial[i];
+    int lo = 0, hi = n_steps - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (steps[mid].first_trial <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const StepDev s = steps[lo];
+    const int64_t k = t - s.first_trial;
+    const double fts = (double)s.f * tsamp;
+    const double P = fts * ((double)s.P0 + (double)k / (double)(s.M - 1));
+    const double span = fts * (double)s.m * (double)s.P0;
+    const double wsec = fts * (double)width[t];
+    period[i] = P;
+    lim[i] = (double)group_widths * wsec * P / span;
+    alive[i] = 1;
+    // rank: stronger first, lower trial first on ties
+    int32_t r = 0;
+    const float si = psnr[i];
+    for (int j = 0; j < np; ++j) {
+      const float sj = psnr[j];
+      r += (sj > si || (sj == si && ptrial[j] < ptrial[i])) ? 1 : 0;
+    }
+    order[r] = i;
+  }
+  __syncthreads();
+  if (group_widths > 0.0f) {
+    for (int r = 0; r < np; ++r) {
+      const int i = order[r];
+      if (alive[i]) {
+        for (int r2 = r + 1 + threadIdx.x; r2 < np; r2 += blockDim.x) {
+          const int j = order[r2];
+          if (alive[j] && fabs(period[j] - period[i]) <= lim[i]) alive[j] = 0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (harmonic_primes >= 2) {
+    for (int r = 0; r < np; ++r) {
+      const int i = order[r];
+      if (alive[i]) {
+        const double Pi = period[i];
+        for (int r2 = r + 1 + threadIdx.x; r2 < np; r2 += blockDim.x) {
+          const int j = order[r2];
+          if (!alive[j]) continue;
+          const double Pj = period[j];
+          bool related = false;
+          for (int32_t x = 2; x <= harmonic_primes && !related; ++x) {
+            if (!is_prime(x)) continue;
+            for (int32_t nn = 1; nn < x && !related; ++nn) {
+              const double r1 = Pi * (double)nn / (double)x;
+              const double r2v = Pi * (double)x / (double)nn;
+              if (fabs(Pj - r1) <= (double)harmonic_tol * r1) related = true;
+              if (fabs(Pj - r2v) <= (double)harmonic_tol * r2v) related = true;
+            }
+          }
+          if (related) alive[j] = 0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    int32_t k = 0;
+    for (int r = 0; r < np; ++r) {
+      const int i = order[r];
+      if (!alive[i]) continue;
+      if (k < max_out) {
+        ffa_candidate c;
+        c.trial = ptrial[i];
+        c.period_s = period[i];
+        c.snr = psnr[i];
+        c.width = width[ptrial[i]];
+        out[k] = c;
+      }
+      ++k;
+    }
+    *n_out = k;
+  }
+}
+
 }  // namespace
 
 // --------------------------------------------------------------- launchers
@@ -1146,6 +1383,34 @@ hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int ma
   else FFA_LAUNCH_ALG(1);
 #undef FFA_LAUNCH_ALG
 #undef FFA_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_sift(const float* snr, const int32_t* width, int64_t n, const ffa_sift_params& prm,
+                       const StepDev* steps, int32_t n_steps, double tsamp, void* ws, int64_t scratch,
+                       ffa_candidate* out, int32_t max_out, int32_t* n_out, hipStream_t st) {
+  if (n < 1 || n > 0x7fffffff) return hipErrorInvalidValue;
+  auto up = [](int64_t v) { return (v + 63) / 64 * 64; };
+  const int64_t nb = (n + kSiftBlock - 1) / kSiftBlock;
+  float* w = reinterpret_cast<float*>(ws) + scratch;
+  int32_t* ctrial = reinterpret_cast<int32_t*>(w);
+  float* csnr = w + n;
+  int32_t* counts = reinterpret_cast<int32_t*>(w + up(2 * n));
+  int32_t* offs = counts + up(nb + 1);
+  int32_t* info = offs + up(nb + 1);
+  int32_t* ptrial = info + 64;
+  float* psnr = reinterpret_cast<float*>(ptrial + kSiftMaxPeaks);
+  double* period = reinterpret_cast<double*>(psnr + kSiftMaxPeaks);  // 8-byte aligned: offsets above are even
+  double* lim = period + kSiftMaxPeaks;
+  int32_t* order = reinterpret_cast<int32_t*>(lim + kSiftMaxPeaks);
+  int32_t* alive = order + kSiftMaxPeaks;
+  sift_count_kernel<<<(unsigned)nb, kSiftBlock, 0, st>>>(snr, n, prm.min_snr, counts);
+  sift_scan_kernel<<<1, 1024, 0, st>>>(counts, nb, offs);
+  sift_write_kernel<<<(unsigned)nb, kSiftBlock, 0, st>>>(snr, n, prm.min_snr, offs, ctrial, csnr);
+  sift_peaks_kernel<<<1, 1024, 0, st>>>(ctrial, csnr, offs + nb, prm.frac_fall, prm.abs_fall, ptrial, psnr, info);
+  sift_final_kernel<<<1, 1024, 0, st>>>(ptrial, psnr, info, width, steps, n_steps, tsamp, prm.group_widths,
+                                        prm.harmonic_primes, prm.harmonic_tol, period, lim, order, alive, out,
+                                        max_out, n_out);
   return hipGetLastError();
 }
 

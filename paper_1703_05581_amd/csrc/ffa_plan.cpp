@@ -242,17 +242,22 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
   const size_t pb = p->phases.size() * sizeof(Phase);
   const size_t fb = p->fold_phases.size() * sizeof(Phase);
   const size_t tb = p->tile_phase.size() * sizeof(int32_t);
+  std::vector<StepDev> sd;
+  for (const Step& st : p->steps) sd.push_back(StepDev{st.first_trial, st.f, st.P0, st.m, st.M});
+  const size_t sdb = sd.size() * sizeof(StepDev);
   const size_t wb = std::max<size_t>(p->wtab.size(), 1) * sizeof(int32_t);
   const size_t sb = std::max<size_t>(p->sqrtw.size(), 1) * sizeof(double);
   auto free_all = [&] {
     if (t.phases) (void)hipFree(t.phases);
     if (t.fold_phases) (void)hipFree(t.fold_phases);
     if (t.tile_phase) (void)hipFree(t.tile_phase);
+    if (t.steps) (void)hipFree(t.steps);
     if (t.widths) (void)hipFree(t.widths);
     if (t.sqrtw) (void)hipFree(t.sqrtw);
   };
   if (hipMalloc(&t.phases, pb) != hipSuccess || hipMalloc(&t.fold_phases, fb) != hipSuccess ||
-      hipMalloc(&t.tile_phase, tb) != hipSuccess || hipMalloc(&t.widths, wb) != hipSuccess || hipMalloc(&t.sqrtw, sb) != hipSuccess) {
+      hipMalloc(&t.tile_phase, tb) != hipSuccess || hipMalloc(&t.steps, sdb) != hipSuccess ||
+      hipMalloc(&t.widths, wb) != hipSuccess || hipMalloc(&t.sqrtw, sb) != hipSuccess) {
     free_all();
     return fail(FFA_ERR_NOMEM, "device tables: hipMalloc failed");
   }
@@ -263,6 +268,8 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
   if (st == FFA_OK)
     st = check_hip(hipMemcpy(t.tile_phase, p->tile_phase.data(), tb, hipMemcpyHostToDevice),
                    "upload tile map");
+  if (st == FFA_OK)
+    st = check_hip(hipMemcpy(t.steps, sd.data(), sdb, hipMemcpyHostToDevice), "upload steps");
   if (st == FFA_OK && !p->wtab.empty())
     st = check_hip(hipMemcpy(t.widths, p->wtab.data(), p->wtab.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice), "upload widths");
@@ -532,10 +539,16 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
       p->fold_phases.push_back(ph);
     }
   }
-  // workspace: series region, then the ring
+  // workspace: series region, then the ring (which ffa_sift reuses as scratch)
   p->ring_off = round_up(p->series_elems, 64);
   p->slot_elems = round_up(p->slot_elems, 64);
-  p->ws_bytes = (size_t)round_up((p->ring_off + (int64_t)p->n_slots * p->slot_elems) * 4, (int64_t)kWsAlign);
+  {
+    const int64_t nb = (p->n_trials + kSiftBlock - 1) / kSiftBlock;
+    p->sift_elems = round_up(2 * p->n_trials, 64) + 2 * round_up(nb + 1, 64) + 64 + 8 * (int64_t)kSiftMaxPeaks;
+  }
+  p->ws_bytes = (size_t)round_up(
+      std::max<int64_t>(p->ring_off + (int64_t)p->n_slots * p->slot_elems, p->ring_off + p->sift_elems) * 4,
+      (int64_t)kWsAlign);
   // test knobs: force the selection's fallback paths
   if (const char* e = std::getenv("FFA_SELECT_ITERS")) p->select_iters = std::max(0, std::atoi(e));
   if (const char* e = std::getenv("FFA_SELECT_CAND")) p->select_cand = std::min(64, std::max(1, std::atoi(e)));
@@ -556,6 +569,7 @@ extern "C" ffa_status ffa_plan_destroy(ffa_plan p) {
     (void)hipFree(t.phases);
     (void)hipFree(t.fold_phases);
     (void)hipFree(t.tile_phase);
+    (void)hipFree(t.steps);
     (void)hipFree(t.widths);
     (void)hipFree(t.sqrtw);
     if (t.device != cur && cur >= 0) (void)hipSetDevice(cur);

@@ -41,7 +41,7 @@ FFA_SNR_ALG2_OFFPULSE = 2
 EXPORTS = (
     "ffa_plan_create", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
     "ffa_plan_periods", "ffa_prepare", "ffa_search_prepared", "ffa_search", "ffa_fold", "ffa_best",
-    "ffa_batch_workspace",
+    "ffa_sift", "ffa_batch_workspace",
     "ffa_search_batch", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
     "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
 )
@@ -64,6 +64,28 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class SiftParams(ctypes.Structure):
+    _fields_ = [
+        ("min_snr", ctypes.c_float),
+        ("frac_fall", ctypes.c_float),
+        ("abs_fall", ctypes.c_float),
+        ("group_widths", ctypes.c_float),
+        ("harmonic_primes", ctypes.c_int32),
+        ("harmonic_tol", ctypes.c_float),
+    ]
+
+
+class Candidate(ctypes.Structure):
+    _fields_ = [
+        ("trial", ctypes.c_int64),
+        ("period_s", ctypes.c_double),
+        ("snr", ctypes.c_float),
+        ("width", ctypes.c_int32),
+    ]
+
+
+assert ctypes.sizeof(Candidate) == 24
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -81,6 +103,7 @@ _lib.ffa_prepare.argtypes = [_vp, _vp, _vp, _sz, _vp]
 _lib.ffa_search_prepared.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp]
 _lib.ffa_fold.argtypes = [_vp, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.ffa_best.argtypes = [_vp, _i64, _vp, _vp]
+_lib.ffa_sift.argtypes = [_vp, _vp, _vp, _P(SiftParams), _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.ffa_batch_workspace.argtypes = [_i32, _P(_vp), _P(_sz)]
 _lib.ffa_search_batch.argtypes = [_i32, _P(_vp), _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
 _lib.ffa_server_create.argtypes = [_sz, _i32, _P(_vp)]
@@ -263,6 +286,42 @@ class Plan:
         _check(_lib.ffa_fold(self._h, series.data_ptr(), step, out.data_ptr(), base, avail,
                              _stream_ptr(stream)), "ffa_fold")
         return out
+
+    def sift(self, snr, width, min_snr: float = 9.0, frac_fall: float = 0.1, abs_fall: float = 1.0,
+             group_widths: float = 0.0, harmonic_primes: int = 0, harmonic_tol: float = 1e-5,
+             max_cands: int = 1024, ws=None, stream=None, raw: bool = False):
+        """ffa_sift: candidates of a periodogram (cuda tensors from search()),
+        strongest first.  Returns a numpy record array (trial, period, snr,
+        width), or with ``raw`` the device buffer (max_cands, 24 bytes) and the
+        one-element int32 count, both on the GPU and not yet synchronised."""
+        import numpy as np
+        import torch
+
+        if snr.numel() != self.n_trials or width.numel() != self.n_trials:
+            raise ValueError("snr and width must hold n_trials entries")
+        if snr.dtype != torch.float32 or width.dtype != torch.int32:
+            raise ValueError("snr must be float32 and width int32")
+        dev = snr.device
+        if ws is None:
+            ws = self.workspace(dev)
+        base = self._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        prm = SiftParams(min_snr, frac_fall, abs_fall, group_widths, harmonic_primes, harmonic_tol)
+        cands = torch.empty((max(max_cands, 1), ctypes.sizeof(Candidate)), dtype=torch.uint8, device=dev)
+        n = torch.empty(1, dtype=torch.int32, device=dev)
+        _check(_lib.ffa_sift(self._h, snr.data_ptr(), width.data_ptr(), ctypes.byref(prm),
+                             cands.data_ptr(), max_cands, n.data_ptr(), base, avail,
+                             _stream_ptr(stream)), "ffa_sift")
+        if raw:
+            return cands, n
+        k = int(n.item())
+        if k < 0:
+            raise RuntimeError("ffa_sift: more than 16384 peaks pass the thresholds; raise min_snr")
+        k = min(k, max_cands)
+        host = cands[:k].cpu().numpy()
+        rec = np.frombuffer(host.tobytes(), dtype=np.dtype(
+            [("trial", "<i8"), ("period", "<f8"), ("snr", "<f4"), ("width", "<i4")]))
+        return rec.copy()
 
     def _check_series(self, series):
         import torch

@@ -172,3 +172,27 @@ def test_dered_plans():
     a = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2], "u8")
     b = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2], "u8", dered_window=-1)
     assert b.ws_bytes > a.ws_bytes and a.n_trials == b.n_trials
+
+
+def test_sift_argument_errors_before_gpu():
+    """ffa_sift checks its pointers, limits and workspace before any GPU call."""
+    p = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500)
+    lib = ffa.lib()
+    good = ffa.SiftParams(9.0, 0.1, 1.0, 2.0, 31, 1e-5)
+    fake = 4096
+    assert lib.ffa_sift(p.handle, None, fake, ctypes.byref(good), fake, 8, fake, fake, p.ws_bytes,
+                        None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_sift(p.handle, fake, fake, ctypes.byref(good), None, 8, fake, fake, p.ws_bytes,
+                        None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_sift(p.handle, fake, fake, ctypes.byref(good), fake, -1, fake, fake, p.ws_bytes,
+                        None) == ffa.FFA_ERR_INVALID
+    for field, value in [("frac_fall", 1.5), ("frac_fall", -0.1), ("abs_fall", -1.0),
+                         ("group_widths", float("inf")), ("harmonic_tol", -1e-3),
+                         ("min_snr", float("nan")), ("harmonic_primes", 5000)]:
+        bad = ffa.SiftParams(9.0, 0.1, 1.0, 2.0, 31, 1e-5)
+        setattr(bad, field, value)
+        assert lib.ffa_sift(p.handle, fake, fake, ctypes.byref(bad), fake, 8, fake, fake, p.ws_bytes,
+                            None) == ffa.FFA_ERR_INVALID, field
+    assert lib.ffa_sift(p.handle, fake, fake, ctypes.byref(good), fake, 8, fake, fake, 64,
+                        None) == ffa.FFA_ERR_INVALID
+    p.close()
