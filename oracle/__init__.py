@@ -23,4 +23,7 @@ from .oracle import (  # noqa: F401
     plan,
     search,
     sift,
+    sigma_gauss,
+    sigma_threshold,
+    snr_histogram,
 )

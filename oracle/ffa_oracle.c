@@ -20,7 +20,10 @@
  *   - Alg. 1    : Sec. 2.2.1 (median/MAD normalisation, Eqs. 3-4; boxcars
  *                 divided by sqrt(width); score = maximum);
  *   - Alg. 2    : Sec. 2.2.2 (boxcar first, 20% exclusion window around the
- *                 maximum, Eq. 5).
+ *                 maximum, Eq. 5);
+ *   - dereddening: Sec. 2.3.1 (running median, default window);
+ *   - sifting   : Sec. 2.3.3 (ffa2best's thresholds, grouping, harmonics);
+ *   - S/N histogram: Sec. 4.1.2 (false-alarm statistics).
  * Readings of points the paper leaves open are listed next to the code.
  *
  * Parity status: plan, downsampling, fold and Alg. 1 are pinned by the
@@ -781,6 +784,31 @@ int64_t oracle_sift(const float* snr, const int32_t* width, int64_t n_trials, in
   }
   free(c);
   return k;
+}
+
+/* ---------------------------------------------------------------------------
+ * False-alarm statistics (Sec. 4.1.2).  The paper maps each S/N value of a
+ * search of pure noise to a Gaussian-equivalent sigma through the fraction of
+ * trials that reach it.  The counting step is a histogram: bin b holds the
+ * values with floor((s - lo) * bins_per_unit) == b, the product taken in
+ * float; values below lo fall in bin 0 and values past the top in the last
+ * bin, so the count at or above every inner edge is exact.  NaN is not
+ * counted.  Counts are added to hist, so several searches accumulate. */
+void oracle_snr_histogram(const float* snr, int64_t n, float lo, float bins_per_unit, int32_t n_bins,
+                          uint64_t* hist) {
+  for (int64_t i = 0; i < n; ++i) {
+    float s = snr[i];
+    if (isnan(s)) continue;
+    float x = (s - lo) * bins_per_unit;
+    int32_t b;
+    if (!(x >= 0.0f))
+      b = 0;
+    else if (x >= (float)(n_bins - 1))
+      b = n_bins - 1;
+    else
+      b = (int32_t)floorf(x);
+    hist[b] += 1;
+  }
 }
 
 double oracle_mad_constant(void) { return ORACLE_K; }

@@ -102,6 +102,8 @@ def _configure(lib):
                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_int32, ctypes.c_float, i64p, f64p,
                                 ctypes.POINTER(ctypes.c_float), i32p]
+    lib.oracle_snr_histogram.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
     lib.oracle_mad_constant.restype = ctypes.c_double
     return lib
 
@@ -333,3 +335,58 @@ def sift(snr: np.ndarray, width: np.ndarray, p: Plan, min_snr: float = 9.0, frac
     out = np.zeros(k, SIFT_DTYPE)
     out["trial"], out["period"], out["snr"], out["width"] = tr[:k], pe[:k], sn[:k], wi[:k]
     return out
+
+
+# ------------------------------------------------ false-alarm statistics
+
+def snr_histogram(snr: np.ndarray, lo: float, bins_per_unit: float, n_bins: int,
+                  hist: np.ndarray | None = None) -> np.ndarray:
+    """Counts of S/N values per bin (see oracle_snr_histogram), added to
+    ``hist`` (uint64) when given."""
+    s = np.ascontiguousarray(snr, dtype=np.float32).ravel()
+    if hist is None:
+        hist = np.zeros(n_bins, np.uint64)
+    if hist.dtype != np.uint64 or hist.size != n_bins or not hist.flags.c_contiguous:
+        raise ValueError("hist must be a contiguous uint64 array of n_bins counts")
+    _load().oracle_snr_histogram(_ptr(s, ctypes.c_float), s.size, lo, bins_per_unit, n_bins,
+                                 _ptr(hist, ctypes.c_uint64))
+    return hist
+
+
+def _tails(hist: np.ndarray) -> np.ndarray:
+    """tail[b] = number of values in bins b and above (exact integers)."""
+    h = np.asarray(hist, dtype=np.uint64)
+    return np.cumsum(h[::-1], dtype=np.uint64)[::-1]
+
+
+def sigma_gauss(hist: np.ndarray) -> np.ndarray:
+    """Gaussian-equivalent sigma at the lower edge of every bin (Sec. 4.1.2):
+    the fraction Q of values at or above the edge, mapped through the normal
+    quantile so that a standard normal variable exceeds sigma with
+    probability Q.  Bin 0 (Q = 1) maps to -inf, an edge no value reaches to
+    +inf."""
+    from scipy.stats import norm
+
+    tail = _tails(hist)
+    total = float(tail[0])
+    if total <= 0:
+        raise ValueError("empty histogram")
+    return norm.isf(tail.astype(np.float64) / total)
+
+
+def sigma_threshold(hist: np.ndarray, lo: float, bins_per_unit: float, sigma: float) -> float:
+    """The S/N that a sigma-sigma detection needs (Sec. 4.1.2): the lowest
+    inner bin edge lo + b / bins_per_unit (b >= 1) at or above which at most
+    a fraction Phi(-sigma) of the values lie (count <= Phi(-sigma) * total,
+    in double)."""
+    from scipy.stats import norm
+
+    tail = _tails(hist)
+    total = float(tail[0])
+    if total <= 0:
+        raise ValueError("empty histogram")
+    limit = float(norm.sf(sigma)) * total
+    for b in range(1, tail.size):
+        if float(tail[b]) <= limit:
+            return float(lo) + float(b) / float(bins_per_unit)
+    raise ValueError("the histogram's top bin holds more than the allowed fraction; widen it")

@@ -444,6 +444,95 @@ def pin_sift_recovers_pulsar(o):
     assert abs(c["period"][0] / ts - 733.3) < 0.5, c[:3]
 
 
+# ------------------------------------------------ false-alarm statistics
+
+def pin_hist_library(o):
+    """The S/N histogram against numpy's, on values at bin centres, with
+    values beyond either end (clamped into the end bins) and NaNs (dropped)."""
+    g = np.random.default_rng(31)
+    lo, bpu, nb = -8.0, 64.0, 700
+    b = g.integers(-200, nb + 200, 50000)
+    v = (lo + (b + 0.5) / bpu).astype(np.float32)
+    v[:5] = [np.nan, np.inf, -np.inf, 1e30, -1e30]
+    h = o.snr_histogram(v, lo, bpu, nb)
+    edges = np.concatenate([[-np.inf], lo + np.arange(1, nb) / bpu, [np.inf]])
+    ref, _ = np.histogram(v[~np.isnan(v)].astype(np.float64), bins=edges)
+    assert np.array_equal(h, ref.astype(np.uint64))
+    assert int(h.sum()) == v.size - 1
+    # accumulation: a second call adds
+    h2 = o.snr_histogram(v, lo, bpu, nb, h.copy())
+    assert np.array_equal(h2, 2 * h)
+
+
+def pin_hist_edges(o):
+    """Bins are half-open [edge, next edge): an exact edge value opens its
+    bin, the float just below it stays in the bin before."""
+    lo, bpu = -8.0, 256.0
+    e3 = np.float32(lo + 3 / bpu)
+    v = np.array([lo, e3, np.nextafter(e3, np.float32(-9)), lo + 63 / bpu, lo + 70 / bpu], np.float32)
+    h = o.snr_histogram(v, lo, bpu, 64)
+    assert list(np.nonzero(h)[0]) == [0, 2, 3, 63] and list(h[[0, 2, 3, 63]]) == [1, 1, 1, 2], h
+
+
+def pin_sigma_gauss_normal(o):
+    """For standard normal values the Gaussian-equivalent sigma of an S/N is
+    the S/N itself (closed form): the exact quantiles of N(0,1) give sigma
+    equal to every edge in [-3, 3]."""
+    from scipy.stats import norm
+
+    n = 1_000_000
+    z = norm.ppf((np.arange(n) + 0.5) / n).astype(np.float32)
+    lo, bpu, nb = -8.0, 64.0, 1024
+    h = o.snr_histogram(z, lo, bpu, nb)
+    sig = o.sigma_gauss(h)
+    edges = lo + np.arange(nb) / bpu
+    sel = (edges >= -3) & (edges <= 3)
+    assert np.max(np.abs(sig[sel] - edges[sel])) < 1e-3, np.max(np.abs(sig[sel] - edges[sel]))
+    assert sig[0] == -np.inf and np.all(np.diff(sig[sel]) > 0)
+    for k in (1.0, 2.0, 3.0):
+        assert abs(o.sigma_threshold(h, lo, bpu, k) - k) <= 1.0 / bpu + 1e-9
+
+
+def pin_sigma_threshold_tail(o):
+    """A 5-sigma threshold on 10^8 values allows Phi(-5) * 10^8 = 28.67 of
+    them at or above it.  With 29 values in bin 90 the threshold moves past
+    that bin (9.1); with 28 there, plus one in bin 50, the edge above bin 50
+    (5.1) is the first with at most 28.67 values at or above it."""
+    lo, bpu, nb = 0.0, 10.0, 100
+    for top, want in ((29, 9.1), (28, 5.1)):
+        h = np.zeros(nb, np.uint64)
+        h[0] = 10**8 - 1 - top
+        h[50] = 1
+        h[90] = top
+        assert abs(o.sigma_threshold(h, lo, bpu, 5.0) - want) < 1e-12, (top, o.sigma_threshold(h, lo, bpu, 5.0))
+    # sigma 0 is the median: half of 4 values at or above edge 2
+    h = np.zeros(10, np.uint64)
+    h[[1, 2, 3, 4]] = 1
+    assert o.sigma_threshold(h, 0.0, 1.0, 0.0) == 3.0
+
+
+def pin_null_white_noise(o):
+    """Loose check of the null distribution (Sec. 4.1.2): Algorithm 1 on one
+    white-noise profile behaves like the maximum of between n_bin (widths
+    fully correlated) and n_bin * n_fil independent normals, so the median
+    S/N of a white-noise search at P0 = 100..199 lies between
+    isf(ln 2 / 100) = 2.46 and isf(ln 2 / (199 * 7)) = 3.29."""
+    from scipy.stats import norm
+
+    g = np.random.default_rng(3)
+    N = 1 << 16
+    x = g.standard_normal(N).astype(np.float32)
+    p = o.plan(N, 1e-3, 0.1, 0.4, 100)
+    snr, _ = o.search(x, p, None)
+    h = o.snr_histogram(snr, -8.0, 64.0, 1024)
+    med = o.sigma_threshold(h, -8.0, 64.0, 0.0)
+    lo_b, hi_b = norm.isf(np.log(2) / 100), norm.isf(np.log(2) / (199 * 7))
+    assert lo_b < med < hi_b, (lo_b, med, hi_b)
+    # a higher sigma needs a higher S/N
+    t = [o.sigma_threshold(h, -8.0, 64.0, k) for k in (1.0, 2.0, 3.0)]
+    assert med < t[0] < t[1] < t[2], t
+
+
 # ---------------------------------------------------- plan / downsample
 
 def pin_downsample(o):
@@ -499,6 +588,11 @@ def pin_search_matches_parts(o):
 
 
 ALL_PINS = [
+    pin_hist_library,
+    pin_hist_edges,
+    pin_sigma_gauss_normal,
+    pin_sigma_threshold_tail,
+    pin_null_white_noise,
     pin_fold_worked_example,
     pin_fold_closed_forms,
     pin_fold_invariants,

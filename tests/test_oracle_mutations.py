@@ -42,6 +42,9 @@ MUTATIONS = [
      "med[c] = buf[cnt / 2];"),
     ("dered_no_interp", "if (c + 1 < nk) b += (med[c + 1] - med[c])", "if (c + 1 < 0) b += (med[c + 1] - med[c])"),
     ("dered_default_2x", "double w4 = 4.0 * pmin / tsamp;", "double w4 = 2.0 * pmin / tsamp;"),
+    ("hist_round", "      b = (int32_t)floorf(x);", "      b = (int32_t)roundf(x);"),
+    ("hist_drop_top", "      b = n_bins - 1;\n    else", "      continue;\n    else"),
+    ("hist_nan_counted", "    if (isnan(s)) continue;\n    float x", "    if (isnan(s)) s = lo;\n    float x"),
     ("sift_fall_either", "} else if (cur->snr - s >= frac_fall * cur->snr && cur->snr - s >= abs_fall) {",
      "} else if (cur->snr - s >= frac_fall * cur->snr || cur->snr - s >= abs_fall) {"),
     ("sift_no_climb", "    if (s > cur->snr) {\n      cur->trial = t;", "    if (0) {\n      cur->trial = t;"),
