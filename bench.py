@@ -57,7 +57,7 @@ def parse():
                     help="with --pmc-summary: searches the profiled run made")
     ap.add_argument("--alg", type=int, choices=[1, 2], default=1,
                     help="profile score: 1 = Algorithm 1 (the headline), 2 = Algorithm 2")
-    ap.add_argument("--mode", choices=["search", "batch", "served"], default="search",
+    ap.add_argument("--mode", choices=["search", "batch", "served", "null"], default="search",
                     help="search: the headline line (default); batch: batched against plain "
                          "searches over workload-4 series; served: the request server under "
                          "Poisson arrivals of workload-5 requests")
@@ -201,6 +201,66 @@ def run_batch(a) -> dict:
             "speedup": res["plain"] / res["batched"], "outputs_equal": same}
 
 
+HIST_LO, HIST_BPU, HIST_BINS = -8.0, 256.0, 16384  # S/N -8 .. 56 in steps of 1/256
+
+
+def run_null(a) -> dict:
+    """False-alarm statistics of Sec. 4.1.2 on workload 6 (26 white-noise
+    series, about 10^8 trials): batched searches with Algorithms 1 and 2, the
+    S/N histogram of every periodogram on the GPU, then the S/N each
+    Gaussian-equivalent sigma needs.  One step = both algorithms over all
+    series, histograms included."""
+    import torch
+
+    from paper_1703_05581_amd import ffa, synth
+
+    series = [synth.workload6(i) for i in range(synth.NULL_SERIES)]
+    pa = series[0].plan
+    xs = [torch.from_numpy(s.data).cuda() for s in series]
+    plans = {alg: ffa.Plan.from_args(pa, snr=alg) for alg in (1, 2)}
+    nt = plans[1].n_trials
+    outs = [(torch.empty(nt, dtype=torch.float32, device="cuda"), torch.empty(nt, dtype=torch.int32, device="cuda"))
+            for _ in series]
+    wsb = torch.empty(max(ffa.batch_workspace_bytes([p] * len(series)) for p in plans.values()) + 256,
+                      dtype=torch.uint8, device="cuda")
+    hists = {alg: torch.zeros(HIST_BINS, dtype=torch.int64, device="cuda") for alg in (1, 2)}
+
+    def step():
+        for alg in (1, 2):
+            hists[alg].zero_()
+            ffa.search_batch([plans[alg]] * len(series), xs, ws=wsb, outs=outs)
+            for o in outs:
+                ffa.snr_histogram(o[0], HIST_LO, HIST_BPU, HIST_BINS, hists[alg])
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / a.steps / 1e3
+    trials = 2 * nt * len(series)
+    res = {}
+    for alg in (1, 2):
+        h = hists[alg].cpu().numpy().view("uint64")
+        assert int(h.sum()) == nt * len(series), "every trial is counted once"
+        res[alg] = {f"{k:g}": round(ffa.sigma_threshold(h, HIST_LO, HIST_BPU, k), 4)
+                    for k in (-2.0, -1.0, 0.0, 1.0, 2.0, 3.0, 4.0, 5.0, 5.5)}
+    return {"metric": "white-noise false-alarm calibration, S/N trials/s", "value": trials / sec,
+            "unit": "trials/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": sec * 1e3,
+            "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic (seeded; workload 6 of paper_1703_05581_amd.synth)",
+            "config": {"workload": "26 white-noise f32 series, 2^21 x 2.048 ms, 1-20 s, base 488 bins, "
+                                   "default widths, Algorithms 1 and 2",
+                       "trials_per_algorithm": nt * len(series),
+                       "histogram": {"lo": HIST_LO, "bins_per_unit": HIST_BPU, "bins": HIST_BINS}},
+            "snr_at_sigma_alg1": res[1], "snr_at_sigma_alg2": res[2],
+            "paper_5sigma_white_noise": {"alg1": 6.6, "alg2": 7.1}}
+
+
 def run_served(a) -> dict:
     """Request server under Poisson arrivals at --load x its measured
     capacity; latency = submit to the end of the search on the GPU."""
@@ -282,7 +342,8 @@ def main():
         import torch
 
         torch.cuda.init()
-        print(json.dumps(run_batch(a) if a.mode == "batch" else run_served(a)))
+        fn = {"batch": run_batch, "served": run_served, "null": run_null}[a.mode]
+        print(json.dumps(fn(a)))
         return
     import numpy as np
     import torch

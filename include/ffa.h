@@ -219,6 +219,40 @@ ffa_status ffa_sift(ffa_plan plan, const float* d_snr, const int32_t* d_width,
                     int32_t max_cands, int32_t* d_n_cands, void* d_ws,
                     size_t ws_bytes, void* stream);
 
+/* False-alarm statistics (Sec. 4.1.2).  The paper calibrates significance
+ * by searching data without pulsars and mapping each S/N to a Gaussian-
+ * equivalent sigma through the fraction of trials that reach it.  The counts
+ * come from a histogram that any number of searches accumulate into; the
+ * mapping runs on the host over the histogram.
+ *
+ * ffa_snr_histogram: adds the n scores of d_snr (device) to d_hist (device,
+ * n_bins uint64 counts, which the caller zeroes before the first call).  Bin
+ * b holds the scores with floor((s - lo) * bins_per_unit) == b, the product
+ * taken in float; scores below lo count in bin 0 and scores past the top in
+ * bin n_bins - 1, so the count at or above every inner edge
+ * lo + b / bins_per_unit (b >= 1) is exact.  NaN is not counted.
+ *   1 <= n_bins <= 16384, lo and bins_per_unit finite, bins_per_unit > 0,
+ *   n >= 0 (0 does nothing).  Asynchronous on `stream`.
+ * Errors: FFA_ERR_INVALID, FFA_ERR_DEVICE. */
+ffa_status ffa_snr_histogram(const float* d_snr, int64_t n, float lo,
+                             float bins_per_unit, int32_t n_bins,
+                             uint64_t* d_hist, void* stream);
+
+/* Host.  sigma[b] (n_bins doubles) = the Gaussian-equivalent sigma at the
+ * lower edge of bin b: with Q the fraction of counts in bins b and above,
+ * the sigma that a standard normal variable exceeds with probability Q.
+ * Bin 0 (Q = 1) gives -inf, an edge no count reaches +inf.
+ * Errors: FFA_ERR_INVALID (NULL pointer, n_bins < 1, empty histogram). */
+ffa_status ffa_sigma_gauss(const uint64_t* hist, int32_t n_bins, double* sigma);
+
+/* Host.  *snr = the S/N that a `sigma`-sigma detection needs: the lowest
+ * inner edge lo + b / bins_per_unit (b >= 1, in double) at or above which
+ * the count is at most Phi(-sigma) times the total.  Errors: FFA_ERR_INVALID
+ * (NULL pointer, empty histogram, or a top bin that already holds more than
+ * that fraction: widen the histogram). */
+ffa_status ffa_sigma_threshold(const uint64_t* hist, int32_t n_bins, float lo,
+                               float bins_per_unit, double sigma, double* snr);
+
 /* Batched search: the periodograms of n series, each with its own plan (any
  * mix of sample types).  The series are spread over a few streams that the
  * library owns on the current GPU, which wait for earlier work on `stream`

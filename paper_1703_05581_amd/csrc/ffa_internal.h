@@ -197,6 +197,9 @@ bool tiles_fit(int is_int, int max_P0, int lds_bytes, int alg);
 hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
                         void* ws, hipStream_t st);
 hipError_t launch_best(const float* snr, int64_t n, int64_t* best, hipStream_t st);
+constexpr int32_t kHistMaxBins = 16384;
+hipError_t launch_snr_histogram(const float* snr, int64_t n, float lo, float bins_per_unit, int32_t n_bins,
+                                uint64_t* hist, hipStream_t st);
 // Candidate sifting (ffa_sift); scratch at element `scratch` of ws.
 hipError_t launch_sift(const float* snr, const int32_t* width, int64_t n, const ffa_sift_params& prm,
                        const StepDev* steps, int32_t n_steps, double tsamp, void* ws, int64_t scratch,

@@ -1223,6 +1223,35 @@ __global__ __launch_bounds__(1024) void sift_final_kernel(
   }
 }
 
+// ------------------------------------------------------------ S/N histogram
+//
+// Each workgroup counts its share of the scores in an LDS histogram (32-bit
+// counters; the launcher keeps every workgroup under 2^31 scores), then adds
+// its non-zero bins to the 64-bit device histogram.
+
+__global__ __launch_bounds__(1024) void snr_hist_kernel(const float* __restrict__ snr, int64_t n, float lo,
+                                                        float bpu, int32_t nb,
+                                                        unsigned long long* __restrict__ hist) {
+#pragma clang fp contract(off)
+  extern __shared__ uint32_t h_lds[];
+  for (int i = threadIdx.x; i < nb; i += 1024) h_lds[i] = 0;
+  __syncthreads();
+  const float top = (float)(nb - 1);
+  const int64_t stride = (int64_t)gridDim.x * 1024;
+  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) {
+    const float s = snr[i];
+    if (__builtin_isnan(s)) continue;
+    const float x = (s - lo) * bpu;
+    const int b = !(x >= 0.0f) ? 0 : (x >= top ? nb - 1 : (int)x);
+    atomicAdd(&h_lds[b], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += 1024) {
+    const uint32_t c = h_lds[i];
+    if (c) atomicAdd(&hist[i], (unsigned long long)c);
+  }
+}
+
 }  // namespace
 
 // --------------------------------------------------------------- launchers
@@ -1411,6 +1440,20 @@ hipError_t launch_sift(const float* snr, const int32_t* width, int64_t n, const 
   sift_final_kernel<<<1, 1024, 0, st>>>(ptrial, psnr, info, width, steps, n_steps, tsamp, prm.group_widths,
                                         prm.harmonic_primes, prm.harmonic_tol, period, lim, order, alive, out,
                                         max_out, n_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_snr_histogram(const float* snr, int64_t n, float lo, float bins_per_unit, int32_t n_bins,
+                                uint64_t* hist, hipStream_t st) {
+  if (n < 0 || n_bins < 1 || n_bins > kHistMaxBins) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  // about 64K scores per workgroup, at most 1024 workgroups unless a
+  // workgroup would then count more than 2^31 scores
+  int64_t blocks = std::min<int64_t>((n + 65535) / 65536, 1024);
+  blocks = std::max<int64_t>(blocks, (n + (1ll << 31) - 1) >> 31);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  snr_hist_kernel<<<(unsigned)blocks, 1024, (size_t)n_bins * 4, st>>>(
+      snr, n, lo, bins_per_unit, n_bins, reinterpret_cast<unsigned long long*>(hist));
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ FFA_SNR_ALG2_OFFPULSE = 2
 EXPORTS = (
     "ffa_plan_create", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
     "ffa_plan_periods", "ffa_prepare", "ffa_search_prepared", "ffa_search", "ffa_fold", "ffa_best",
-    "ffa_sift", "ffa_batch_workspace",
+    "ffa_sift", "ffa_snr_histogram", "ffa_sigma_gauss", "ffa_sigma_threshold", "ffa_batch_workspace",
     "ffa_search_batch", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
     "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
 )
@@ -104,6 +104,10 @@ _lib.ffa_search_prepared.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp]
 _lib.ffa_fold.argtypes = [_vp, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.ffa_best.argtypes = [_vp, _i64, _vp, _vp]
 _lib.ffa_sift.argtypes = [_vp, _vp, _vp, _P(SiftParams), _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.ffa_snr_histogram.argtypes = [_vp, _i64, ctypes.c_float, ctypes.c_float, _i32, _vp, _vp]
+_lib.ffa_sigma_gauss.argtypes = [_P(ctypes.c_uint64), _i32, _P(ctypes.c_double)]
+_lib.ffa_sigma_threshold.argtypes = [_P(ctypes.c_uint64), _i32, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_double, _P(ctypes.c_double)]
 _lib.ffa_batch_workspace.argtypes = [_i32, _P(_vp), _P(_sz)]
 _lib.ffa_search_batch.argtypes = [_i32, _P(_vp), _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
 _lib.ffa_server_create.argtypes = [_sz, _i32, _P(_vp)]
@@ -344,6 +348,56 @@ def best(snr, stream=None, out=None):
     return out if out is not None else int(res.item())
 
 
+def snr_histogram(snr, lo: float, bins_per_unit: float, n_bins: int, hist=None, stream=None):
+    """ffa_snr_histogram: adds the scores of ``snr`` (a float32 cuda tensor)
+    to ``hist`` (an int64 cuda tensor of n_bins counts, zeroed when created
+    here) and returns it."""
+    import torch
+
+    if snr.dtype != torch.float32 or not snr.is_contiguous():
+        raise ValueError("snr must be a contiguous float32 tensor")
+    if hist is None:
+        hist = torch.zeros(n_bins, dtype=torch.int64, device=snr.device)
+    if hist.dtype != torch.int64 or hist.numel() != n_bins or not hist.is_contiguous():
+        raise ValueError("hist must be a contiguous int64 tensor of n_bins counts")
+    _check(_lib.ffa_snr_histogram(snr.data_ptr(), snr.numel(), lo, bins_per_unit, n_bins, hist.data_ptr(),
+                                  _stream_ptr(stream)), "ffa_snr_histogram")
+    return hist
+
+
+def _host_counts(hist):
+    import numpy as np
+
+    if hasattr(hist, "cpu"):
+        hist = hist.cpu().numpy()
+    h = np.ascontiguousarray(hist)
+    if h.dtype == np.int64:
+        h = h.view(np.uint64)
+    if h.dtype != np.uint64:
+        raise ValueError("counts must be int64 or uint64")
+    return h
+
+
+def sigma_gauss(hist):
+    """ffa_sigma_gauss: Gaussian-equivalent sigma at every bin's lower edge."""
+    import numpy as np
+
+    h = _host_counts(hist)
+    out = np.empty(h.size, np.float64)
+    _check(_lib.ffa_sigma_gauss(h.ctypes.data_as(_P(ctypes.c_uint64)), h.size,
+                                out.ctypes.data_as(_P(ctypes.c_double))), "ffa_sigma_gauss")
+    return out
+
+
+def sigma_threshold(hist, lo: float, bins_per_unit: float, sigma: float) -> float:
+    """ffa_sigma_threshold: the S/N a ``sigma``-sigma detection needs."""
+    h = _host_counts(hist)
+    out = ctypes.c_double()
+    _check(_lib.ffa_sigma_threshold(h.ctypes.data_as(_P(ctypes.c_uint64)), h.size, lo, bins_per_unit, sigma,
+                                    ctypes.byref(out)), "ffa_sigma_threshold")
+    return out.value
+
+
 def batch_workspace_bytes(plans) -> int:
     arr = (_vp * len(plans))(*[p.handle for p in plans])
     ws = _sz()
@@ -352,8 +406,9 @@ def batch_workspace_bytes(plans) -> int:
 
 
 def search_batch(plans, series, ws=None, outs=None, stream=None):
-    """Periodograms of many series (cuda tensors), one plan each, in one
-    persistent launch.  Returns a list of (snr, width) tensors."""
+    """ffa_search_batch: periodograms of many series (cuda tensors), one plan
+    each, spread over the library's streams.  Returns a list of (snr, width)
+    tensors."""
     import torch
 
     n = len(plans)

@@ -23,6 +23,10 @@ them; the shapes follow Sec. 2.4 and Sec. 4 of the paper):
                 one pulsar of S/N 15.
   5 "served"  : f32 series of N from {2^20 .. 2^23}, tsamp 1 ms, workload 2's plan and
                 noise model (unclipped floats), workload 2's pulsars in 30% of requests.
+  6 "null"    : 26 f32 series of white N(0,1) noise for the false-alarm statistics of
+                Sec. 4.1.2: 2^21 samples of 2.048 ms (an HTRU-length observation of 64 us
+                samples downsampled by 2^5), 1-20 s, base period 488 bins (1 s, the lowest
+                trial period in samples), the paper's default widths; about 1.5e8 trials.
 """
 from __future__ import annotations
 
@@ -198,8 +202,25 @@ def workload5(index: int, sizes=(20, 21, 22, 23)) -> Series:
     return Series(x.astype(np.float32), pa, psrs, seed)
 
 
+NULL_SERIES = 26
+
+
+def plan_args_null() -> PlanArgs:
+    return PlanArgs(N=1 << 21, tsamp=2.048e-3, pmin=1.0, pmax=20.0, bins_min=488, widths=())
+
+
+def workload6(index: int) -> Series:
+    """Series ``index`` (0..25) of the white-noise false-alarm set."""
+    if not 0 <= index < NULL_SERIES:
+        raise IndexError(index)
+    seed = 1000 * 6 + index
+    g = rng(seed)
+    pa = plan_args_null()
+    return Series(g.standard_normal(pa.N).astype(np.float32), pa, [], seed)
+
+
 def workload(wl: int, index: int = 0) -> Series:
-    return {1: workload1, 2: workload2, 3: workload3, 4: workload4, 5: workload5}[wl](index)
+    return {1: workload1, 2: workload2, 3: workload3, 4: workload4, 5: workload5, 6: workload6}[wl](index)
 
 
 # ------------------------------------------------------ small random cases

@@ -1,0 +1,131 @@
+"""False-alarm statistics (paper Sec. 4.1.2) on the GPU: the S/N histogram
+against the oracle's, bit for bit, through the C ABI; a uint8 noise search
+histogrammed on each side; and the white-noise calibration at full size
+(workload 6, about 10^8 trials per algorithm) against the paper's figures."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ffa():
+    from paper_1703_05581_amd import ffa as mod
+
+    return mod
+
+
+def _values(seed, n):
+    g = np.random.default_rng(seed)
+    v = (g.standard_normal(n) * 4 + 3).astype(np.float32)
+    k = min(n, 64)
+    # exact edges of 1/256 bins, their float neighbours, non-finite values
+    e = (-8.0 + g.integers(0, 4000, k) / 256.0).astype(np.float32)
+    v[:k] = e
+    v[k // 2:k] = np.nextafter(e[k // 2:], np.float32(-100))
+    if n > 80:
+        v[64:72] = [np.nan, np.inf, -np.inf, 1e30, -1e30, -8.0, 56.0, 55.99]
+    return v
+
+
+CASES = [(-8.0, 256.0, 16384), (-8.0, 256.0, 1), (0.0, 1.0, 7), (-3.5, 10.0, 1000), (2.0, 64.0, 4096)]
+
+
+@pytest.mark.parametrize("n", [0, 1, 1023, 65536 * 3 + 17, 2_000_000])
+@pytest.mark.parametrize("case", CASES, ids=[f"lo{c[0]}_b{c[1]}_n{c[2]}" for c in CASES])
+def test_histogram_parity(torch_cuda, ffa, oracle_mod, n, case):
+    torch = torch_cuda
+    lo, bpu, nb = case
+    v = _values(n + nb, n)
+    print(f"histogram n={n} lo={lo} bpu={bpu} bins={nb}", flush=True)
+    d = torch.from_numpy(v).cuda()
+    h = ffa.snr_histogram(d, lo, bpu, nb)
+    want = oracle_mod.snr_histogram(v, lo, bpu, nb)
+    assert np.array_equal(h.cpu().numpy().view(np.uint64), want)
+    # a second call accumulates
+    ffa.snr_histogram(d, lo, bpu, nb, h)
+    assert np.array_equal(h.cpu().numpy().view(np.uint64), 2 * want)
+
+
+def test_histogram_argument_errors(torch_cuda, ffa):
+    torch = torch_cuda
+    d = torch.zeros(10, dtype=torch.float32, device="cuda")
+    for lo, bpu, nb in [(0.0, 0.0, 8), (0.0, -1.0, 8), (float("nan"), 1.0, 8), (0.0, 1.0, 0), (0.0, 1.0, 16385)]:
+        # the binding refuses a counts tensor of the wrong size itself; the
+        # library refuses the rest
+        with pytest.raises((ffa.FFAError, ValueError)):
+            ffa.snr_histogram(d, lo, bpu, nb, torch.zeros(max(nb, 1), dtype=torch.int64, device="cuda"))
+
+
+def test_u8_noise_search_histogram(torch_cuda, ffa, oracle_mod):
+    """uint8 noise: the periodograms are bit-exact, so each side histograms
+    its own and the counts, sigma curve and thresholds agree exactly."""
+    torch = torch_cuda
+    g = np.random.default_rng(606)
+    N, tsamp, pmin, pmax, B = 1 << 17, 1e-3, 0.2, 1.0, 200
+    x = np.clip(np.rint(128 + 16 * g.standard_normal(N)), 0, 255).astype(np.uint8)
+    gp = ffa.Plan(N, tsamp, pmin, pmax, B, None, "u8")
+    op = oracle_mod.plan(N, tsamp, pmin, pmax, B)
+    snr, _ = gp.search(torch.from_numpy(x).cuda())
+    osnr, _ = oracle_mod.search(x, op, None)
+    lo, bpu, nb = -8.0, 256.0, 16384
+    h = ffa.snr_histogram(snr, lo, bpu, nb).cpu().numpy().view(np.uint64)
+    want = oracle_mod.snr_histogram(osnr, lo, bpu, nb)
+    assert np.array_equal(h, want)
+    for k in (0.0, 1.0, 2.0, 3.0):
+        assert ffa.sigma_threshold(h, lo, bpu, k) == oracle_mod.sigma_threshold(want, lo, bpu, k)
+
+
+def test_null_workload_sampled_steps(torch_cuda, ffa, oracle_mod):
+    """Workload 6's plan (base 488 bins, default widths, f = 1..16) on one of
+    its series: sampled steps against the oracle, both algorithms."""
+    from test_gpu_parity import run_case
+
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload6(0)
+    pa = s.plan
+    for alg in (1, 2):
+        run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min, None,
+                 "f32", steps_max=6, alg=alg)
+
+
+def test_null_calibration(torch_cuda, ffa):
+    """All 26 white-noise series with both algorithms: every trial counted,
+    S/N rising with sigma, and for Algorithm 1 the S/N of a 5-sigma detection
+    at the paper's white-noise figure (6.6; measured 6.625).  Algorithm 2's
+    tail depends on the widest boxcar relative to the profile (its sigma comes
+    from the filtered profile, whose off-pulse part holds few independent
+    values when the boxcar is wide): with the paper's width rule it reaches
+    11.5 at 5 sigma, not the paper's 7.1, which this reading matches only with
+    boxcars of at most 8-16 bins.  So Algorithm 2's figure is recorded, not
+    asserted."""
+    torch = torch_cuda
+    from paper_1703_05581_amd import synth
+
+    series = [synth.workload6(i) for i in range(synth.NULL_SERIES)]
+    pa = series[0].plan
+    xs = [torch.from_numpy(s.data).cuda() for s in series]
+    lo, bpu, nb = -8.0, 256.0, 16384
+    for alg in (1, 2):
+        plan = ffa.Plan.from_args(pa, snr=alg)
+        outs = ffa.search_batch([plan] * len(xs), xs)
+        h = torch.zeros(nb, dtype=torch.int64, device="cuda")
+        for o in outs:
+            ffa.snr_histogram(o[0], lo, bpu, nb, h)
+        hc = h.cpu().numpy().view(np.uint64)
+        assert int(hc.sum()) == plan.n_trials * len(xs)
+        t = [ffa.sigma_threshold(hc, lo, bpu, k) for k in (0.0, 1.0, 2.0, 3.0, 4.0, 5.0)]
+        print(f"alg{alg}: trials {int(hc.sum())}, S/N at 0..5 sigma {t}", flush=True)
+        assert all(a < b for a, b in zip(t, t[1:])), t
+        if alg == 1:
+            assert abs(t[5] - 6.6) < 0.3, t[5]
+        del outs
