@@ -119,6 +119,21 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   return ((uint64_t)readlane((uint32_t)(v >> 32), l) << 32) | readlane((uint32_t)v, l);
 }
 
+// The width table of a step, held one entry per lane (lane i: width i, its
+// square root and reciprocal square root), so the scoring loops read entries
+// with v_readlane instead of memory loads.
+struct WidthLanes {
+  int32_t w;
+  double sq, isq;
+  __device__ __forceinline__ int32_t width(int i) const { return (int32_t)readlane((uint32_t)w, i); }
+  __device__ __forceinline__ double sqrtw(int i) const {
+    return __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(sq), i));
+  }
+  __device__ __forceinline__ double isqrtw(int i) const {
+    return __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(isq), i));
+  }
+};
+
 // Sum of one value per lane over the wave (a fixed reduction tree, so the
 // result is deterministic); wave-uniform.
 __device__ __forceinline__ int64_t wave_sum(int64_t v) {
@@ -141,6 +156,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   v = add(v, dpp64<kDppRowMirror>(bits(v)));
   v = add(v, dpp64<kDppBcast15, 0xA>(bits(v)));
   v = add(v, dpp64<kDppBcast31, 0xC>(bits(v)));
+  return __longlong_as_double((long long)readlane64(bits(v), 63));
+}
+
+// Maximum of one double per lane (no NaNs); wave-uniform.
+__device__ __forceinline__ double wave_dmax(double v) {
+  auto mx = [](double a, uint64_t b) { return fmax(a, __longlong_as_double((long long)b)); };
+  auto bits = [](double a) { return (uint64_t)__double_as_longlong(a); };
+  v = mx(v, dpp64<kDppXor1>(bits(v)));
+  v = mx(v, dpp64<kDppXor2>(bits(v)));
+  v = mx(v, dpp64<kDppHalfMirror>(bits(v)));
+  v = mx(v, dpp64<kDppRowMirror>(bits(v)));
+  v = mx(v, dpp64<kDppBcast15, 0xA>(bits(v)));
+  v = mx(v, dpp64<kDppBcast31, 0xC>(bits(v)));
   return __longlong_as_double((long long)readlane64(bits(v), 63));
 }
 
@@ -319,7 +347,7 @@ __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int
     // end that stayed put twice in a row down-weighted (Illinois rule)
     const float flo = wlo * ((float)(k1 - c_lo) + 1.0f);
     const float fhi = whi * ((float)(c_hi - k1) - 1.0f);
-    const float frac = halve ? 0.5f : (flo + fhi > 0.0f ? __fdividef(flo, flo + fhi) : 0.5f);
+    const float frac = halve ? 0.5f : (flo + fhi > 0.0f ? flo * __builtin_amdgcn_rcpf(flo + fhi) : 0.5f);
     uint32_t T;
     if (FKEY && it < kn.max_iters) {  // float keys: interpolate / halve the values
       const float a = fval(lo), b = fval(hi - 1u);
@@ -417,7 +445,7 @@ __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int
 // mean, the variance and the score are in double.
 template <int E, bool INT>
 __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, int wmax,
-                                           const int32_t* widths, int nw, float* snr_out,
+                                           const WidthLanes& wt, int nw, float* snr_out,
                                            int32_t* width_out) {
   using A = typename Types<INT>::A;
   const int lane = lane_id();
@@ -447,7 +475,7 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
   double best = 0.0;
   int32_t bw = 0;
   for (int i = 0; i < nw; ++i) {
-    const int32_t w = widths[i];
+    const int32_t w = wt.width(i);
     A breg[ER];
     if constexpr (kRegs) {
 #pragma unroll
@@ -526,8 +554,7 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
 // a host table, so every rounding is a correctly rounded IEEE operation.
 template <int E, bool INT>
 __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
-                              const int32_t* widths, const double* sqrtw, const double* isqrtw,
-                              int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
+                              const WidthLanes& wt, int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
   using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
   const int lane = lane_id();
@@ -597,24 +624,17 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   A cex[E];  // C[j] (exclusive prefix) of this lane's bins
   circular_prefix<E, INT>(row, P0, wmax, cex);
 
-  // Each width: largest boxcar sum, then its score num_w / ((K*MAD)*sqrt(w)).
-  // The divisor scale is the same for every width, so widths are ranked by
-  // num_w * (1/sqrt(w)) first; the exact division runs only for a width
-  // within 1e-12 of the best seen so far.  A width skipped that way is
-  // strictly below the final maximum, so the result and the first-width tie
-  // rule are those of dividing for every width.
+  // Each width's score is num_w / ((K*MAD)*sqrt(w)), the box maximum taken
+  // over all positions.
   const double scale = INT ? kMadK * (double)mad4 : kMadK * (double)mad;
-  double best = 0.0, amax = -INFINITY;
-  int32_t bw = 0;
-#pragma unroll
-  for (int i = 0; i < kMaxWidths; ++i) {
-    if (i >= nw) break;
-    const int32_t w = widths[i];
+  // Pass 1: the largest box of each width (wave-uniform), kept in lane i for
+  // width i (as a key for floats).  Two widths per iteration for ILP.
+  const int nfull = P0 / kWave;  // registers holding 64 real bins
+  auto lane_max = [&](int32_t w) -> A {
     A mx;  // box sums are >= 0 for integers
     if constexpr (INT) mx = 0u;
     else mx = -INFINITY;
     const T* rw = row + w + lane;
-    const int nfull = P0 / kWave;  // registers holding 64 real bins
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       if (r < nfull) {  // wave-uniform branch
@@ -627,24 +647,40 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
         else mx = fmaxf(mx, b);
       }
     }
-    double num;
-    if constexpr (INT) {
-      const uint32_t pk = wave_umax(mx);
-      num = (double)(2 * (2 * (int64_t)pk - (int64_t)w * (int64_t)med2));
-    } else {
-      const float pk = fval(wave_umax(fkey(mx)));
-      num = (double)pk - (double)w * (double)med;
-    }
-    const double a = num * isqrtw[i];
-    amax = a > amax ? a : amax;
-    if (a >= amax - 1e-12 * fabs(amax)) {
-      const double sc = num / (scale * sqrtw[i]);
-      if (bw == 0 || sc > best) {
-        best = sc;
-        bw = w;
-      }
-    }
+    return mx;
+  };
+  auto as_key = [](A v) -> uint32_t {
+    if constexpr (INT) return v;
+    else return fkey(v);
+  };
+  uint32_t pk_l = 0;
+  int i = 0;
+  for (; i + 2 <= nw; i += 2) {
+    const A m0 = lane_max(wt.width(i)), m1 = lane_max(wt.width(i + 1));
+    const uint32_t p0 = wave_umax(as_key(m0)), p1 = wave_umax(as_key(m1));
+    pk_l = lane == i ? p0 : (lane == i + 1 ? p1 : pk_l);
   }
+  if (i < nw) {
+    const uint32_t p0 = wave_umax(as_key(lane_max(wt.width(i))));
+    pk_l = lane == i ? p0 : pk_l;
+  }
+  // Pass 2, lane i = width i: num_i, and the ranking value num_i / sqrt(w_i)
+  // up to the common factor.  The exact score num / (scale * sqrt(w)) is
+  // computed for the widths within 1e-12 of the largest ranking value only;
+  // any other width scores strictly lower, so the maximum and the first-width
+  // tie rule are those of scoring every width.
+  const bool live = lane < nw;
+  double num;
+  if constexpr (INT) num = (double)(2 * (2 * (int64_t)pk_l - (int64_t)wt.w * (int64_t)med2));
+  else num = (double)fval(pk_l) - (double)wt.w * (double)med;
+  const double a = live ? num * wt.isq : -INFINITY;
+  const double amax = wave_dmax(a);
+  const bool cand = live && a >= amax - 1e-12 * fabs(amax);
+  const double sc = cand ? num / (scale * wt.sq) : -INFINITY;
+  const double best = wave_dmax(sc);
+  const uint64_t hit = __ballot(cand && sc == best);
+  const int first = __ffsll((unsigned long long)hit) - 1;
+  const int32_t bw = wt.width(first);
   if (lane == 0) {
     *snr_out = (float)best;
     *width_out = bw;
@@ -655,14 +691,13 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 // P0 <= 64*EMAX are scored (the launcher picks EMAX from the largest P0).
 template <bool INT, int EMAX, int ALG>
 __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
-                               const int32_t* widths, const double* sqrtw, const double* isqrtw,
-                               int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
+                               const WidthLanes& wt, int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
 #define FFA_SCORE(EE)                                                                              \
   do {                                                                                             \
     if constexpr (ALG == 2)                                                                        \
-      score_alg2<EE, INT>(row, P0, wmax, widths, nw, snr_out, width_out);                          \
+      score_alg2<EE, INT>(row, P0, wmax, wt, nw, snr_out, width_out);                              \
     else                                                                                           \
-      score_profile<EE, INT>(row, scratch, P0, wmax, widths, sqrtw, isqrtw, nw, kn, snr_out, width_out); \
+      score_profile<EE, INT>(row, scratch, P0, wmax, wt, nw, kn, snr_out, width_out);             \
   } while (0)
   if (P0 <= 64) FFA_SCORE(1);
   else if (P0 <= 128) FFA_SCORE(2);
@@ -687,9 +722,11 @@ __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint
 
 // One workgroup per tile.  A launch covers tiles whose inputs were all
 // written by earlier launches on the stream (the planner's windows), so
-// workgroups never wait on one another.
+// workgroups never wait on one another.  For profiles of up to 512 bins the
+// registers are held to 8 waves per SIMD, so two workgroups share a CU when
+// their tiles' LDS allows it.
 template <bool INT, int EMAX, int ALG>
-__global__ __launch_bounds__(kThreads) void ffa_tile_kernel(TileArgs a, void* __restrict__ ws_raw) {
+__global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(TileArgs a, void* __restrict__ ws_raw) {
   using T = typename Types<INT>::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -783,14 +820,16 @@ __global__ __launch_bounds__(kThreads) void ffa_tile_kernel(TileArgs a, void* __
     const int32_t* widths = a.widths + ph.wofs;
     const double* sw = a.sqrtw + ph.wofs;
     const double* isw = a.sqrtw + ph.isqrt_ofs;
-    int wmax = 0;
-    for (int i = 0; i < ph.nw; ++i) wmax = widths[i] > wmax ? widths[i] : wmax;
+    WidthLanes wt;
+    wt.w = lane < ph.nw ? widths[lane] : 0;
+    wt.sq = lane < ph.nw ? sw[lane] : 1.0;
+    wt.isq = lane < ph.nw ? isw[lane] : 1.0;
+    const int wmax = (int)wave_umax((uint32_t)wt.w);
     const int64_t trial0 = ph.first_trial + ((int64_t)q << d);
     for (int tt = wave; tt < R; tt += nwaves) {
       T* row = lds + (size_t)bitrev(tt, d) * S;
       const int64_t trial = trial0 + tt;
-      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, widths, sw, isw, ph.nw, kn,
-                                a.snr + trial, a.width + trial);
+      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, wt, ph.nw, kn, a.snr + trial, a.width + trial);
     }
   }
 }
