@@ -287,6 +287,33 @@ __device__ __forceinline__ uint32_t lane_select(uint32_t c, int cnt, int t) {
   return c;  // not reached: the loop ends by returning
 }
 
+// Counts of the keys below three pivots, in one pass: per-lane counts packed
+// 10 bits apart, one wave sum (valid while n <= 1023).
+template <int E>
+__device__ __forceinline__ void count_lt3(const uint32_t (&key)[E], const uint32_t (&t)[3], int (&c)[3]) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < E; ++r)
+    acc += (key[r] < t[0] ? 1u : 0u) + (key[r] < t[1] ? (1u << 10) : 0u) + (key[r] < t[2] ? (1u << 20) : 0u);
+  acc += dpp<kDppXor1>(0u, acc);
+  acc += dpp<kDppXor2>(0u, acc);
+  acc += dpp<kDppHalfMirror>(0u, acc);
+  acc += dpp<kDppRowMirror>(0u, acc);
+  acc += dpp<kDppBcast15, 0xA>(0u, acc);
+  acc += dpp<kDppBcast31, 0xC>(0u, acc);
+  const uint32_t s = readlane(acc, 63);
+  c[0] = (int)(s & 1023u);
+  c[1] = (int)((s >> 10) & 1023u);
+  c[2] = (int)(s >> 20);
+}
+
+// Three ascending first pivots for a selection (a guess from the profile's
+// moments); any pivots keep it exact.
+struct Prior {
+  bool on;
+  uint32_t t[3];
+};
+
 struct SelectKnobs {
   int max_iters;  // counting rounds before the full-sort fallback
   int max_cand;   // candidates small enough for lane_select (<= 64)
@@ -302,7 +329,7 @@ struct SelectKnobs {
 // interpolation happens on the float values.  Every exit is exact.
 template <int E, bool FKEY>
 __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int k1, int k2, uint32_t kmin,
-                            uint32_t kmax, uint32_t* scratch, SelectKnobs kn,
+                            uint32_t kmax, uint32_t* scratch, SelectKnobs kn, const Prior& pr,
                             uint32_t& v1, uint32_t& v2) {
   const int lane = lane_id();
   uint32_t lo = kmin, hi = kmax + 1u;  // kmax < kPadKey
@@ -310,6 +337,38 @@ __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int
   bool halve = false;
   int side = 0;         // +1: hi moved last round, -1: lo moved
   float wlo = 1.0f, whi = 1.0f;  // Illinois weights of the bracket ends
+  // the straddle exit: k1 < count(keys < T) <= k2 puts v1 below T, v2 above
+  auto straddle = [&](uint32_t T) {
+    uint32_t mx = 0u, mn = kPadKey;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      if (key[r] < T) mx = umax(mx, key[r]);
+      else mn = umin(mn, key[r]);
+    }
+    v1 = wave_umax(mx);
+    v2 = wave_umin(mn);
+  };
+  if constexpr (E <= 8) {
+    if (pr.on) {  // first round: the three guessed pivots at once
+      int c[3];
+      count_lt3(key, pr.t, c);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const uint32_t T = pr.t[j];
+        if (T <= lo || T >= hi) continue;
+        if (c[j] <= k1) {
+          lo = T;
+          c_lo = c[j];
+        } else if (c[j] > k2) {
+          hi = T;
+          c_hi = c[j];
+        } else {
+          straddle(T);
+          return;
+        }
+      }
+    }
+  }
   // Rounds past max_iters only halve the key range, which ends the loop
   // within 33 more rounds (the range is at most 2^32).
   for (int it = 0; it < kn.max_iters + 34; ++it) {
@@ -371,14 +430,7 @@ __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int
       whi = 1.0f;
       side = 1;
     } else {  // k1 < c <= k2: the two targets straddle T
-      uint32_t mx = 0u, mn = kPadKey;
-#pragma unroll
-      for (int r = 0; r < E; ++r) {
-        if (key[r] < T) mx = umax(mx, key[r]);
-        else mn = umin(mn, key[r]);
-      }
-      v1 = wave_umax(mx);
-      v2 = wave_umin(mn);
+      straddle(T);
       return;
     }
     halve = (c_hi - c_lo) * 4 > before * 3;
@@ -574,10 +626,45 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   }
   kmin = wave_umin(kmin);
   kmax = wave_umax(kmax);
+  // Mean and spread of the profile in float, relative to its minimum: they
+  // only place the selections' first pivots (about 2.5 standard errors either
+  // side of the expected median and MAD of normal noise).
+  Prior pm{false, {0u, 0u, 0u}}, pd{false, {0u, 0u, 0u}};
+  float sd = 0.f, mu_y = 0.f;
+  if constexpr (E <= 8) {
+    float s1 = 0.f, s2 = 0.f;
+    const float base = INT ? 0.f : fval(kmin);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      if (r * kWave + lane < P0) {
+        const float y = INT ? (float)(key[r] - kmin) : fval(key[r]) - base;
+        s1 += y;
+        s2 += y * y;
+      }
+    }
+    s1 = __uint_as_float(readlane(__float_as_uint(wave_scan(s1)), 63));
+    s2 = __uint_as_float(readlane(__float_as_uint(wave_scan(s2)), 63));
+    const float inv = __builtin_amdgcn_rcpf((float)P0);
+    mu_y = s1 * inv;
+    const float var = s2 * inv - mu_y * mu_y;
+    sd = var > 0.f ? __builtin_sqrtf(var) : 0.f;
+    const float h = 2.5f * sd * __builtin_amdgcn_rsqf((float)P0);
+    pm.on = sd > 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float v = mu_y + (float)(j - 1) * h;
+      if constexpr (INT) {
+        const float u = (float)kmin + v;
+        pm.t[j] = (uint32_t)fminf(fmaxf(u, 0.f), 4294967040.f);
+      } else {
+        pm.t[j] = fkey(base + v);
+      }
+    }
+  }
 
   // median (even P0: mean of the two middle order statistics)
   uint32_t m1, m2;
-  select_pair<E, !INT>(key, P0, k1, k2, kmin, kmax, scratch, kn, m1, m2);
+  select_pair<E, !INT>(key, P0, k1, k2, kmin, kmax, scratch, kn, pm, m1, m2);
   uint64_t med2 = 0;
   float med = 0.f;
   uint32_t dmax;
@@ -601,8 +688,20 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     }
   }
   const uint32_t dmin = INT ? 0u : fkey(0.f);
+  if constexpr (E <= 8) {
+    // the MAD of normal noise is 0.6745 sd (doubled for integers)
+    const float m = (INT ? 2.f : 1.f) * 0.6745f * sd;
+    const float e = 2.4f * __builtin_amdgcn_rsqf((float)P0);
+    pd.on = sd > 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float v = m * (1.f + (float)(j - 1) * e);
+      if constexpr (INT) pd.t[j] = (uint32_t)fminf(fmaxf(v, 0.f), 4294967040.f);
+      else pd.t[j] = fkey(fmaxf(v, 0.f));
+    }
+  }
   uint32_t d1, d2;
-  select_pair<E, !INT>(key, P0, k1, k2, dmin, dmax, scratch, kn, d1, d2);
+  select_pair<E, !INT>(key, P0, k1, k2, dmin, dmax, scratch, kn, pd, d1, d2);
   uint64_t mad4 = 0;
   float mad = 0.f;
   bool mad_zero;
