@@ -50,11 +50,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=768,
                     help="FFA executions the oracle times for the CPU baseline")
+    ap.add_argument("--cpu-steps-1core", type=int, default=48,
+                    help="FFA executions timed on one core for the single-core oracle figure (0: skip)")
     ap.add_argument("--check", action="store_true", help="check sampled trials against the oracle")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--pmc-summary", metavar="DB", nargs="+")
     ap.add_argument("--searches", type=int, default=0,
                     help="with --pmc-summary: searches the profiled run made")
+    ap.add_argument("--workload", type=int, choices=[2, 3], default=2,
+                    help="search mode: workload 2 (the metric's configuration) or 3 (HTRU-like, dereddened)")
     ap.add_argument("--alg", type=int, choices=[1, 2], default=1,
                     help="profile score: 1 = Algorithm 1 (the headline), 2 = Algorithm 2")
     ap.add_argument("--mode", choices=["search", "batch", "served", "null"], default="search",
@@ -63,11 +67,31 @@ def parse():
                          "Poisson arrivals of workload-5 requests")
     ap.add_argument("--series", type=int, default=32, help="batch: series in the batch")
     ap.add_argument("--requests", type=int, default=400, help="served: timed requests")
-    ap.add_argument("--load", type=float, default=0.7, help="served: offered load / capacity")
+    ap.add_argument("--load", type=float, nargs="+", default=[0.7],
+                    help="served: offered loads / capacity, run in turn")
     return ap.parse_args()
 
 
-def workload_units(plan):
+WORKLOAD_TEXT = {
+    2: "uint8 series 2^20 samples, tsamp 1 ms, P0 256..511 at f=1,2,4, 10 widths, 768 FFA executions, "
+       "1835008 trials",
+    3: "f32 series 2^23 samples (71.6 min at 0.512 ms) with red noise, 0.5-30 s, P0 256..511 at f=2..128, "
+       "dereddened with the default 2 s window, 10 widths",
+}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def workload_units(plan, u8: bool = True, n_widths: int = 10):
     """trial*samples, algorithmic bytes and algorithmic operations of one search."""
     ts = 0
     in_bytes = 0
@@ -79,11 +103,11 @@ def workload_units(plan):
         elts = st.M * st.P0
         ts += st.M * st.m * st.P0
         # one read of the step's m*P0 samples: uint8 at f = 1, int32 sums above
-        in_bytes += st.m * st.P0 * (1 if st.f == 1 else 4)
+        in_bytes += st.m * st.P0 * (1 if st.f == 1 and u8 else 4)
         # butterfly: L adds per profile bin; Algorithm 1: 2 ops per bin per
         # width (boxcar difference, running max), 1 prefix add, |x - median|,
         # and two exact selections at 2 comparisons per bin each.
-        ops += elts * (L + 2 * 10 + 1 + 1 + 4)
+        ops += elts * (L + 2 * n_widths + 1 + 1 + 4)
     return ts, in_bytes + 8 * trials, ops
 
 
@@ -282,48 +306,54 @@ def run_served(a) -> dict:
     for t in ts:
         srv.wait(t)
     cap = 64 / (time.perf_counter() - t0)
-    rate = a.load * cap
-    arrivals = synth.poisson_arrivals(7, rate, len(reqs))
     import threading
 
-    lat, done = [], []
-    tickets = []
-    lock = threading.Lock()
+    runs = []
+    for li, load in enumerate(a.load):
+        rate = load * cap
+        arrivals = synth.poisson_arrivals(7 + li, rate, len(reqs))
+        lat, done = [], []
+        tickets = []
+        lock = threading.Lock()
 
-    def collector():
-        i = 0
-        while i < len(reqs):
+        def collector():
+            i = 0
+            while i < len(reqs):
+                with lock:
+                    have = len(tickets)
+                if i >= have:
+                    time.sleep(1e-4)
+                    continue
+                _, _, l = srv.wait(tickets[i])
+                if i >= 100:
+                    lat.append(l)
+                done.append(time.perf_counter())
+                i += 1
+
+        th = threading.Thread(target=collector)
+        th.start()
+        start = time.perf_counter()
+        for r, at in zip(reqs, arrivals):
+            now = time.perf_counter() - start
+            if at > now:
+                time.sleep(at - now)
+            t = srv.submit(plans[r.plan.N], r.data)
             with lock:
-                have = len(tickets)
-            if i >= have:
-                time.sleep(1e-4)
-                continue
-            _, _, l = srv.wait(tickets[i])
-            if i >= 100:
-                lat.append(l)
-            done.append(time.perf_counter())
-            i += 1
-
-    th = threading.Thread(target=collector)
-    th.start()
-    start = time.perf_counter()
-    for r, at in zip(reqs, arrivals):
-        now = time.perf_counter() - start
-        if at > now:
-            time.sleep(at - now)
-        t = srv.submit(plans[r.plan.N], r.data)
-        with lock:
-            tickets.append(t)
-    th.join()
+                tickets.append(t)
+        th.join()
+        span = done[-1] - done[100]
+        served_ts = sum(trial_samples(plans[r.plan.N]) for r in reqs[101:])
+        lat = np.array(lat)
+        runs.append({"load": load, "offered_rate_hz": rate, "p50_s": float(np.percentile(lat, 50)),
+                     "p99_s": float(np.percentile(lat, 99)), "served_trial_samples_per_s": served_ts / span})
+        print(f"served load {load}: p50 {runs[-1]['p50_s'] * 1e3:.1f} ms p99 {runs[-1]['p99_s'] * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
     srv.close()
-    span = done[-1] - done[100]
-    served_ts = sum(trial_samples(plans[r.plan.N]) for r in reqs[101:])
-    lat = np.array(lat)
+    first = runs[0]
     return {"metric": "FFA served requests: submit-to-result latency (workload 5)",
-            "value": float(np.percentile(lat, 50)), "unit": "s", "higher_is_better": False,
-            "n_gpus": 1, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "requests": a.requests, "warmup_requests": 100, "offered_rate_hz": rate,
-            "capacity_hz": cap, "load": a.load, "served_trial_samples_per_s": served_ts / span,
+            "value": first["p50_s"], "unit": "s", "higher_is_better": False,
+            "n_gpus": 1, "p50_s": first["p50_s"], "p99_s": first["p99_s"],
+            "requests": a.requests, "warmup_requests": 100, "capacity_hz": cap, "loads": runs,
             "dtype": "f32", "data": "synthetic (seeded; workload 5 of paper_1703_05581_amd.synth)",
             "config": {"workload": "Poisson arrivals of f32 requests, 2^20..2^23 samples, "
                                    "P0 256..511 at f=1,2,4; 16 GiB pool, 4 streams"}}
@@ -352,14 +382,14 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
-    series = synth.workload2(0)
+    series = synth.workload(a.workload, 0)
     pa = series.plan
     plan = ffa.Plan.from_args(pa, snr=a.alg)
     x = torch.from_numpy(series.data).to(dev)
     snr = torch.empty(plan.n_trials, dtype=torch.float32, device=dev)
     wid = torch.empty(plan.n_trials, dtype=torch.int32, device=dev)
     ws = plan.workspace(dev)
-    ts, alg_bytes, alg_ops = workload_units(plan)
+    ts, alg_bytes, alg_ops = workload_units(plan, pa.dtype == "u8", len(pa.widths))
 
     best_t = torch.empty(1, dtype=torch.int64, device=dev)
     for _ in range(a.warmup):
@@ -389,7 +419,7 @@ def main():
     prep_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / a.steps
     best_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / a.steps
     ksec = kern_ms / 1e3
-    traffic = stored_traffic()
+    traffic = stored_traffic() if a.workload == 2 and a.alg == 1 else None
 
     out = {
         "metric": f"FFA trial*samples/s incl. boxcar S/N (Algorithm {a.alg})",
@@ -402,10 +432,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i32",
-        "data": "synthetic (seeded; workload 2 of paper_1703_05581_amd.synth)",
-        "config": {"workload": "uint8 series 2^20 samples, tsamp 1 ms, P0 256..511 at f=1,2,4, "
-                               "10 widths, 768 FFA executions, 1835008 trials",
+        "dtype": "i32" if pa.dtype == "u8" else "f32",
+        "data": f"synthetic (seeded; workload {a.workload} of paper_1703_05581_amd.synth)",
+        "config": {"workload": WORKLOAD_TEXT[a.workload],
                    "N": pa.N, "trials": plan.n_trials, "executions": plan.n_steps,
                    "trial_samples": ts},
         "roofline": {
@@ -448,21 +477,35 @@ def main():
             threads = os.cpu_count() or 1
         threads = max(1, min(threads, 16))
         t0 = time.perf_counter()
-        snr_o, w_o = oracle.search(series.data, op, list(pa.widths), alg=a.alg, steps=sel, threads=threads)
+        dw = oracle.dered_default_window(pa.tsamp, pa.pmin, pa.pmax) if pa.dered_window == -1 else pa.dered_window
+        snr_o, w_o = oracle.search(series.data, op, list(pa.widths), alg=a.alg, steps=sel, threads=threads,
+                                   dered_window=dw, dered_stride=pa.dered_stride)
         cpu_s = time.perf_counter() - t0
         sample_ts = int(sum(int(op.M[s]) * int(op.m[s]) * int(op.P0[s]) for s in sel))
         out["cpu_baseline"] = {"value": sample_ts / cpu_s, "unit": "trial*samples/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"{sel.size} of {op.n_steps} FFA executions of the same "
-                                         f"series, {sample_ts:.3e} trial*samples in {cpu_s:.1f} s"}
+                                         f"series, {sample_ts:.3e} trial*samples in {cpu_s:.1f} s",
+                               "cpu_model": cpu_model()}
+        if a.cpu_steps_1core > 0 and not a.check:
+            sel1 = sel[:: max(1, sel.size // a.cpu_steps_1core)][: a.cpu_steps_1core]
+            t1 = time.perf_counter()
+            oracle.search(series.data, op, list(pa.widths), alg=a.alg, steps=sel1, threads=1, dered_window=dw,
+                          dered_stride=pa.dered_stride)
+            s1 = time.perf_counter() - t1
+            ts1 = int(sum(int(op.M[s]) * int(op.m[s]) * int(op.P0[s]) for s in sel1))
+            out["cpu_baseline"]["one_core"] = {"value": ts1 / s1, "unit": "trial*samples/s",
+                                               "sample": f"{sel1.size} FFA executions, {ts1:.3e} "
+                                                         f"trial*samples in {s1:.1f} s"}
         if a.check:
             sys.path.insert(0, os.path.join(ROOT, "tests"))
             from parity import check_periodogram, step_trials
 
             idx = step_trials(op, sel)
-            exact = a.alg == 1
+            exact = a.alg == 1 and pa.dtype == "u8" and not pa.dered_window
             summ = check_periodogram(oracle, series.data, op, list(pa.widths), snr.cpu().numpy(),
-                                     wid.cpu().numpy(), snr_o, w_o, idx, exact=exact, alg=a.alg)
+                                     wid.cpu().numpy(), snr_o, w_o, idx, exact=exact, alg=a.alg,
+                                     dered_window=dw, dered_stride=pa.dered_stride)
             out["check"] = (f"{idx.size} trials bit-exact" if exact else
                             f"{idx.size} trials, max |dS/N| {summ['max_abs_dsnr']:.2e}")
     print(json.dumps(out))

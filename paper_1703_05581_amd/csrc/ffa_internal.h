@@ -89,6 +89,7 @@ struct Step {
   int32_t total_tiles;
   int32_t lds_bytes;          // largest LDS footprint of its passes
   int32_t fold_phase0;        // its phases in pass order, in Plan::fold_phases
+  int64_t lds_budget = 0;     // LDS bytes a tile may use
 };
 
 // One launch of a search: a window of the queue whose tiles depend only on

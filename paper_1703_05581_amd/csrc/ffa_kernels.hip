@@ -199,55 +199,105 @@ constexpr uint32_t kPadKey = 0xffffffffu;  // above every real key
 // then it walks the bins in chunks of 64.  Chunk c reads B at
 // [64c + s, 64c + 64 + s] and writes B at [64c, 64c + 63], so no write lands
 // where a later chunk reads, and the halo keeps the old bins.  No barrier is
-// needed inside a level.
+// needed inside a level.  Where the row's spare bins allow a halo of
+// 3*2^(l-1), levels l and l+1 run as one pass over four rows (radix 4): the
+// same sums in the same order, with 10 reads and 4 writes per four outputs
+// instead of 12 and 8, and one barrier instead of two.
 template <typename T>
 __device__ __forceinline__ void butterfly(T* lds, int S, int P0, int H, int d) {
   const int lane = lane_id();
   const int wave = wave_id();
   const int nwaves = blockDim.x / kWave;
   const int R = 1 << d;
-  for (int l = 1; l <= d; ++l) {
+  const int nfull = P0 / kWave;
+  const bool tail = nfull * kWave + lane < P0;
+  const int room = S - P0 < P0 ? S - P0 : P0;  // bins a halo may hold
+  int l = 1;
+  while (l <= d) {
     const int half = 1 << (l - 1);
-    for (int p = wave; p < (R >> 1); p += nwaves) {
-      const int beta = p >> (l - 1);
-      const int v = p & (half - 1);
-      T* A = lds + (size_t)(beta * 2 * half + bitrev(v, l - 1)) * S;
-      T* B = A + (size_t)half * S;
-      const int sh = v < P0 ? v : v % P0;
-      const int hn = sh + 1 < H ? sh + 1 : H;  // halo bins this pair reads
-      for (int i = lane; i < hn; i += kWave) B[P0 + i] = B[i];
-      // The chunk loop is wave-uniform so that all lanes work on the same
-      // chunk together: the in-place writes rely on it.  Full chunks run
-      // unpredicated, two at a time; the last partial chunk is predicated.
-      T* pa = A + lane;
-      T* pb = B + lane;
-      const T* pb0 = B + sh + lane;
-      const int nfull = P0 / kWave;
-      int c = 0;
-      for (; c + 2 <= nfull; c += 2) {
-        const T a0 = pa[0], a1 = pa[kWave];
-        const T x0 = pb0[0], y0 = pb0[1], x1 = pb0[kWave], y1 = pb0[kWave + 1];
-        pa[0] = a0 + x0;
-        pb[0] = a0 + y0;
-        pa[kWave] = a1 + x1;
-        pb[kWave] = a1 + y1;
-        pa += 2 * kWave;
-        pb += 2 * kWave;
-        pb0 += 2 * kWave;
+    if (l < d && 3 * half <= room) {
+      // Levels l and l+1 at once (radix 4).  Unit (block b, index v < half)
+      // holds partial v of the four quarters of a block of 4*half rows,
+      // x0..x3 (all shifts below P0, as 3*half <= P0).  With every index
+      // mod P0,
+      //   t_{4v}   = (x0 + x1[+v])   + (x2[+2v]   + x3[+3v])
+      //   t_{4v+1} = (x0 + x1[+v])   + (x2[+2v+1] + x3[+3v+1])
+      //   t_{4v+2} = (x0 + x1[+v+1]) + (x2[+2v+1] + x3[+3v+2])
+      //   t_{4v+3} = (x0 + x1[+v+1]) + (x2[+2v+2] + x3[+3v+3])
+      // which are the two levels' sums in the same order, written over
+      // x0, x2, x1, x3: the slots the two single levels would use.  The
+      // halos hold bins 0..k*v+k of x_k, so no read wraps.
+      for (int u = wave; u < (R >> 2); u += nwaves) {
+        const int blk = u >> (l - 1);
+        const int v = u & (half - 1);
+        T* X0 = lds + (size_t)(blk * 4 * half + bitrev(v, l - 1)) * S;
+        T* X1 = X0 + (size_t)half * S;
+        T* X2 = X1 + (size_t)half * S;
+        T* X3 = X2 + (size_t)half * S;
+        for (int i = lane; i < v + 1; i += kWave) X1[P0 + i] = X1[i];
+        for (int i = lane; i < 2 * v + 2; i += kWave) X2[P0 + i] = X2[i];
+        for (int i = lane; i < 3 * v + 3; i += kWave) X3[P0 + i] = X3[i];
+        const T* p1 = X1 + v + lane;
+        const T* p2 = X2 + 2 * v + lane;
+        const T* p3 = X3 + 3 * v + lane;
+        auto unit = [&](int j) {
+          const T x0 = X0[j + lane];
+          const T x1a = p1[j], x1b = p1[j + 1];
+          const T x2a = p2[j], x2b = p2[j + 1], x2c = p2[j + 2];
+          const T x3a = p3[j], x3b = p3[j + 1], x3c = p3[j + 2], x3d = p3[j + 3];
+          const T a0 = x0 + x1a, a1 = x0 + x1b;
+          X0[j + lane] = a0 + (x2a + x3a);
+          X2[j + lane] = a0 + (x2b + x3b);
+          X1[j + lane] = a1 + (x2b + x3c);
+          X3[j + lane] = a1 + (x2c + x3d);
+        };
+        for (int c = 0; c < nfull; ++c) unit(c * kWave);
+        if (tail) unit(nfull * kWave);
       }
-      if (c < nfull) {
-        const T a0 = pa[0], x0 = pb0[0], y0 = pb0[1];
-        pa[0] = a0 + x0;
-        pb[0] = a0 + y0;
-        pa += kWave;
-        pb += kWave;
-        pb0 += kWave;
+      l += 2;
+    } else {
+      // One level: pair (A_v, B_v) of each block of 2*half rows gives
+      //   out_{2v}[j] = A_v[j] + B_v[(j + v) mod P0]
+      //   out_{2v+1}[j] = A_v[j] + B_v[(j + v + 1) mod P0]
+      // written over A_v and B_v.  B's halo holds its bins 0..v.
+      for (int p = wave; p < (R >> 1); p += nwaves) {
+        const int beta = p >> (l - 1);
+        const int v = p & (half - 1);
+        T* A = lds + (size_t)(beta * 2 * half + bitrev(v, l - 1)) * S;
+        T* B = A + (size_t)half * S;
+        const int sh = v < P0 ? v : v % P0;
+        const int hn = sh + 1 < H ? sh + 1 : H;  // halo bins this pair reads
+        for (int i = lane; i < hn; i += kWave) B[P0 + i] = B[i];
+        T* pa = A + lane;
+        T* pb = B + lane;
+        const T* pb0 = B + sh + lane;
+        int c = 0;
+        for (; c + 2 <= nfull; c += 2) {
+          const T a0 = pa[0], a1 = pa[kWave];
+          const T x0 = pb0[0], y0 = pb0[1], x1 = pb0[kWave], y1 = pb0[kWave + 1];
+          pa[0] = a0 + x0;
+          pb[0] = a0 + y0;
+          pa[kWave] = a1 + x1;
+          pb[kWave] = a1 + y1;
+          pa += 2 * kWave;
+          pb += 2 * kWave;
+          pb0 += 2 * kWave;
+        }
+        if (c < nfull) {
+          const T a0 = pa[0], x0 = pb0[0], y0 = pb0[1];
+          pa[0] = a0 + x0;
+          pb[0] = a0 + y0;
+          pa += kWave;
+          pb += kWave;
+          pb0 += kWave;
+        }
+        if (tail) {
+          const T a0 = pa[0], x0 = pb0[0], y0 = pb0[1];
+          pa[0] = a0 + x0;
+          pb[0] = a0 + y0;
+        }
       }
-      if (nfull * kWave + lane < P0) {
-        const T a0 = pa[0], x0 = pb0[0], y0 = pb0[1];
-        pa[0] = a0 + x0;
-        pb[0] = a0 + y0;
-      }
+      l += 1;
     }
     __syncthreads();
   }

@@ -56,16 +56,26 @@ void step_widths(const std::vector<int32_t>& user, int32_t P0,
 // LDS row stride of a pass of depth d: P0 bins plus a halo of
 // min(2^(d-1), P0) bins for the shifted butterfly reads; the last pass also
 // needs P0 + wmax + 1 entries for the boxcar prefix sums.
+// Where the LDS budget still allows it at the same depth, the row keeps
+// 3*2^(d-2) spare bins instead, so the kernel can run the top two levels as
+// one radix-4 pass (it reads the spare room from the stride).
 int32_t halo_of(int32_t P0, int32_t d) { return std::min<int32_t>(int32_t(1) << (d - 1), P0); }
 int32_t stride_of(const Step& s, int32_t d, bool last) {
-  const int32_t h = halo_of(s.P0, d);
-  return s.P0 + std::max<int32_t>(h, last ? s.wmax + 1 : 0);
+  const int32_t extra = last ? s.wmax + 1 : 0;
+  const int32_t base = s.P0 + std::max<int32_t>(halo_of(s.P0, d), extra);
+  if (d >= 2) {
+    const int32_t wide = s.P0 + std::max<int32_t>(std::min<int32_t>(3 << (d - 2), s.P0), extra);
+    const int64_t lds = (int64_t(1) << d) * wide * 4 + (last ? (int64_t)kScratchBytes : 0);
+    if (wide > base && lds <= s.lds_budget) return wide;
+  }
+  return base;
 }
 int64_t lds_of(const Step& s, int32_t d, bool last) {
   return (int64_t(1) << d) * stride_of(s, d, last) * 4 + (last ? (int64_t)kScratchBytes : 0);
 }
 
 void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
+  s->lds_budget = lds_budget;
   int32_t dfin = 1, dmid = 1;
   auto fits = [&](int32_t d, bool last) { return lds_of(*s, d, last) <= lds_budget; };
   while (dfin < 24 && fits(dfin + 1, true)) ++dfin;
