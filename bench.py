@@ -91,7 +91,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def workload_units(plan, u8: bool = True, n_widths: int = 10):
+def workload_units(plan, u8: bool = True, n_widths: int = 10, alg: int = 1):
     """trial*samples, algorithmic bytes and algorithmic operations of one search."""
     ts = 0
     in_bytes = 0
@@ -106,8 +106,13 @@ def workload_units(plan, u8: bool = True, n_widths: int = 10):
         in_bytes += st.m * st.P0 * (1 if st.f == 1 and u8 else 4)
         # butterfly: L adds per profile bin; Algorithm 1: 2 ops per bin per
         # width (boxcar difference, running max), 1 prefix add, |x - median|,
-        # and two exact selections at 2 comparisons per bin each.
-        ops += elts * (L + 2 * n_widths + 1 + 1 + 4)
+        # and two exact selections at 2 comparisons per bin each.  Algorithm 2:
+        # 1 prefix add and, per width, the box difference, the running max,
+        # the kept sum, the deviation and its squared sum (5 ops).
+        if alg == 2:
+            ops += elts * (L + 1 + 5 * n_widths)
+        else:
+            ops += elts * (L + 2 * n_widths + 1 + 1 + 4)
     return ts, in_bytes + 8 * trials, ops
 
 
@@ -389,7 +394,7 @@ def main():
     snr = torch.empty(plan.n_trials, dtype=torch.float32, device=dev)
     wid = torch.empty(plan.n_trials, dtype=torch.int32, device=dev)
     ws = plan.workspace(dev)
-    ts, alg_bytes, alg_ops = workload_units(plan, pa.dtype == "u8", len(pa.widths))
+    ts, alg_bytes, alg_ops = workload_units(plan, pa.dtype == "u8", len(pa.widths), a.alg)
 
     best_t = torch.empty(1, dtype=torch.int64, device=dev)
     for _ in range(a.warmup):
