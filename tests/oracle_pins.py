@@ -238,6 +238,30 @@ def pin_alg1_snr_level(o):
     assert 0.90 < ratio < 1.15, ratio
 
 
+def pin_fold_snr_eq7(o):
+    """A top-hat pulsar of height h and duty cycle delta folded at its own
+    period over N samples has matched S/N h*sqrt(delta*N) (Eq. 7, with the
+    pulse energy h*delta*P); with only power-of-two widths in the set the
+    paper reports losses up to about 15% (Sec. 3.2).  Averaged over 30 noise
+    realisations the score of trial 0 (period exactly P0) lands in 0.80 to
+    1.05 of it."""
+    g = np.random.default_rng(33)
+    P0, m, h, w = 200, 163, 0.3, 10
+    M = 256
+    n = m * P0
+    expect = h * math.sqrt(w / P0 * n)
+    vals = []
+    for _ in range(30):
+        x = g.standard_normal(n)
+        j0 = int(g.integers(0, P0))
+        ph = (np.arange(n) - j0) % P0
+        x[ph < w] += h
+        F = o.fold(x, P0, m, M)
+        vals.append(o.alg1(F[0], [1, 2, 4, 8, 16, 32, 64])[0])
+    ratio = float(np.mean(vals)) / expect
+    assert 0.80 <= ratio <= 1.05, ratio
+
+
 def pin_default_widths(o):
     """Powers of two up to the first one exceeding 20% of the profile (Sec. 2.2.1)."""
     assert o.default_widths(256) == [1, 2, 4, 8, 16, 32, 64]
@@ -605,6 +629,7 @@ ALL_PINS = [
     pin_alg1_integer_path,
     pin_alg1_mad_zero,
     pin_alg1_snr_level,
+    pin_fold_snr_eq7,
     pin_alg2_worked_examples,
     pin_alg2_invariants,
     pin_alg2_sigma_zero,
