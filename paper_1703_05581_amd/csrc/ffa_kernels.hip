@@ -372,8 +372,10 @@ struct SelectKnobs {
 // Exact order statistics v1 = key_(k1) and v2 = key_(k2), k2 in {k1, k1+1},
 // of the n real keys in key[E] (pads are kPadKey), given kmin/kmax of the
 // real keys.  A bracket [lo, hi) holding both targets is narrowed by counting
-// keys below a pivot (one ballot per register); pivots interpolate the ranks
-// inside the bracket, falling back to halving it when a round gains little.
+// keys below a pivot (one ballot per register).  With a prior (E <= 8) the
+// first round counts its three pivots at once; later pivots interpolate the
+// ranks inside the bracket, falling back to halving it when a round gains
+// little.
 // Once at most max_cand keys remain in the bracket they are compacted into
 // the wave's LDS scratch and selected exactly.  FKEY: keys encode floats, so
 // interpolation happens on the float values.  Every exit is exact.
