@@ -907,34 +907,43 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
   const int valid = min(R, ph.vin - (h << d));
 
   // stage the group's rows (rows >= valid are zero padding, paper Sec. 2.1).
-  // Element e of the staged block is row e / P0, bin e % P0; loads are
-  // issued in batches so many are in flight.
+  // Each wave copies two whole rows at a time, its lanes walking the bins in
+  // chunks of 64: up to 16 loads in flight per lane, addressed by immediate
+  // offsets from one base per row and group of 8 chunks.
   {
     const T* src = ws + src_off;
-    const uint32_t W = (uint32_t)P0;
-    const uint32_t total = (uint32_t)R * W;
-    const uint32_t real = (uint32_t)valid * W;
-    const uint32_t magic = 0xffffffffu / W;  // floor(2^32 / W): exact after one correction
-    constexpr int kBatch = 8;
-    for (uint32_t base = threadIdx.x; base < total; base += kBatch * kThreads) {
-      T v[kBatch];
+    const int nfull = P0 / kWave;
+    const bool tail = nfull * kWave + lane < P0;
+    for (int r0 = wave; r0 < R; r0 += 2 * nwaves) {
+      const int r1 = r0 + nwaves;
+      const bool has1 = r1 < R;
+      const bool in0 = r0 < valid, in1 = r1 < valid;
+      const T* s0 = src + (size_t)r0 * P0 + lane;
+      const T* s1 = src + (size_t)r1 * P0 + lane;
+      T* d0 = lds + (size_t)r0 * S + lane;
+      T* d1 = lds + (size_t)r1 * S + lane;
+      for (int c0 = 0; c0 < nfull; c0 += 8) {
+        T a[8], b[8];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        const uint32_t e = base + (uint32_t)b * kThreads;
-        v[b] = e < real ? src[e] : (T)0;
-      }
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        const uint32_t e = base + (uint32_t)b * kThreads;
-        if (e < total) {
-          uint32_t row = __umulhi(e, magic);
-          uint32_t col = e - row * W;
-          if (col >= W) {
-            ++row;
-            col -= W;
+        for (int c = 0; c < 8; ++c) {
+          if (c0 + c < nfull) {
+            a[c] = in0 ? s0[(c0 + c) * kWave] : (T)0;
+            b[c] = in1 ? s1[(c0 + c) * kWave] : (T)0;
           }
-          lds[row * (uint32_t)S + col] = v[b];
         }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (c0 + c < nfull) {
+            d0[(c0 + c) * kWave] = a[c];
+            if (has1) d1[(c0 + c) * kWave] = b[c];
+          }
+        }
+      }
+      if (tail) {
+        const T a = in0 ? s0[nfull * kWave] : (T)0;
+        const T b = in1 ? s1[nfull * kWave] : (T)0;
+        d0[nfull * kWave] = a;
+        if (has1) d1[nfull * kWave] = b;
       }
     }
   }
