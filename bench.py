@@ -469,6 +469,21 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    else:
+        # measured streaming peak: a 256 MiB device copy (read + write bytes / time)
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * 5 * COPY_BYTES / (c0.elapsed_time(c1) / 1e3) / 1e9
+        out["hbm"]["copy_GBs"] = copy_gbs
+        out["hbm"]["frac_of_copy"] = out["hbm"]["achieved_GBs"] / copy_gbs
+        del src, dst
 
     if a.check or not a.no_cpu_baseline:
         import oracle
