@@ -613,26 +613,34 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
       dj += dj < 0 ? P0 : 0;
       return dj >= n_ex;
     };
-    double S;
-    if constexpr (INT) {
-      int64_t ss = 0;
-      visit([&](int e, A b) { ss += kept(e) ? (int64_t)(uint32_t)b : 0; });
-      S = (double)wave_sum(ss);
-    } else {
-      double ss = 0.0;
-      visit([&](int e, A b) { ss += kept(e) ? (double)b : 0.0; });
-      S = wave_sum(ss);
+    // One pass over the kept boxes for their mean and population variance,
+    // as sums of d = box - c with c a kept box (the one half a profile from
+    // j*): a flat off-pulse region gives exactly 0, and for integer profiles
+    // the sum of d is exact.
+    const int q = (jstar + P0 / 2) % P0;
+    const A cbox = (A)row[q + w] - (A)row[q];  // the prefix sums give any box
+    double s1, s2 = 0.0;
+    {
+      // for integer profiles every box and d are integers below 2^32, and
+      // their sums below 2^53, so s1 is exact in double
+      const double cd = as_double(cbox);
+      double t1 = 0.0;
+      visit([&](int e, A b) {
+        const double dv = as_double(b) - cd;
+        const bool k = kept(e);
+        t1 += k ? dv : 0.0;
+        s2 += k ? dv * dv : 0.0;
+      });
+      s1 = wave_sum(t1);
     }
-    const double mean = S / (double)cnt;
-    double v = 0.0;
-    visit([&](int e, A b) {
-      const double t = as_double(b) - mean;
-      v += kept(e) ? t * t : 0.0;
-    });
-    const double sd = sqrt(wave_sum(v) / (double)cnt);
-    double peak;
-    if constexpr (INT) peak = (double)pk;
-    else peak = (double)fval(pk);
+    s2 = wave_sum(s2);
+    const double mrel = s1 / (double)cnt;  // kept mean - c
+    const double var = (s2 - s1 * mrel) / (double)cnt;
+    const double sd = var > 0.0 ? sqrt(var) : 0.0;
+    double peak;  // relative to c
+    if constexpr (INT) peak = (double)pk - as_double(cbox);
+    else peak = (double)fval(pk) - (double)cbox;
+    const double mean = mrel;
     // w = P0: every box is the whole profile, so sigma is exactly 0
     const double a = (sd > 0.0 && w < P0) ? (peak - mean) / sd : 0.0;
     if (i == 0 || a > best) {
