@@ -138,3 +138,21 @@ def test_sift_search_output(torch_cuda, ffa, oracle_mod):
     top = got["period"][:5]
     for p in psrs:
         assert np.min(np.abs(top - p.period_s) / p.period_s) < 2e-3, (p.period_s, top)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_sift_random_parameters(torch_cuda, ffa, oracle_mod, plans, seed):
+    """Random thresholds, group widths, prime limits and tolerances on random
+    synthetic periodograms: identical candidate lists."""
+    torch = torch_cuda
+    gp, op = plans
+    g = np.random.default_rng(500 + seed)
+    snr, width = synthetic_periodogram(op, seed=900 + seed, quantised=bool(g.random() < 0.3))
+    prm = (float(g.uniform(6.0, 12.0)), float(g.choice([0.0, 0.02, 0.1, 0.3])), float(g.choice([0.0, 0.25, 1.0, 2.0])),
+           float(g.choice([0.0, 0.5, 2.0, 10.0])), int(g.choice([0, 2, 3, 7, 31, 97])),
+           float(g.choice([1e-6, 1e-5, 1e-4, 1e-3])))
+    want = oracle_mod.sift(snr, width, op, *prm)
+    if oracle_mod.sift(snr, width, op, *prm[:3]).size > 16384:
+        pytest.skip("more peaks than the GPU scratch holds")
+    got = gp.sift(torch.from_numpy(snr).cuda(), torch.from_numpy(width).cuda(), *prm, max_cands=16384)
+    _same(got, want)
