@@ -211,8 +211,11 @@ typedef struct {
  * d_cands (device, room for max_cands), strongest first.  *d_n_cands
  * (device) receives the number of candidates found (only the first max_cands
  * are written), or -1 when more than 16384 peaks pass the thresholds (raise
- * min_snr).  The plan's workspace is used as scratch (its contents are not
- * needed after a search).  Asynchronous on `stream`.  Errors:
+ * min_snr).  The plan's workspace (d_ws, at least the plan's ws_bytes,
+ * 256-B aligned) is used as scratch; its contents are not needed after a
+ * search.  Parameters: min_snr finite, 0 <= frac_fall <= 1, abs_fall,
+ * group_widths and harmonic_tol finite and >= 0, harmonic_primes <= 1000,
+ * max_cands >= 0 (0: count only).  Asynchronous on `stream`.  Errors:
  * FFA_ERR_INVALID (bad parameter, small workspace), FFA_ERR_DEVICE. */
 ffa_status ffa_sift(ffa_plan plan, const float* d_snr, const int32_t* d_width,
                     const ffa_sift_params* params, ffa_candidate* d_cands,
