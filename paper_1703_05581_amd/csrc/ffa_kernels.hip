@@ -1387,6 +1387,25 @@ __global__ __launch_bounds__(1024) void sift_final_kernel(
     }
   }
   if (harmonic_primes >= 2) {
+    // the primes up to the limit (168 below 1000)
+    __shared__ int32_t primes[168];
+    __shared__ int32_t n_primes;
+    if (threadIdx.x == 0) {
+      int32_t k = 0;
+      for (int32_t x = 2; x <= harmonic_primes && k < 168; ++x)
+        if (is_prime(x)) primes[k++] = x;
+      n_primes = k;
+    }
+    __syncthreads();
+    const double tol = (double)harmonic_tol;
+    // n in [lo, hi] of 1..x-1 around a real bound pair, with one bin of margin
+    // for the rounding of the bounds
+    auto span = [](double a, double b, int32_t x, int32_t& lo, int32_t& hi) {
+      lo = a > (double)x ? x : (int32_t)floor(fmax(a, 0.0)) - 1;
+      hi = b > (double)x ? x - 1 : (int32_t)ceil(fmax(b, 0.0)) + 1;
+      lo = lo < 1 ? 1 : lo;
+      hi = hi > x - 1 ? x - 1 : hi;
+    };
     for (int r = 0; r < np; ++r) {
       const int i = order[r];
       if (alive[i]) {
@@ -1395,14 +1414,24 @@ __global__ __launch_bounds__(1024) void sift_final_kernel(
           const int j = order[r2];
           if (!alive[j]) continue;
           const double Pj = period[j];
+          const double rho = Pj / Pi;
           bool related = false;
-          for (int32_t x = 2; x <= harmonic_primes && !related; ++x) {
-            if (!is_prime(x)) continue;
-            for (int32_t nn = 1; nn < x && !related; ++nn) {
+          // P*n/x within tol of Pj needs n in [x*rho/(1+tol), x*rho/(1-tol)];
+          // P*x/n needs n in [x*(1-tol)/rho, x*(1+tol)/rho].  Each n there is
+          // tested with the same expression as the full scan over 0 < n < x,
+          // so the decision is the same.
+          for (int q = 0; q < n_primes && !related; ++q) {
+            const int32_t x = primes[q];
+            int32_t lo, hi;
+            span((double)x * rho / (1.0 + tol), tol < 1.0 ? (double)x * rho / (1.0 - tol) : 1e300, x, lo, hi);
+            for (int32_t nn = lo; nn <= hi && !related; ++nn) {
               const double r1 = Pi * (double)nn / (double)x;
+              if (fabs(Pj - r1) <= tol * r1) related = true;
+            }
+            span((double)x * (1.0 - tol) / rho, (double)x * (1.0 + tol) / rho, x, lo, hi);
+            for (int32_t nn = lo; nn <= hi && !related; ++nn) {
               const double r2v = Pi * (double)x / (double)nn;
-              if (fabs(Pj - r1) <= (double)harmonic_tol * r1) related = true;
-              if (fabs(Pj - r2v) <= (double)harmonic_tol * r2v) related = true;
+              if (fabs(Pj - r2v) <= tol * r2v) related = true;
             }
           }
           if (related) alive[j] = 0;
