@@ -32,3 +32,16 @@ def test_three_pass_and_small_windows(monkeypatch):
     assert L["lookahead"] == 1
     monkeypatch.setenv("FFA_LOOKAHEAD", "3")
     check(ffa.Plan(300000, 1e-3, 0.2, 2.0, 100, None))
+
+
+@pytest.mark.parametrize("lds_kb", [24, 48, 96, 160])
+def test_lds_budgets(monkeypatch, lds_kb):
+    """Smaller tile LDS budgets give shallower tiles, more passes and a
+    different halo room (so a different mix of radix-2 and radix-4 levels);
+    every tile still fits and every dependency is met."""
+    monkeypatch.setenv("FFA_TILE_LDS", str(lds_kb * 1024))
+    for args in [(150000, 1e-3, 0.1, 1.5, 97, None, "f32"), (300000, 1e-3, 0.3, 3.0, 300, None, "u8"),
+                 (80000, 1e-3, 0.01, 0.2, 8, [1, 2, 4], "u8")]:
+        p = ffa.Plan(*args)
+        L = check(p)
+        assert L["lds_bytes"] <= lds_kb * 1024
