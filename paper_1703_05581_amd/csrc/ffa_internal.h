@@ -53,7 +53,8 @@ struct Phase {
   int32_t nw;
   int32_t isqrt_ofs;    // the step's 1/sqrt(width) values in the sqrt table
   int32_t launch;       // index of the launch that runs the phase
-  int32_t pad_[2];
+  int32_t u16;          // 1: the tile keeps its rows as 16-bit sums in LDS
+  int32_t pad_[1];
 };
 static_assert(sizeof(Phase) == 96, "phase layout");
 
@@ -90,6 +91,7 @@ struct Step {
   int32_t lds_bytes;          // largest LDS footprint of its passes
   int32_t fold_phase0;        // its phases in pass order, in Plan::fold_phases
   int64_t lds_budget = 0;     // LDS bytes a tile may use
+  int32_t u16_first = 0;      // the first of two passes keeps 16-bit sums
 };
 
 // One launch of a search: a window of the queue whose tiles depend only on

@@ -877,6 +877,74 @@ __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint
 #undef FFA_SCORE
 }
 
+// Copy a tile's 2^d rows (R rows of P0 bins, contiguous at src) into LDS
+// rows of stride S; rows >= valid are zero padding (paper Sec. 2.1).  Each
+// wave copies two whole rows at a time, its lanes walking the bins in chunks
+// of 64: up to 16 loads in flight per lane, addressed by immediate offsets
+// from one base per row and group of 8 chunks.  TL may be narrower than TS
+// when the caller knows the values fit.
+template <typename TL, typename TS>
+__device__ __forceinline__ void stage_rows(TL* lds, const TS* src, int R, int valid, int P0, int S) {
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int nwaves = blockDim.x / kWave;
+  const int nfull = P0 / kWave;
+  const bool tail = nfull * kWave + lane < P0;
+  for (int r0 = wave; r0 < R; r0 += 2 * nwaves) {
+    const int r1 = r0 + nwaves;
+    const bool has1 = r1 < R;
+    const bool in0 = r0 < valid, in1 = r1 < valid;
+    const TS* s0 = src + (size_t)r0 * P0 + lane;
+    const TS* s1 = src + (size_t)r1 * P0 + lane;
+    TL* d0 = lds + (size_t)r0 * S + lane;
+    TL* d1 = lds + (size_t)r1 * S + lane;
+    for (int c0 = 0; c0 < nfull; c0 += 8) {
+      TS a[8], b[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c0 + c < nfull) {
+          a[c] = in0 ? s0[(c0 + c) * kWave] : (TS)0;
+          b[c] = in1 ? s1[(c0 + c) * kWave] : (TS)0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c0 + c < nfull) {
+          d0[(c0 + c) * kWave] = (TL)a[c];
+          if (has1) d1[(c0 + c) * kWave] = (TL)b[c];
+        }
+      }
+    }
+    if (tail) {
+      const TS a = in0 ? s0[nfull * kWave] : (TS)0;
+      const TS b = in1 ? s1[nfull * kWave] : (TS)0;
+      d0[nfull * kWave] = (TL)a;
+      if (has1) d1[nfull * kWave] = (TL)b;
+    }
+  }
+}
+
+// Hand partial t of a first-pass tile (LDS row bitrev(t, d)) to the next
+// pass, rotated left by t*h bins, at out0 + t*dst_step: the levels above
+// this pass then act on the rotated rows like a plain FFA tree.
+template <typename TL, typename TO>
+__device__ __forceinline__ void write_partials(const TL* lds, TO* out0, int R, int d, int S, int P0,
+                                               int64_t dst_step, int h) {
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int nwaves = blockDim.x / kWave;
+  for (int tt = wave; tt < R; tt += nwaves) {
+    const TL* srow = lds + (size_t)bitrev(tt, d) * S;
+    const int rot = (int)(((int64_t)tt * h) % P0);
+    TO* out = out0 + (int64_t)tt * dst_step;
+    for (int j = lane; j < P0; j += kWave) {
+      int i = j + rot;
+      i -= (i >= P0) ? P0 : 0;
+      out[j] = (TO)srow[i];
+    }
+  }
+}
+
 // ------------------------------------------------------------- tile kernel
 
 // One workgroup per tile.  A launch covers tiles whose inputs were all
@@ -914,47 +982,19 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
   const int64_t src_off = in_base + ((int64_t)q * Gin + ((int64_t)h << d)) * P0;
   const int valid = min(R, ph.vin - (h << d));
 
-  // stage the group's rows (rows >= valid are zero padding, paper Sec. 2.1).
-  // Each wave copies two whole rows at a time, its lanes walking the bins in
-  // chunks of 64: up to 16 loads in flight per lane, addressed by immediate
-  // offsets from one base per row and group of 8 chunks.
-  {
-    const T* src = ws + src_off;
-    const int nfull = P0 / kWave;
-    const bool tail = nfull * kWave + lane < P0;
-    for (int r0 = wave; r0 < R; r0 += 2 * nwaves) {
-      const int r1 = r0 + nwaves;
-      const bool has1 = r1 < R;
-      const bool in0 = r0 < valid, in1 = r1 < valid;
-      const T* s0 = src + (size_t)r0 * P0 + lane;
-      const T* s1 = src + (size_t)r1 * P0 + lane;
-      T* d0 = lds + (size_t)r0 * S + lane;
-      T* d1 = lds + (size_t)r1 * S + lane;
-      for (int c0 = 0; c0 < nfull; c0 += 8) {
-        T a[8], b[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          if (c0 + c < nfull) {
-            a[c] = in0 ? s0[(c0 + c) * kWave] : (T)0;
-            b[c] = in1 ? s1[(c0 + c) * kWave] : (T)0;
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          if (c0 + c < nfull) {
-            d0[(c0 + c) * kWave] = a[c];
-            if (has1) d1[(c0 + c) * kWave] = b[c];
-          }
-        }
-      }
-      if (tail) {
-        const T a = in0 ? s0[nfull * kWave] : (T)0;
-        const T b = in1 ? s1[nfull * kWave] : (T)0;
-        d0[nfull * kWave] = a;
-        if (has1) d1[nfull * kWave] = b;
-      }
+  if constexpr (INT) {
+    if (ph.u16) {  // a first pass whose sums stay below 2^16 (the planner checks)
+      uint16_t* l16 = reinterpret_cast<uint16_t*>(lds_raw);
+      stage_rows(l16, ws + src_off, R, valid, P0, S);
+      __syncthreads();
+      butterfly<uint16_t>(l16, S, P0, H, d);
+      const int64_t Gout = Gin >> d;
+      write_partials(l16, ws + ((ph.pass & 1) ? buf1 : buf0) + (((int64_t)q << d) * Gout + h) * P0, R, d, S, P0,
+                     Gout * P0, h);
+      return;
     }
   }
+  stage_rows(lds, ws + src_off, R, valid, P0, S);
   __syncthreads();
 
   butterfly<T>(lds, S, P0, H, d);
@@ -963,18 +1003,8 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
     // Hand partial t to the next pass rotated left by t*h bins: the levels
     // above this pass then act on the rotated rows like a plain FFA tree.
     const int64_t Gout = Gin >> d;
-    T* out0 = ws + ((ph.pass & 1) ? buf1 : buf0) + (((int64_t)q << d) * Gout + h) * P0;
-    const int64_t dst_step = Gout * P0;
-    for (int tt = wave; tt < R; tt += nwaves) {
-      const T* srow = lds + (size_t)bitrev(tt, d) * S;
-      const int rot = (int)(((int64_t)tt * h) % P0);
-      T* out = out0 + (int64_t)tt * dst_step;
-      for (int j = lane; j < P0; j += kWave) {
-        int i = j + rot;
-        i -= (i >= P0) ? P0 : 0;
-        out[j] = srow[i];
-      }
-    }
+    write_partials(lds, ws + ((ph.pass & 1) ? buf1 : buf0) + (((int64_t)q << d) * Gout + h) * P0, R, d, S, P0,
+                   Gout * P0, h);
   } else if (a.mode == kModeProfiles) {
     T* out = reinterpret_cast<T*>(a.profiles) +
              (ph.first_trial + ((int64_t)q << d) - a.trial_base) * (int64_t)P0;

@@ -60,19 +60,21 @@ void step_widths(const std::vector<int32_t>& user, int32_t P0,
 // 3*2^(d-2) spare bins instead, so the kernel can run the top two levels as
 // one radix-4 pass (it reads the spare room from the stride).
 int32_t halo_of(int32_t P0, int32_t d) { return std::min<int32_t>(int32_t(1) << (d - 1), P0); }
-int32_t stride_of(const Step& s, int32_t d, bool last) {
+// esz: bytes per LDS element (4, or 2 for a 16-bit first pass).
+int32_t stride_of(const Step& s, int32_t d, bool last, int32_t esz = 4) {
   const int32_t extra = last ? s.wmax + 1 : 0;
   const int32_t base = s.P0 + std::max<int32_t>(halo_of(s.P0, d), extra);
   if (d >= 2) {
     const int32_t wide = s.P0 + std::max<int32_t>(std::min<int32_t>(3 << (d - 2), s.P0), extra);
-    const int64_t lds = (int64_t(1) << d) * wide * 4 + (last ? (int64_t)kScratchBytes : 0);
+    const int64_t lds = (int64_t(1) << d) * wide * esz + (last ? (int64_t)kScratchBytes : 0);
     if (wide > base && lds <= s.lds_budget) return wide;
   }
   return base;
 }
-int64_t lds_of(const Step& s, int32_t d, bool last) {
-  return (int64_t(1) << d) * stride_of(s, d, last) * 4 + (last ? (int64_t)kScratchBytes : 0);
+int64_t lds_of(const Step& s, int32_t d, bool last, int32_t esz = 4) {
+  return (int64_t(1) << d) * stride_of(s, d, last, esz) * esz + (last ? (int64_t)kScratchBytes : 0);
 }
+int32_t esz_of(const Phase& ph) { return ph.u16 ? 2 : 4; }
 
 void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
   s->lds_budget = lds_budget;
@@ -171,7 +173,8 @@ bool phases_valid(const ffa_plan_s* p) {
     if ((int64_t)ph.ntiles != Q * ph.ng || ph.ng < 1 || ph.vin < 1) return false;
     if (ph.halo < std::min<int64_t>(R / 2, s.P0) || ph.halo > s.P0) return false;
     if (ph.stride < s.P0 + ph.halo || (last && ph.stride < s.P0 + s.wmax + 1)) return false;
-    const int64_t lds = R * ph.stride * 4 + (last ? (int64_t)kScratchBytes : 0);
+    if (ph.u16 && (ph.pass != 0 || last || !p->acc_int || s.octave + dp > 8)) return false;
+    const int64_t lds = R * ph.stride * esz_of(ph) + (last ? (int64_t)kScratchBytes : 0);
     if (lds > (int64_t)kLdsBytes || lds > w.lds_bytes || ph.P0 > w.max_P0) return false;
     if (ph.wofs != s.wofs || ph.nw != s.nw || (last && s.nw < 1)) return false;
     if (s.n_passes > 1 && MP * (s.n_passes > 2 ? 2 : 1) > p->slot_elems) return false;
@@ -331,6 +334,9 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   // smaller tiles (more passes) at higher occupancy.
   const int64_t lds_budget = env_int("FFA_TILE_LDS", (int64_t)kLdsBytes, 16384, (int64_t)kLdsBytes);
   const int32_t split_mode = (int32_t)env_int("FFA_SPLIT_MODE", 1, 0, 2);
+  // 16-bit first passes (uint8 input without dereddening): see below
+  const bool int_mode = d->dtype == FFA_IN_U8 && d->dered_window == 0;
+  const bool allow_u16 = int_mode && env_int("FFA_U16", 1, 0, 1) != 0;
 
   // --- steps (octave f = 2^o; P0 in [B, 2B) with pmin <= P0*f*tsamp < pmax)
   const int64_t B = d->bins_min;
@@ -373,6 +379,24 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
         p->sqrtw.push_back(std::sqrt((double)w));
       }
       split_passes(&s, lds_budget, split_mode);
+      // A two-pass step whose last pass needs more than half the CU's LDS
+      // runs one workgroup per CU there.  For uint8 input the first pass can
+      // hold its sums in 16 bits while 255 * 2^(octave + depth) < 2^16; the
+      // half-size rows let it take more levels, and the last pass fewer, so
+      // that two scoring workgroups share a CU (profiles of up to 512 bins,
+      // whose kernel holds 8 waves per SIMD).
+      if (allow_u16 && s.n_passes == 2 && s.P0 <= 512 && lds_of(s, s.depth[1], true) > (int64_t)kLdsBytes / 2) {
+        for (int32_t dl = s.depth[1] - 1; dl >= 1; --dl) {
+          const int32_t d0 = s.L - dl;
+          if (o + d0 > 8) break;
+          if (lds_of(s, dl, true) <= (int64_t)kLdsBytes / 2 && lds_of(s, d0, false, 2) <= lds_budget) {
+            s.depth[0] = d0;
+            s.depth[1] = dl;
+            s.u16_first = 1;
+            break;
+          }
+        }
+      }
       if (s.n_passes > kMaxPasses) {
         delete p;
         return fail(FFA_ERR_UNSUPPORTED, "step needs too many passes");
@@ -459,14 +483,15 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
       ph.depth = dp;
       ph.D = D;
       ph.vin = (int32_t)vin;
-      ph.stride = stride_of(s, dp, last);
+      ph.u16 = pass == 0 && s.u16_first ? 1 : 0;
+      ph.stride = stride_of(s, dp, last, esz_of(ph));
       ph.halo = halo_of(s.P0, dp);
       ph.wofs = s.wofs;
       ph.nw = s.nw;
       ph.isqrt_ofs = nsq + s.wofs;
       s.tiles[pass] = (int32_t)nt;
       s.total_tiles += (int32_t)nt;
-      s.lds_bytes = std::max<int32_t>(s.lds_bytes, (int32_t)lds_of(s, dp, last));
+      s.lds_bytes = std::max<int32_t>(s.lds_bytes, (int32_t)lds_of(s, dp, last, esz_of(ph)));
       nat.push_back(ph);
       D += dp;
     }
@@ -505,7 +530,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   const bool split = env_int("FFA_SPLIT_OCCUPANCY", 1, 0, 1) != 0;
   auto occ_class = [&](const Phase& ph) {
     if (!split) return (int32_t)0;
-    const int64_t lds = lds_of(p->steps[ph.step], ph.depth, ph.last != 0);
+    const int64_t lds = lds_of(p->steps[ph.step], ph.depth, ph.last != 0, esz_of(ph));
     return (int32_t)std::min<int64_t>(4, (int64_t)kLdsBytes / std::max<int64_t>(lds, 1));
   };
   for (size_t i = 0; i < nat.size(); ++i)
@@ -531,7 +556,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     ph.launch = (int32_t)(p->launches.size() - 1);
     ph.tile0 = t0;
     ln.ntiles += ph.ntiles;
-    ln.lds_bytes = std::max<int32_t>(ln.lds_bytes, (int32_t)lds_of(p->steps[ph.step], ph.depth, ph.last != 0));
+    ln.lds_bytes = std::max<int32_t>(ln.lds_bytes, (int32_t)lds_of(p->steps[ph.step], ph.depth, ph.last != 0, esz_of(ph)));
     ln.max_P0 = std::max(ln.max_P0, ph.P0);
     const int32_t idx = (int32_t)p->phases.size();
     for (int32_t j = 0; j < ph.ntiles; ++j) p->tile_phase.push_back(idx);

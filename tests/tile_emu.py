@@ -13,7 +13,7 @@ PHASE_DT = np.dtype([
     ("ntiles", "<i4"), ("ng", "<i4"), ("step", "<i4"), ("pass_", "<i4"), ("last", "<i4"),
     ("P0", "<i4"), ("M", "<i4"), ("depth", "<i4"), ("D", "<i4"), ("vin", "<i4"),
     ("stride", "<i4"), ("halo", "<i4"), ("wofs", "<i4"), ("nw", "<i4"), ("isqrt_ofs", "<i4"),
-    ("launch", "<i4"), ("pad0", "<i4"), ("pad1", "<i4")])
+    ("launch", "<i4"), ("u16", "<i4"), ("pad1", "<i4")])
 assert PHASE_DT.itemsize == 96
 SCRATCH = 16 * 64 * 4
 LDS_MAX = 160 * 1024
@@ -73,7 +73,13 @@ def check(plan):
         assert w0 <= x["tile0"] and x["tile0"] + x["ntiles"] <= w0 + wn, "phase outside its launch"
         s, p, P0, M = int(x["step"]), int(x["pass_"]), int(x["P0"]), int(x["M"])
         d, R = int(x["depth"]), 1 << int(x["depth"])
-        lds = R * int(x["stride"]) * 4 + (SCRATCH if x["last"] else 0)
+        esz = 2 if x["u16"] else 4
+        if x["u16"]:
+            # 16-bit rows only on a first pass of a uint8 plan whose sums fit
+            octave = plan.step(s).f.bit_length() - 1
+            assert p == 0 and not x["last"] and plan.dtype == "u8" and not plan.dered_window, s
+            assert 255 * 2 ** (octave + d) < 65536, (s, octave, d)
+        lds = R * int(x["stride"]) * esz + (SCRATCH if x["last"] else 0)
         assert lds <= wlds <= LDS_MAX and P0 <= wp0
         slot = s % L["n_slots"]
         slot0 = L["ring_off"] + slot * L["slot_elems"]
