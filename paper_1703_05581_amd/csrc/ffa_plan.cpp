@@ -397,6 +397,12 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
           }
         }
       }
+      // Likewise a first pass that needs more than half the LDS in 32 bits
+      // but not in 16 runs two workgroups per CU with 16-bit rows.
+      if (allow_u16 && s.n_passes == 2 && !s.u16_first && s.P0 <= 512 && o + s.depth[0] <= 8 &&
+          lds_of(s, s.depth[0], false) > (int64_t)kLdsBytes / 2 &&
+          lds_of(s, s.depth[0], false, 2) <= std::min<int64_t>((int64_t)kLdsBytes / 2, lds_budget))
+        s.u16_first = 1;
       if (s.n_passes > kMaxPasses) {
         delete p;
         return fail(FFA_ERR_UNSUPPORTED, "step needs too many passes");
