@@ -285,3 +285,24 @@ def test_alg2_workload2_sampled(torch_cuda, ffa, oracle_mod):
     pa = s.plan
     run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
              list(pa.widths), "u8", steps_max=16, alg=2)
+
+
+def test_u16_first_passes_agree(torch_cuda, ffa, monkeypatch):
+    """uint8 steps whose first pass keeps 16-bit sums give the same
+    periodogram, bit for bit, as with 32-bit rows everywhere."""
+    from tile_emu import phases
+
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload2(0)
+    x = torch_cuda.from_numpy(s.data).cuda()
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("FFA_U16", flag)
+        plan = ffa.Plan.from_args(s.plan)
+        n16 = int(phases(plan)["u16"].sum())
+        assert (n16 > 0) == (flag == "1"), n16
+        print("u16", flag, "phases", n16, flush=True)
+        outs.append([t.clone() for t in plan.search(x)])
+        torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(outs[0][0], outs[1][0]) and torch_cuda.equal(outs[0][1], outs[1][1])
