@@ -337,24 +337,20 @@ __device__ __forceinline__ uint32_t lane_select(uint32_t c, int cnt, int t) {
   return c;  // not reached: the loop ends by returning
 }
 
-// Counts of the keys below three pivots, in one pass: per-lane counts packed
-// 10 bits apart, one wave sum (valid while n <= 1023).
+// Counts of the keys below three pivots: one compare per key and pivot, the
+// ballots counted on the scalar unit (the vector unit is the busier one).
 template <int E>
 __device__ __forceinline__ void count_lt3(const uint32_t (&key)[E], const uint32_t (&t)[3], int (&c)[3]) {
-  uint32_t acc = 0;
+  int c0 = 0, c1 = 0, c2 = 0;
 #pragma unroll
-  for (int r = 0; r < E; ++r)
-    acc += (key[r] < t[0] ? 1u : 0u) + (key[r] < t[1] ? (1u << 10) : 0u) + (key[r] < t[2] ? (1u << 20) : 0u);
-  acc += dpp<kDppXor1>(0u, acc);
-  acc += dpp<kDppXor2>(0u, acc);
-  acc += dpp<kDppHalfMirror>(0u, acc);
-  acc += dpp<kDppRowMirror>(0u, acc);
-  acc += dpp<kDppBcast15, 0xA>(0u, acc);
-  acc += dpp<kDppBcast31, 0xC>(0u, acc);
-  const uint32_t s = readlane(acc, 63);
-  c[0] = (int)(s & 1023u);
-  c[1] = (int)((s >> 10) & 1023u);
-  c[2] = (int)(s >> 20);
+  for (int r = 0; r < E; ++r) {
+    c0 += wave_count(key[r] < t[0]);
+    c1 += wave_count(key[r] < t[1]);
+    c2 += wave_count(key[r] < t[2]);
+  }
+  c[0] = c0;
+  c[1] = c1;
+  c[2] = c2;
 }
 
 // Three ascending first pivots for a selection (a guess from the profile's
