@@ -49,6 +49,7 @@ constexpr int kDppHalfMirror = 0x141; // lane i <- 7-i within 8
 constexpr int kDppBcast15 = 0x142;    // lane 15 of each row -> next row
 constexpr int kDppBcast31 = 0x143;    // lane 31 -> rows 2 and 3
 constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppRor4 = 0x124, kDppRor8 = 0x128;  // lane i <- (i - n) mod 16 within a row
 
 template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
@@ -57,6 +58,15 @@ __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// A value the wave holds in every lane, marked as such for the compiler
+// (scalar registers, uniform branches).
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float uniform(float v) {
+  return __uint_as_float((uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(v)));
 }
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
@@ -71,6 +81,35 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
   v = umax(v, dpp<kDppBcast15, 0xA>(0u, v));
   v = umax(v, dpp<kDppBcast31, 0xC>(0u, v));
   return readlane(v, 63);
+}
+
+// Wave maxima of eight values at once: lane L returns the maximum over all
+// lanes of v[L & 7].  Three exchange steps each halve what a lane keeps
+// (partners keep opposite halves, so every value is combined once per step),
+// one row rotation and two lane permutes finish the reduction, and a last
+// permute moves each maximum to the lanes of its index.
+__device__ __forceinline__ uint32_t bpermute(int src_lane, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)v);
+}
+
+__device__ __forceinline__ uint32_t wave_umax8(const uint32_t (&v)[8]) {
+  const int lane = lane_id();
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  uint32_t r[4], s[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)  // r[j]: index j + 4*b0, over lanes L and L^1
+    r[j] = umax(b0 ? v[j + 4] : v[j], dpp<kDppXor1>(0u, b0 ? v[j] : v[j + 4]));
+#pragma unroll
+  for (int j = 0; j < 2; ++j)  // s[j]: index j + 2*b1 + 4*b0, over the quad
+    s[j] = umax(b1 ? r[j + 2] : r[j], dpp<kDppXor2>(0u, b1 ? r[j] : r[j + 2]));
+  // index b2 + 2*b1 + 4*b0 (bits of L reversed), over two quads of the row
+  // (lane L - 4 mod 16 has the other b2 and the same b0, b1)
+  uint32_t t = umax(b2 ? s[1] : s[0], dpp<kDppRor4>(0u, b2 ? s[0] : s[1]));
+  t = umax(t, dpp<kDppRor8>(0u, t));  // the other two quads: the whole row
+  t = umax(t, bpermute(lane ^ 16, t));
+  t = umax(t, bpermute(lane ^ 32, t));
+  const int k = lane & 7;
+  return bpermute(((k & 1) << 2) | (k & 2) | (k >> 2), t);
 }
 
 __device__ __forceinline__ uint32_t wave_umin(uint32_t v) {
@@ -334,7 +373,7 @@ __device__ __forceinline__ uint32_t lane_select(uint32_t c, int cnt, int t) {
       active &= ~(lt | eq);
     }
   }
-  return c;  // not reached: the loop ends by returning
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)c);  // not reached: the loop returns
 }
 
 // Counts of the keys below three pivots: one compare per key and pivot, the
@@ -358,6 +397,13 @@ __device__ __forceinline__ void count_lt3(const uint32_t (&key)[E], const uint32
 struct Prior {
   bool on;
   uint32_t t[3];
+};
+
+// What a wave carries from one profile to the next for the first pivots:
+// the profiles' common mean and the spread of the last one (0: unknown).
+struct WavePrior {
+  float mean;
+  float sd;
 };
 
 struct SelectKnobs {
@@ -428,9 +474,10 @@ __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int
     const int cand = c_hi - c_lo;
     if (cand <= kn.max_cand) {
       int base = 0;
+      const uint32_t span = hi - lo;
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        const bool in = key[r] >= lo && key[r] < hi;
+        const bool in = key[r] - lo < span;  // lo <= key < hi, one compare
         const uint64_t m = __ballot(in);
         const int pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -502,6 +549,13 @@ struct Types<false> {
   using A = float;
 };
 
+// Registers of a profile's lane layout (bin j in register j/64) that hold 64
+// real bins for every P0 that score_dispatch sends to an E-register scorer:
+// P0 > 64(E-1) for E <= 8, and above the previous case's bound for the
+// larger E.  Their bounds checks then fold away at compile time.
+template <int E>
+constexpr int kFullRegs = E <= 8 ? E - 1 : (E == 12 ? 8 : (E == 16 ? 12 : (E == 24 ? 16 : 24)));
+
 // Circular prefix sums of the profile in `row`, in place: afterwards row[k] =
 // C[k] = sum_{i<k} F[i mod P0] for k <= P0 + wmax, and cex[r] holds C[j] of
 // the lane's bin j = 64r + lane.  A box of width w starting at j is then
@@ -516,7 +570,7 @@ __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = r * kWave + lane;
-    xv[r] = e < P0 ? (A)row[e] : (A)0;
+    xv[r] = (r < kFullRegs<E> || e < P0) ? (A)row[e] : (A)0;
   }
   wave_lds_sync();
   A carry = (A)0;
@@ -525,7 +579,7 @@ __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int
     const int e = r * kWave + lane;
     const A s = wave_scan(xv[r]);
     cex[r] = carry + s - xv[r];
-    if (e < P0) row[e + 1] = (T)(carry + s);
+    if (r < kFullRegs<E> || e < P0) row[e + 1] = (T)(carry + s);
     if constexpr (INT) carry += readlane(s, 63);
     else carry += __uint_as_float(readlane(__float_as_uint(s), 63));
   }
@@ -586,7 +640,7 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
       if constexpr (kRegs) {
 #pragma unroll
         for (int r = 0; r < E; ++r)
-          if (r * kWave + lane < P0) f(r * kWave + lane, breg[r]);
+          if (r < kFullRegs<E> || r * kWave + lane < P0) f(r * kWave + lane, breg[r]);
       } else {
         for (int e = lane; e < P0; e += kWave) f(e, (A)row[e + w] - (A)row[e]);
       }
@@ -662,7 +716,8 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
 // a host table, so every rounding is a correctly rounded IEEE operation.
 template <int E, bool INT>
 __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
-                              const WidthLanes& wt, int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
+                              const WidthLanes& wt, int nw, SelectKnobs kn, WavePrior& wp, float* snr_out,
+                              int32_t* width_out) {
   using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
   const int lane = lane_id();
@@ -674,7 +729,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = r * kWave + lane;
-    const bool real = e < P0;
+    const bool real = r < kFullRegs<E> || e < P0;
     if constexpr (INT) key[r] = real ? (uint32_t)row[e] : kPadKey;
     else key[r] = real ? fkey(row[e]) : kPadKey;
     kmin = umin(kmin, key[r]);
@@ -682,39 +737,42 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   }
   kmin = wave_umin(kmin);
   kmax = wave_umax(kmax);
-  // Mean and spread of the profile in float, relative to its minimum: they
-  // only place the selections' first pivots (about 2.5 standard errors either
-  // side of the expected median and MAD of normal noise).
+  // Mean and spread of the profile in float: they only place the selections'
+  // first pivots (about 2.5 standard errors either side of the expected
+  // median and MAD of normal noise).  Every profile of an FFA execution sums
+  // the same samples, so the mean is shared; the spread is taken from the
+  // previous profile's MAD.  The wave's first profile, and any after a zero
+  // MAD, computes both from its moments.
   Prior pm{false, {0u, 0u, 0u}}, pd{false, {0u, 0u, 0u}};
-  float sd = 0.f, mu_y = 0.f;
+  float sd = 0.f;
   if constexpr (E <= 8) {
-    float s1 = 0.f, s2 = 0.f;
-    const float base = INT ? 0.f : fval(kmin);
+    if (__builtin_amdgcn_readfirstlane(wp.sd > 0.f ? 1 : 0) == 0) {
+      float s1 = 0.f, s2 = 0.f;
+      const float base = INT ? (float)kmin : fval(kmin);
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      if (r * kWave + lane < P0) {
-        const float y = INT ? (float)(key[r] - kmin) : fval(key[r]) - base;
-        s1 += y;
-        s2 += y * y;
+      for (int r = 0; r < E; ++r) {
+        if (r < kFullRegs<E> || r * kWave + lane < P0) {
+          const float y = INT ? (float)(key[r] - kmin) : fval(key[r]) - base;
+          s1 += y;
+          s2 += y * y;
+        }
       }
+      s1 = __uint_as_float(readlane(__float_as_uint(wave_scan(s1)), 63));
+      s2 = __uint_as_float(readlane(__float_as_uint(wave_scan(s2)), 63));
+      const float inv = __builtin_amdgcn_rcpf((float)P0);
+      const float mu_y = s1 * inv;
+      const float var = s2 * inv - mu_y * mu_y;
+      wp.mean = uniform(base + mu_y);
+      wp.sd = uniform(var > 0.f ? __builtin_sqrtf(var) : 0.f);
     }
-    s1 = __uint_as_float(readlane(__float_as_uint(wave_scan(s1)), 63));
-    s2 = __uint_as_float(readlane(__float_as_uint(wave_scan(s2)), 63));
-    const float inv = __builtin_amdgcn_rcpf((float)P0);
-    mu_y = s1 * inv;
-    const float var = s2 * inv - mu_y * mu_y;
-    sd = var > 0.f ? __builtin_sqrtf(var) : 0.f;
+    sd = wp.sd;
     const float h = 2.5f * sd * __builtin_amdgcn_rsqf((float)P0);
-    pm.on = sd > 0.f;
+    pm.on = __builtin_amdgcn_readfirstlane(sd > 0.f ? 1 : 0) != 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const float v = mu_y + (float)(j - 1) * h;
-      if constexpr (INT) {
-        const float u = (float)kmin + v;
-        pm.t[j] = (uint32_t)fminf(fmaxf(u, 0.f), 4294967040.f);
-      } else {
-        pm.t[j] = fkey(base + v);
-      }
+      const float u = wp.mean + (float)(j - 1) * h;
+      if constexpr (INT) pm.t[j] = uniform_u32((uint32_t)fminf(fmaxf(u, 0.f), 4294967040.f));
+      else pm.t[j] = uniform_u32(fkey(u));
     }
   }
 
@@ -735,7 +793,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   // MAD: the same selection on |x - median| (doubled for integers)
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const bool real = r * kWave + lane < P0;
+    const bool real = r < kFullRegs<E> || r * kWave + lane < P0;
     if constexpr (INT) {  // 2*x and med2 are below 2^32 (sums below 2^31)
       const uint32_t tx = 2u * key[r], m2 = (uint32_t)med2;
       key[r] = real ? (tx >= m2 ? tx - m2 : m2 - tx) : kPadKey;
@@ -748,12 +806,12 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     // the MAD of normal noise is 0.6745 sd (doubled for integers)
     const float m = (INT ? 2.f : 1.f) * 0.6745f * sd;
     const float e = 2.4f * __builtin_amdgcn_rsqf((float)P0);
-    pd.on = sd > 0.f;
+    pd.on = __builtin_amdgcn_readfirstlane(sd > 0.f ? 1 : 0) != 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const float v = m * (1.f + (float)(j - 1) * e);
-      if constexpr (INT) pd.t[j] = (uint32_t)fminf(fmaxf(v, 0.f), 4294967040.f);
-      else pd.t[j] = fkey(fmaxf(v, 0.f));
+      if constexpr (INT) pd.t[j] = uniform_u32((uint32_t)fminf(fmaxf(v, 0.f), 4294967040.f));
+      else pd.t[j] = uniform_u32(fkey(fmaxf(v, 0.f)));
     }
   }
   uint32_t d1, d2;
@@ -768,6 +826,9 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     mad = (float)(0.5 * ((double)fval(d1) + (double)fval(d2)));
     mad_zero = mad == 0.f;
   }
+  // the spread of normal noise with this MAD, for the next profile's pivots
+  if constexpr (INT) wp.sd = uniform((float)(0.25 * kMadK) * (float)mad4);
+  else wp.sd = uniform((float)kMadK * mad);
   if (mad_zero) {
     if (lane == 0) {
       *snr_out = 0.f;
@@ -792,7 +853,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     const T* rw = row + w + lane;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      if (r < nfull) {  // wave-uniform branch
+      if (r < kFullRegs<E> || r < nfull) {  // wave-uniform branch
         const A b = (A)rw[r * kWave] - cex[r];
         if constexpr (INT) mx = umax(mx, b);
         else mx = fmaxf(mx, b);
@@ -810,6 +871,13 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   };
   uint32_t pk_l = 0;
   int i = 0;
+  for (; i + 8 <= nw; i += 8) {  // eight widths reduced together
+    uint32_t m8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m8[k] = as_key(lane_max(wt.width(i + k)));
+    const uint32_t p8 = wave_umax8(m8);
+    pk_l = (uint32_t)(lane - i) < 8u ? p8 : pk_l;
+  }
   for (; i + 2 <= nw; i += 2) {
     const A m0 = lane_max(wt.width(i)), m1 = lane_max(wt.width(i + 1));
     const uint32_t p0 = wave_umax(as_key(m0)), p1 = wave_umax(as_key(m1));
@@ -846,13 +914,14 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 // P0 <= 64*EMAX are scored (the launcher picks EMAX from the largest P0).
 template <bool INT, int EMAX, int ALG>
 __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
-                               const WidthLanes& wt, int nw, SelectKnobs kn, float* snr_out, int32_t* width_out) {
+                               const WidthLanes& wt, int nw, SelectKnobs kn, WavePrior& wp, float* snr_out,
+                               int32_t* width_out) {
 #define FFA_SCORE(EE)                                                                              \
   do {                                                                                             \
     if constexpr (ALG == 2)                                                                        \
       score_alg2<EE, INT>(row, P0, wmax, wt, nw, snr_out, width_out);                              \
     else                                                                                           \
-      score_profile<EE, INT>(row, scratch, P0, wmax, wt, nw, kn, snr_out, width_out);             \
+      score_profile<EE, INT>(row, scratch, P0, wmax, wt, nw, kn, wp, snr_out, width_out);         \
   } while (0)
   if (P0 <= 64) FFA_SCORE(1);
   else if (P0 <= 128) FFA_SCORE(2);
@@ -1020,10 +1089,11 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
     wt.isq = lane < ph.nw ? isw[lane] : 1.0;
     const int wmax = (int)wave_umax((uint32_t)wt.w);
     const int64_t trial0 = ph.first_trial + ((int64_t)q << d);
+    WavePrior wp{0.f, 0.f};
     for (int tt = wave; tt < R; tt += nwaves) {
       T* row = lds + (size_t)bitrev(tt, d) * S;
       const int64_t trial = trial0 + tt;
-      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, wt, ph.nw, kn, a.snr + trial, a.width + trial);
+      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, wt, ph.nw, kn, wp, a.snr + trial, a.width + trial);
     }
   }
 }
