@@ -173,6 +173,28 @@ struct WidthLanes {
   }
 };
 
+// Sums of two values per lane over the wave at once (fixed trees, so the
+// results are deterministic): after the first exchange even lanes carry a
+// and odd lanes b, and the remaining steps keep that parity.
+__device__ __forceinline__ void wave_sum2(double a, double b, double& sa, double& sb) {
+  auto bits = [](double x) { return (uint64_t)__double_as_longlong(x); };
+  auto dbl = [](uint64_t u) { return __longlong_as_double((long long)u); };
+  const int lane = lane_id();
+  const bool odd = lane & 1;
+  double v = (odd ? b : a) + dbl(dpp64<kDppXor1>(bits(odd ? a : b)));
+  v += dbl(dpp64<kDppXor2>(bits(v)));  // the quad
+  v += dbl(dpp64<kDppRor4>(bits(v)));  // two quads
+  v += dbl(dpp64<kDppRor8>(bits(v)));  // the row
+  auto perm = [&](int src, double x) {
+    const uint64_t u = bits(x);
+    return dbl(((uint64_t)bpermute(src, (uint32_t)(u >> 32)) << 32) | bpermute(src, (uint32_t)u));
+  };
+  v += perm(lane ^ 16, v);
+  v += perm(lane ^ 32, v);
+  sa = dbl(readlane64(bits(v), 0));
+  sb = dbl(readlane64(bits(v), 1));
+}
+
 // Sum of one value per lane over the wave (a fixed reduction tree, so the
 // result is deterministic); wave-uniform.
 __device__ __forceinline__ int64_t wave_sum(int64_t v) {
@@ -673,17 +695,17 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
     {
       // for integer profiles every box and d are integers below 2^32, and
       // their sums below 2^53, so s1 is exact in double
+      // a box inside the window is replaced by c itself, so it adds an
+      // exact 0 to both sums
       const double cd = as_double(cbox);
       double t1 = 0.0;
       visit([&](int e, A b) {
-        const double dv = as_double(b) - cd;
-        const bool k = kept(e);
-        t1 += k ? dv : 0.0;
-        s2 += k ? dv * dv : 0.0;
+        const double dv = as_double(kept(e) ? b : cbox) - cd;
+        t1 += dv;
+        s2 = fma(dv, dv, s2);
       });
-      s1 = wave_sum(t1);
+      wave_sum2(t1, s2, s1, s2);
     }
-    s2 = wave_sum(s2);
     const double mrel = s1 / (double)cnt;  // kept mean - c
     const double var = (s2 - s1 * mrel) / (double)cnt;
     const double sd = var > 0.0 ? sqrt(var) : 0.0;
