@@ -25,8 +25,6 @@ TileArgs base_args(ffa_plan p, const DeviceTables* dt) {
   a.sqrtw = dt->sqrtw;
   a.oct_base = 0;
   a.ring_off = p->ring_off;
-  a.slot_elems = p->slot_elems;
-  a.n_slots = p->n_slots;
   a.alg = p->desc.snr == FFA_SNR_ALG2_OFFPULSE ? 2 : 1;
   a.select_iters = p->select_iters;
   a.select_cand = p->select_cand;

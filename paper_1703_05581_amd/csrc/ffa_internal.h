@@ -54,7 +54,7 @@ struct Phase {
   int32_t isqrt_ofs;    // the step's 1/sqrt(width) values in the sqrt table
   int32_t launch;       // index of the launch that runs the phase
   int32_t u16;          // 1: the tile keeps its rows as 16-bit sums in LDS
-  int32_t pad_[1];
+  int32_t ring64;       // multi-pass step: its intermediates start at ring_off + 64*ring64
 };
 static_assert(sizeof(Phase) == 96, "phase layout");
 
@@ -71,9 +71,7 @@ struct TileArgs {
   int64_t tile0;
   int64_t oct_base;           // element offset of the series region in the workspace
   int64_t ring_off;           // element offset of the intermediate ring
-  int64_t slot_elems;         // elements per ring slot (two buffers of M*P0)
   int64_t trial_base;         // fold: trial index of output row 0
-  int32_t n_slots;
   int32_t mode;
   int32_t alg;                // profile score: 1 = Algorithm 1, 2 = Algorithm 2
   int32_t select_iters;
@@ -92,6 +90,7 @@ struct Step {
   int32_t fold_phase0;        // its phases in pass order, in Plan::fold_phases
   int64_t lds_budget = 0;     // LDS bytes a tile may use
   int32_t u16_first = 0;      // the first of two passes keeps 16-bit sums
+  int64_t ring_pos = 0;       // multi-pass: element offset of its intermediates in the ring
 };
 
 // One launch of a search: a window of the queue whose tiles depend only on
@@ -128,7 +127,7 @@ struct ffa_plan_s {
   ffa_plan_desc desc;
   std::vector<int32_t> user_widths;
   std::vector<ffa::Step> steps;
-  std::vector<ffa::Phase> phases;       // queue order: pass p of step s at key s + p*lookahead
+  std::vector<ffa::Phase> phases;       // queue order: pass p of step group g in window g + p
   std::vector<ffa::Phase> fold_phases;  // per step, its passes in order
   std::vector<int32_t> tile_phase;      // queue tile -> index in phases
   std::vector<ffa::Launch> launches;     // launches of a search, in order
@@ -137,9 +136,8 @@ struct ffa_plan_s {
   int64_t n_trials = 0;
   int64_t n_tiles = 0;
   int32_t max_passes = 1;
-  int32_t lookahead = 1;                // keys per window
-  int32_t n_slots = 1;                  // intermediate ring slots
-  int64_t slot_elems = 0;               // intermediate elements per slot
+  int32_t lookahead = 1;                // steps in the largest window group
+  int64_t ring_elems = 0;               // elements of the intermediate ring
   int32_t lds_bytes = 0;                // largest tile LDS footprint
   int32_t max_P0 = 0;
   int32_t n_octaves = 0;                // octaves 0..n_octaves-1 are built

@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
   const int32_t k = (int32_t)(t - ph.tile0);
   const int32_t q = k / ph.ng;
   const int32_t h = k - q * ph.ng;
-  const int64_t buf0 = a.ring_off + (int64_t)(ph.step % a.n_slots) * a.slot_elems;
+  const int64_t buf0 = a.ring_off + (int64_t)ph.ring64 * 64;
   const int64_t buf1 = buf0 + (int64_t)ph.M * ph.P0;
 
   // geometry of this tile

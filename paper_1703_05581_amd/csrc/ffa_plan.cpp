@@ -141,8 +141,78 @@ int64_t env_int(const char* name, int64_t def, int64_t lo, int64_t hi) {
   return def;
 }
 
+// Ring space a multi-pass step's intermediates take: one M*P0 buffer, two
+// when a middle pass reads one and writes the other; 64-element aligned.
+int64_t ring_region(const Step& s) {
+  return s.n_passes > 1 ? round_up((int64_t)(s.n_passes > 2 ? 2 : 1) * s.M * s.P0, 64) : 0;
+}
+
+// The ring as an arena.  Steps are cut into groups of consecutive steps;
+// pass p of a step in group g runs in window g + p, so a group's
+// intermediates are live in windows g .. g + max_passes - 1.  The groups'
+// multi-pass steps are placed one after another, groups in order, wrapping
+// to the start when a group would run past the end.  At most max_passes
+// consecutive groups are live at once, so a ring of the largest such sum
+// plus the largest group is enough: the live span then wraps at most once,
+// and the space a wrap skips is less than the group that wraps.
+int64_t ring_need(const std::vector<Step>& steps, const std::vector<int32_t>& grp, int32_t max_passes) {
+  std::vector<int64_t> g(steps.empty() ? 0 : (size_t)grp.back() + 1, 0);
+  for (size_t i = 0; i < steps.size(); ++i) g[(size_t)grp[i]] += ring_region(steps[i]);
+  int64_t best = 0, gmax = 0, run = 0;
+  for (size_t i = 0; i < g.size(); ++i) {
+    run += g[i];
+    if (i >= (size_t)max_passes) run -= g[i - (size_t)max_passes];
+    best = std::max(best, run);
+    gmax = std::max(gmax, g[i]);
+  }
+  return best + gmax;
+}
+
+int64_t place_ring(std::vector<Step>& steps, const std::vector<int32_t>& grp, int32_t max_passes) {
+  const int64_t cap = ring_need(steps, grp, max_passes);
+  int64_t head = 0;
+  for (size_t i0 = 0; i0 < steps.size();) {
+    size_t i1 = i0;
+    int64_t size = 0;
+    while (i1 < steps.size() && grp[i1] == grp[i0]) size += ring_region(steps[i1++]);
+    if (head + size > cap) head = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      steps[i].ring_pos = head;
+      head += ring_region(steps[i]);
+    }
+    i0 = i1;
+  }
+  return cap;
+}
+
+// Groups of consecutive steps: each closes once it holds about `target`
+// tiles (all passes), or once its ring share would pass
+// budget / (max_passes + 1), which keeps ring_need within the budget unless
+// a single step alone is larger.  `fixed` > 0 instead takes that many steps
+// per group.
+std::vector<int32_t> group_steps(const std::vector<Step>& steps, int64_t target, int64_t budget_elems,
+                                 int32_t max_passes, int64_t fixed) {
+  std::vector<int32_t> grp(steps.size(), 0);
+  const int64_t share = max_passes > 1 ? budget_elems / (max_passes + 1) : INT64_MAX;
+  int32_t g = 0;
+  int64_t tiles = 0, ring = 0, n = 0;
+  for (size_t i = 0; i < steps.size(); ++i) {
+    const int64_t t = steps[i].total_tiles, r = ring_region(steps[i]);
+    const bool full = fixed > 0 ? n >= fixed : (tiles + t > target || ring + r > share);
+    if (n > 0 && full) {
+      ++g;
+      tiles = ring = n = 0;
+    }
+    grp[i] = g;
+    tiles += t;
+    ring += r;
+    ++n;
+  }
+  return grp;
+}
+
 // Every tile a phase can produce must read and write inside its buffers (the
-// octave series, its step's two intermediate buffers in a ring slot, its own
+// octave series, its step's two intermediate buffers in the ring, its own
 // trials, one workgroup's LDS), and every tile it reads must come from an
 // earlier launch.  Checked once per plan, before anything can be launched.
 bool phases_valid(const ffa_plan_s* p) {
@@ -177,7 +247,9 @@ bool phases_valid(const ffa_plan_s* p) {
     const int64_t lds = R * ph.stride * esz_of(ph) + (last ? (int64_t)kScratchBytes : 0);
     if (lds > (int64_t)kLdsBytes || lds > w.lds_bytes || ph.P0 > w.max_P0) return false;
     if (ph.wofs != s.wofs || ph.nw != s.nw || (last && s.nw < 1)) return false;
-    if (s.n_passes > 1 && MP * (s.n_passes > 2 ? 2 : 1) > p->slot_elems) return false;
+    if (s.n_passes > 1 && (s.ring_pos < 0 || s.ring_pos % 64 || (int64_t)ph.ring64 * 64 != s.ring_pos ||
+                           s.ring_pos + ring_region(s) > p->ring_elems || ring_region(s) < MP * (s.n_passes > 2 ? 2 : 1)))
+      return false;
     const int64_t Gin = (int64_t)s.M >> D;
     for (int64_t k = 0; k < ph.ntiles; ++k) {
       if (p->tile_phase[(size_t)(ph.tile0 + k)] != (int32_t)i) return false;
@@ -209,15 +281,23 @@ bool phases_valid(const ffa_plan_s* p) {
     if (last) last_win[(size_t)ph.step] = ph.launch;
   }
   if (expect != p->n_tiles || (int64_t)p->tile_phase.size() != p->n_tiles) return false;
-  // ring: a multi-pass step starts after the previous multi-pass user of its
-  // slot has finished
-  std::vector<int32_t> slot_last(std::max<int32_t>(p->n_slots, 1), -1);
+  // ring: two multi-pass steps whose launches overlap hold disjoint ranges
+  std::vector<size_t> multi;
   for (size_t si = 0; si < ns; ++si) {
     if (first_win[si] < 0 || last_win[si] < 0) return false;
-    if (p->steps[si].n_passes < 2) continue;
-    int32_t& prev = slot_last[si % (size_t)p->n_slots];
-    if (prev >= 0 && last_win[(size_t)prev] >= first_win[si]) return false;
-    prev = (int32_t)si;
+    if (p->steps[si].n_passes > 1) multi.push_back(si);
+  }
+  std::stable_sort(multi.begin(), multi.end(), [&](size_t a, size_t b) { return first_win[a] < first_win[b]; });
+  std::vector<size_t> live;
+  for (size_t si : multi) {
+    const Step& s = p->steps[si];
+    live.erase(std::remove_if(live.begin(), live.end(), [&](size_t o) { return last_win[o] < first_win[si]; }),
+               live.end());
+    for (size_t o : live) {
+      const Step& t = p->steps[o];
+      if (s.ring_pos < t.ring_pos + ring_region(t) && t.ring_pos < s.ring_pos + ring_region(s)) return false;
+    }
+    live.push_back(si);
   }
   return true;
 }
@@ -454,7 +534,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
 
   // --- phases: one per (step, pass), tiles Q * ng
   struct Key {
-    int64_t key;
+    int64_t key;  // window
     int32_t pass, step, cls;
   };
   std::vector<Key> order;
@@ -505,33 +585,30 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     p->max_passes = std::max(p->max_passes, s.n_passes);
     p->lds_bytes = std::max(p->lds_bytes, s.lds_bytes);
     p->max_P0 = std::max(p->max_P0, s.P0);
-    if (s.n_passes > 1) p->slot_elems = std::max<int64_t>(p->slot_elems, (int64_t)(s.n_passes > 2 ? 2 : 1) * s.M * s.P0);
   }
   p->n_tiles = tiles_total;
   if (tiles_total >= (int64_t(1) << 31)) {
     delete p;
     return fail(FFA_ERR_UNSUPPORTED, "too many tiles in one search");
   }
-  // Queue order: pass p of step s at key s + p*lookahead; a window is
-  // `lookahead` consecutive keys (about FFA_WINDOW_TILES tiles) and runs as
-  // one launch per occupancy class.  The previous pass of a step is then
-  // always in an earlier window.  Ring slot s mod n_slots holds step s's
-  // intermediates from its first pass (window s / lookahead) to its last (at
-  // most max_passes - 1 windows later), so n_slots = max_passes * lookahead
-  // keeps two steps of one slot from overlapping.
-  const double avg = (double)tiles_total / (double)p->steps.size();
-  const int64_t target = env_int("FFA_WINDOW_TILES", 16384, 1, 1 << 24);
-  int64_t la = std::max<int64_t>(1, (int64_t)std::ceil((double)target / avg));
-  if (p->max_passes > 1) {
-    // keep the ring within kRingBudget bytes
-    const int64_t slot_bytes = round_up(p->slot_elems, 64) * 4;
-    const int64_t budget = env_int("FFA_RING_MB", kRingBudget >> 20, 1, int64_t(1) << 20) << 20;
-    la = std::min<int64_t>(la, std::max<int64_t>(1, budget / (slot_bytes * p->max_passes)));
+  // Queue order: windows of consecutive step groups (about FFA_WINDOW_TILES
+  // tiles each, within the ring budget FFA_RING_MB), pass p of group g in
+  // window g + p, each window one launch per occupancy class.  The previous
+  // pass of a step is then always in an earlier window.
+  const int64_t target = env_int("FFA_WINDOW_TILES", 32768, 1, 1 << 24);
+  const int64_t budget = env_int("FFA_RING_MB", kRingBudget >> 20, 1, int64_t(1) << 20) << 20;
+  const int64_t fixed = env_int("FFA_LOOKAHEAD", 0, 0, 4096);
+  const std::vector<int32_t> grp = group_steps(p->steps, target, budget / 4, p->max_passes, fixed);
+  p->ring_elems = place_ring(p->steps, grp, p->max_passes);
+  {
+    int32_t most = 0;
+    for (size_t i0 = 0, i1 = 0; i0 < grp.size(); i0 = i1) {
+      while (i1 < grp.size() && grp[i1] == grp[i0]) ++i1;
+      most = std::max<int32_t>(most, (int32_t)(i1 - i0));
+    }
+    p->lookahead = most;  // steps in the largest group
   }
-  la = std::min<int64_t>(la, 4096);
-  la = env_int("FFA_LOOKAHEAD", la, 1, 4096);
-  p->lookahead = (int32_t)la;
-  p->n_slots = p->max_passes > 1 ? p->max_passes * p->lookahead : 1;
+  for (Phase& ph : nat) ph.ring64 = (int32_t)(p->steps[(size_t)ph.step].ring_pos / 64);
   // occupancy class: workgroups per CU that the phase's LDS footprint allows
   const bool split = env_int("FFA_SPLIT_OCCUPANCY", 1, 0, 1) != 0;
   auto occ_class = [&](const Phase& ph) {
@@ -540,22 +617,20 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
     return (int32_t)std::min<int64_t>(4, (int64_t)kLdsBytes / std::max<int64_t>(lds, 1));
   };
   for (size_t i = 0; i < nat.size(); ++i)
-    order.push_back({(int64_t)nat[i].step + (int64_t)nat[i].pass * p->lookahead, nat[i].pass,
-                     nat[i].step, occ_class(nat[i])});
-  const int64_t LA = p->lookahead;
-  std::stable_sort(order.begin(), order.end(), [LA](const Key& a, const Key& b) {
-    if (a.key / LA != b.key / LA) return a.key / LA < b.key / LA;
+    order.push_back({(int64_t)grp[(size_t)nat[i].step] + nat[i].pass, nat[i].pass, nat[i].step, occ_class(nat[i])});
+  std::stable_sort(order.begin(), order.end(), [](const Key& a, const Key& b) {
+    if (a.key != b.key) return a.key < b.key;  // window
     if (a.cls != b.cls) return a.cls < b.cls;
-    return a.key != b.key ? a.key < b.key : a.pass < b.pass;
+    return a.step != b.step ? a.step < b.step : a.pass < b.pass;
   });
   int64_t t0 = 0, cur_win = -1;
   int32_t cur_cls = -1;
   p->tile_phase.reserve((size_t)tiles_total);
   for (const Key& k : order) {
     Phase ph = nat[p->steps[k.step].fold_phase0 + k.pass];
-    if (k.key / LA != cur_win || k.cls != cur_cls) {
+    if (k.key != cur_win || k.cls != cur_cls) {
       p->launches.push_back(Launch{t0, 0, 0, 0});
-      cur_win = k.key / LA;
+      cur_win = k.key;
       cur_cls = k.cls;
     }
     Launch& ln = p->launches.back();
@@ -582,13 +657,12 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   }
   // workspace: series region, then the ring (which ffa_sift reuses as scratch)
   p->ring_off = round_up(p->series_elems, 64);
-  p->slot_elems = round_up(p->slot_elems, 64);
   {
     const int64_t nb = (p->n_trials + kSiftBlock - 1) / kSiftBlock;
     p->sift_elems = round_up(2 * p->n_trials, 64) + 2 * round_up(nb + 1, 64) + 64 + 8 * (int64_t)kSiftMaxPeaks;
   }
   p->ws_bytes = (size_t)round_up(
-      std::max<int64_t>(p->ring_off + (int64_t)p->n_slots * p->slot_elems, p->ring_off + p->sift_elems) * 4,
+      std::max<int64_t>(p->ring_off + p->ring_elems, p->ring_off + p->sift_elems) * 4,
       (int64_t)kWsAlign);
   // test knobs: force the selection's fallback paths
   if (const char* e = std::getenv("FFA_SELECT_ITERS")) p->select_iters = std::max(0, std::atoi(e));
@@ -677,8 +751,8 @@ extern "C" int64_t ffa_debug_layout(ffa_plan p, int64_t* out, int64_t cap) {
   const int64_t need = 8 + 4 * nw;
   if (!out || cap < need) return need;
   out[0] = p->ring_off;
-  out[1] = p->slot_elems;
-  out[2] = p->n_slots;
+  out[1] = p->ring_elems;
+  out[2] = 0;
   out[3] = p->n_tiles;
   out[4] = p->lds_bytes;
   out[5] = p->max_P0;

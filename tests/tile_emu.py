@@ -13,7 +13,7 @@ PHASE_DT = np.dtype([
     ("ntiles", "<i4"), ("ng", "<i4"), ("step", "<i4"), ("pass_", "<i4"), ("last", "<i4"),
     ("P0", "<i4"), ("M", "<i4"), ("depth", "<i4"), ("D", "<i4"), ("vin", "<i4"),
     ("stride", "<i4"), ("halo", "<i4"), ("wofs", "<i4"), ("nw", "<i4"), ("isqrt_ofs", "<i4"),
-    ("launch", "<i4"), ("u16", "<i4"), ("pad1", "<i4")])
+    ("launch", "<i4"), ("u16", "<i4"), ("ring64", "<i4")])
 assert PHASE_DT.itemsize == 96
 SCRATCH = 16 * 64 * 4
 LDS_MAX = 160 * 1024
@@ -39,7 +39,7 @@ def layout(plan):
     lib.ffa_debug_layout(plan.handle, out, need)
     v = list(out)
     wins = np.array(v[8:], dtype=np.int64).reshape(-1, 4)
-    return dict(ring_off=v[0], slot_elems=v[1], n_slots=v[2], n_tiles=v[3], lds_bytes=v[4],
+    return dict(ring_off=v[0], ring_elems=v[1], n_tiles=v[3], lds_bytes=v[4],
                 max_P0=v[5], ws_bytes=v[6], lookahead=v[7], launches=wins)
 
 
@@ -61,14 +61,20 @@ def check(plan):
     octs = octaves(plan)
     ws_elems = L["ws_bytes"] // 4
     assert L["ring_off"] >= octs[-1][0] + octs[-1][1]
-    assert L["ring_off"] + L["n_slots"] * L["slot_elems"] <= ws_elems
+    assert L["ring_off"] + L["ring_elems"] <= ws_elems
     wins = L["launches"]
     assert wins[0, 0] == 0 and int(wins[:, 1].sum()) == L["n_tiles"]
     assert all(wins[i, 0] + wins[i, 1] == wins[i + 1, 0] for i in range(len(wins) - 1))
     done = {}        # (step, pass) -> launch that ran it
-    owner = {}       # ring slot -> step whose intermediates it holds
+    npass = {}       # step -> passes
+    for x in ph:
+        npass[int(x["step"])] = max(npass.get(int(x["step"]), 0), int(x["pass_"]) + 1)
+    live = {}        # step -> (start, end) of the ring range its intermediates hold
+    ended = {}       # step -> launch of its last pass
     for x in ph:
         w = int(x["launch"])
+        for t in [t for t in live if ended.get(t, w) < w]:
+            del live[t]  # read for the last time in an earlier launch
         w0, wn, wlds, wp0 = (int(v) for v in wins[w])
         assert w0 <= x["tile0"] and x["tile0"] + x["ntiles"] <= w0 + wn, "phase outside its launch"
         s, p, P0, M = int(x["step"]), int(x["pass_"]), int(x["P0"]), int(x["M"])
@@ -81,18 +87,20 @@ def check(plan):
             assert 255 * 2 ** (octave + d) < 65536, (s, octave, d)
         lds = R * int(x["stride"]) * esz + (SCRATCH if x["last"] else 0)
         assert lds <= wlds <= LDS_MAX and P0 <= wp0
-        slot = s % L["n_slots"]
-        slot0 = L["ring_off"] + slot * L["slot_elems"]
         MP = M * P0
+        region = MP * (2 if npass[s] > 2 else 1)
+        slot0 = L["ring_off"] + 64 * int(x["ring64"])
+        slot_end = slot0 + region
+        if npass[s] > 1:
+            assert L["ring_off"] <= slot0 and slot_end <= L["ring_off"] + L["ring_elems"], ("ring range", s)
         if p == 0 and not x["last"]:
-            prev = owner.get(slot)
-            if prev is not None and prev != s:
-                last_prev = max(v for (st, _), v in done.items() if st == prev)
-                assert last_prev < w, ("slot reused while in use", s, prev)
-            owner[slot] = s
+            # no step whose intermediates are still to be read holds any of this range
+            for t, (a, b) in live.items():
+                assert b <= slot0 or slot_end <= a, ("ring range in use", s, t)
+            live[s] = (slot0, slot_end)
         if p > 0:
             assert done.get((s, p - 1), w) < w, ("previous pass not in an earlier launch", s, p)
-            assert owner.get(slot) == s, ("slot taken by another step", s)
+            assert live.get(s) == (slot0, slot_end), ("ring range moved or taken", s)
         Gin = M >> int(x["D"])
         for k in range(int(x["ntiles"])):
             q, h = divmod(k, int(x["ng"]))
@@ -105,13 +113,15 @@ def check(plan):
                 assert 0 <= rel and rel + valid * P0 <= n, ("pass-0 read", s, k)
             else:
                 src = slot0 + (MP if (p - 1) & 1 else 0) + rel
-                assert slot0 <= src and src + valid * P0 <= slot0 + L["slot_elems"], ("read", s, k)
+                assert slot0 <= src and src + valid * P0 <= slot_end, ("read", s, k)
             if not x["last"]:
                 Gout = Gin >> d
                 dst = slot0 + (MP if p & 1 else 0) + ((q << d) * Gout + h) * P0
-                assert slot0 <= dst and dst + (R - 1) * Gout * P0 + P0 <= slot0 + L["slot_elems"], ("write", s, k)
+                assert slot0 <= dst and dst + (R - 1) * Gout * P0 + P0 <= slot_end, ("write", s, k)
             else:
                 t0 = int(x["first_trial"]) + (q << d)
                 assert 0 <= t0 and t0 + R <= plan.n_trials, ("trial", s, k)
         done[(s, p)] = w
+        if x["last"]:
+            ended[s] = w
     return L
