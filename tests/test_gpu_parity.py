@@ -228,20 +228,24 @@ def test_selection_paths(torch_cuda, ffa, oracle_mod, knob, dtype, monkeypatch):
 
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype, monkeypatch):
-    """The periodogram does not depend on how the queue is cut into launches:
-    one key per launch, three, and the default agree bit for bit."""
+    """The periodogram does not depend on how the queue is cut into launches
+    or where the ring places each step: one step per window group, three, a
+    4 MB ring with small groups (the arena wraps many times) and the default
+    agree bit for bit."""
     from paper_1703_05581_amd import synth
 
     N = 300000
     x = torch_cuda.from_numpy(synth.random_series(77, N, dtype)).cuda()
     outs = []
-    for la in ("1", "3", None):
-        if la is None:
-            monkeypatch.delenv("FFA_LOOKAHEAD", raising=False)
-        else:
-            monkeypatch.setenv("FFA_LOOKAHEAD", la)
+    keys = ("FFA_LOOKAHEAD", "FFA_RING_MB", "FFA_WINDOW_TILES")
+    for env in ({"FFA_LOOKAHEAD": "1"}, {"FFA_LOOKAHEAD": "3"}, {"FFA_RING_MB": "4", "FFA_WINDOW_TILES": "500"}, {}):
+        for k in keys:
+            if k in env:
+                monkeypatch.setenv(k, env[k])
+            else:
+                monkeypatch.delenv(k, raising=False)
         plan = ffa.Plan(N, 1e-3, 0.2, 2.0, 100, W10, dtype)
-        print("lookahead", la, flush=True)
+        print("queue", env, flush=True)
         outs.append([t.clone() for t in plan.search(x)])
         torch_cuda.cuda.synchronize()
     for o in outs[1:]:

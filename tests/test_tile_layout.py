@@ -45,3 +45,21 @@ def test_lds_budgets(monkeypatch, lds_kb):
         p = ffa.Plan(*args)
         L = check(p)
         assert L["lds_bytes"] <= lds_kb * 1024
+
+
+@pytest.mark.parametrize("ring_mb,tiles", [(1, 64), (4, 500), (16, 3000), (64, 100000)])
+def test_ring_arena_budgets(monkeypatch, ring_mb, tiles):
+    """Small ring budgets and window targets cut the steps into many small
+    groups whose ranges wrap around the arena again and again; no two steps
+    whose launches overlap may share ring space, and the ring stays within
+    the budget unless one step alone needs more."""
+    monkeypatch.setenv("FFA_RING_MB", str(ring_mb))
+    monkeypatch.setenv("FFA_WINDOW_TILES", str(tiles))
+    for args in [(600000, 1e-3, 1.990, 2.010, 1000, [1, 2, 4, 8], "f32"),
+                 (300000, 1e-3, 0.2, 2.0, 100, None, "u8"),
+                 (400000, 1e-3, 0.05, 3.0, 64, None, "f32")]:
+        p = ffa.Plan(*args)
+        L = check(p)
+        largest = max((p.step(s).M * p.step(s).P0 * (2 if len(p.passes(s)) > 2 else 1)
+                       for s in range(p.n_steps) if len(p.passes(s)) > 1), default=0)
+        assert L["ring_elems"] * 4 <= max(ring_mb << 20, 3 * 4 * (largest + 64) * 2), (args, L["ring_elems"])
