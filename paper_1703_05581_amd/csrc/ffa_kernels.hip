@@ -1174,13 +1174,17 @@ __global__ void prep_f32_kernel(const float* __restrict__ in, int64_t n,
 // Running-median dereddening (paper Sec. 2.3.1): the median of the window at
 // every knot t_c = c*stride, then the linearly interpolated baseline is
 // subtracted.  One workgroup per knot finds the median by radix selection on
-// order-preserving keys: four passes of 8-bit digits, each counting the keys
-// that share the digits found so far into an LDS histogram.  The medians are
-// kept in double and the baseline is subtracted in double, so the series
-// (exact int32 sums for uint8 input, float otherwise) is rounded once, to the
-// float32 output written over it.
+// order-preserving keys (staged in LDS when the window fits): one pass per
+// 8-bit digit counts the keys that share the digits found so far into an
+// LDS histogram, and a block-wide scan of the 256 bins finds the digit that
+// holds the target rank.  For an even count the upper middle value is the
+// lower one again if it repeats, else the smallest key above it.  The
+// medians are kept in double and the baseline is subtracted in double, so
+// the series (exact int32 sums for uint8 input, float otherwise) is rounded
+// once, to the float32 output written over it.
 
-constexpr int kKnotThreads = 256;
+constexpr int kKnotThreads = 256;   // one thread per histogram bin
+constexpr int kKnotStage = 4096;    // window keys staged in LDS
 
 __device__ __forceinline__ uint32_t series_key(int32_t v) { return (uint32_t)v; }  // sums are >= 0
 __device__ __forceinline__ uint32_t series_key(float v) { return fkey(v); }
@@ -1196,59 +1200,87 @@ __device__ __forceinline__ double key_value(uint64_t k, double) {
 
 // k-th smallest (0-based) key of x[lo..hi) (all threads return it).
 template <typename T>
-__device__ auto knot_select(const T* __restrict__ x, int64_t lo, int64_t hi, int64_t k, uint32_t* hist,
-                            uint32_t* s_digit, int64_t* s_below) {
-  using K = decltype(series_key(T()));
-  constexpr int kBits = 8 * (int)sizeof(K);
-  K prefix = 0;
-  for (int shift = kBits - 8; shift >= 0; shift -= 8) {
-    for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0u;
-    __syncthreads();
-    const K hmask = shift == kBits - 8 ? (K)0 : (K)(~(K)0 << (shift + 8));
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      const K key = series_key(x[i]);
-      if ((key & hmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 0xffu], 1u);
-    }
-    __syncthreads();
-    // the digit whose bin holds rank k (a short serial scan by one thread)
-    if (threadIdx.x == 0) {
-      int64_t below = 0;
-      uint32_t dg = 255u;
-      for (uint32_t b = 0; b < 256u; ++b) {
-        if (k < below + (int64_t)hist[b]) {
-          dg = b;
-          break;
-        }
-        below += hist[b];
-      }
-      *s_digit = dg;
-      *s_below = below;
-    }
-    __syncthreads();
-    prefix |= (K)*s_digit << shift;
-    k -= *s_below;
-    __syncthreads();
-  }
-  return prefix;
-}
-
-template <typename T>
 __global__ __launch_bounds__(kKnotThreads) void knot_median_kernel(const T* __restrict__ x, int64_t n,
                                                                    int32_t window, int32_t stride,
                                                                    double* __restrict__ med) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t s_digit;
+  using K = decltype(series_key(T()));
+  constexpr int kBits = 8 * (int)sizeof(K);
+  __shared__ K skeys[kKnotStage];
+  __shared__ uint32_t hist[kKnotThreads];
+  __shared__ uint32_t wsum[kKnotThreads / kWave];
+  __shared__ uint32_t s_digit, s_eq;
   __shared__ int64_t s_below;
+  __shared__ K s_min;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
   const int64_t c = blockIdx.x;
   const int64_t t = c * stride;
   int64_t lo = t - window / 2, hi = lo + window;
   lo = lo < 0 ? 0 : lo;
   hi = hi > n ? n : hi;
   const int64_t cnt = hi - lo;
-  const double v1 = key_value(knot_select(x, lo, hi, (cnt - 1) / 2, hist, &s_digit, &s_below), T());
-  double m = v1;
-  if (cnt % 2 == 0) m = 0.5 * (v1 + key_value(knot_select(x, lo, hi, cnt / 2, hist, &s_digit, &s_below), T()));
-  if (threadIdx.x == 0) med[c] = m;
+  if (cnt <= 0) {  // not reached for knots inside the series
+    if (tid == 0) med[c] = 0.0;
+    return;
+  }
+  const bool staged = cnt <= kKnotStage;
+  if (staged)
+    for (int64_t i = tid; i < cnt; i += kKnotThreads) skeys[i] = series_key(x[lo + i]);
+  auto key_at = [&](int64_t i) -> K { return staged ? skeys[i] : series_key(x[lo + i]); };
+  // rank (cnt - 1) / 2, one 8-bit digit per pass, most significant first
+  int64_t k = (cnt - 1) / 2;
+  K prefix = 0;
+  uint32_t eq = 0;  // keys equal to the result, after the last pass
+  for (int shift = kBits - 8; shift >= 0; shift -= 8) {
+    hist[tid] = 0u;
+    __syncthreads();
+    const K hmask = shift == kBits - 8 ? (K)0 : (K)(~(K)0 << (shift + 8));
+    for (int64_t i = tid; i < cnt; i += kKnotThreads) {
+      const K key = key_at(i);
+      if ((key & hmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    // thread b owns bin b: keys below the bin = exclusive prefix over bins
+    const uint32_t h = hist[tid];
+    const uint32_t incl = wave_scan(h);
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    const int64_t below = (int64_t)(base + incl - h);
+    if (k >= below && k < below + (int64_t)h) {  // exactly one bin holds rank k
+      s_digit = (uint32_t)tid;
+      s_below = below;
+      s_eq = h;
+    }
+    __syncthreads();
+    prefix |= (K)s_digit << shift;
+    k -= s_below;
+    eq = s_eq;
+    __syncthreads();
+  }
+  double m = key_value(prefix, T());
+  if (cnt % 2 == 0) {
+    K v2 = prefix;
+    if (k + 1 >= (int64_t)eq) {  // rank cnt/2 is the smallest key above
+      if (tid == 0) s_min = ~(K)0;
+      __syncthreads();
+      K mn = ~(K)0;
+      for (int64_t i = tid; i < cnt; i += kKnotThreads) {
+        const K key = key_at(i);
+        if (key > prefix && key < mn) mn = key;
+      }
+      if constexpr (sizeof(K) == 8)
+        atomicMin(reinterpret_cast<unsigned long long*>(&s_min), (unsigned long long)mn);
+      else
+        atomicMin(reinterpret_cast<unsigned int*>(&s_min), (unsigned int)mn);
+      __syncthreads();
+      v2 = s_min;
+    }
+    m = 0.5 * (m + key_value(v2, T()));
+  }
+  if (tid == 0) med[c] = m;
 }
 
 // out[i] = x[i] - baseline(i), in double, rounded once to float32.  `out` may
