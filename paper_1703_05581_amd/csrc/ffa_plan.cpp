@@ -17,7 +17,7 @@ namespace {
 thread_local std::string g_last_error;
 
 // Largest intermediate ring of a plan (bytes); the launches shrink to fit it.
-constexpr int64_t kRingBudget = int64_t(2048) << 20;
+constexpr int64_t kRingBudget = int64_t(4096) << 20;
 
 int32_t next_pow2(int64_t m) {
   int32_t M = 1;
