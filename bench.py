@@ -57,11 +57,12 @@ def parse():
     ap.add_argument("--pmc-summary", metavar="DB", nargs="+")
     ap.add_argument("--searches", type=int, default=0,
                     help="with --pmc-summary: searches the profiled run made")
-    ap.add_argument("--workload", type=int, choices=[2, 3], default=2,
-                    help="search mode: workload 2 (the metric's configuration) or 3 (HTRU-like, dereddened)")
+    ap.add_argument("--workload", type=int, choices=[1, 2, 3], default=2,
+                    help="search and graph modes: workload 2 (the metric's configuration), 3 (HTRU-like, "
+                         "dereddened) or 1 (small, launch-bound)")
     ap.add_argument("--alg", type=int, choices=[1, 2], default=1,
                     help="profile score: 1 = Algorithm 1 (the headline), 2 = Algorithm 2")
-    ap.add_argument("--mode", choices=["search", "batch", "served", "null"], default="search",
+    ap.add_argument("--mode", choices=["search", "batch", "served", "null", "graph"], default="search",
                     help="search: the headline line (default); batch: batched against plain "
                          "searches over workload-4 series; served: the request server under "
                          "Poisson arrivals of workload-5 requests")
@@ -73,6 +74,7 @@ def parse():
 
 
 WORKLOAD_TEXT = {
+    1: "f32 series 2^16 samples, tsamp 1 ms, P0 500..999 (0.5-1.0 s), one octave, 10 widths, 500 FFA executions",
     2: "uint8 series 2^20 samples, tsamp 1 ms, P0 256..511 at f=1,2,4, 10 widths, 768 FFA executions, "
        "1835008 trials",
     3: "f32 series 2^23 samples (71.6 min at 0.512 ms) with red noise, 0.5-30 s, P0 256..511 at f=2..128, "
@@ -230,6 +232,58 @@ def run_batch(a) -> dict:
             "speedup": res["plain"] / res["batched"], "outputs_equal": same}
 
 
+def run_graph(a) -> dict:
+    """One search captured in a HIP graph and replayed, against the same
+    search launched eagerly; every replay's periodogram is checked equal to
+    the eager one."""
+    import torch
+
+    from paper_1703_05581_amd import ffa, synth
+
+    series = synth.workload(a.workload, 0)
+    plan = ffa.Plan.from_args(series.plan, snr=a.alg)
+    x = torch.from_numpy(series.data).cuda()
+    snr = torch.empty(plan.n_trials, dtype=torch.float32, device="cuda")
+    wid = torch.empty(plan.n_trials, dtype=torch.int32, device="cuda")
+    ws = plan.workspace()
+    for _ in range(max(1, a.warmup)):
+        plan.search(x, snr, wid, ws)  # also makes the plan's device tables
+    torch.cuda.synchronize()
+    ref = (snr.clone(), wid.clone())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.search(x, snr, wid, ws)
+    torch.cuda.synchronize()
+    same = True
+    for _ in range(3):  # replays with eager work in between
+        snr.zero_()
+        wid.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same &= torch.equal(snr, ref[0]) and torch.equal(wid, ref[1])
+    res = {}
+    for name, fn in (("eager", lambda: plan.search(x, snr, wid, ws)), ("graph", g.replay)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / a.steps
+    same &= torch.equal(snr, ref[0]) and torch.equal(wid, ref[1])
+    ts = trial_samples(plan)
+    return {"metric": "FFA trial*samples/s, search replayed from a HIP graph",
+            "value": ts / (res["graph"] / 1e3), "unit": "trial*samples/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": res["graph"], "higher_is_better": True,
+            "dtype": "i32" if series.plan.dtype == "u8" else "f32",
+            "data": f"synthetic (seeded; workload {a.workload} of paper_1703_05581_amd.synth)",
+            "config": {"workload": WORKLOAD_TEXT[a.workload], "trial_samples": ts},
+            "eager_ms": res["eager"], "speedup": res["eager"] / res["graph"], "outputs_equal": same}
+
+
 HIST_LO, HIST_BPU, HIST_BINS = -8.0, 256.0, 16384  # S/N -8 .. 56 in steps of 1/256
 
 
@@ -377,7 +431,7 @@ def main():
         import torch
 
         torch.cuda.init()
-        fn = {"batch": run_batch, "served": run_served, "null": run_null}[a.mode]
+        fn = {"batch": run_batch, "served": run_served, "null": run_null, "graph": run_graph}[a.mode]
         print(json.dumps(fn(a)))
         return
     import numpy as np
