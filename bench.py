@@ -62,7 +62,7 @@ def parse():
                          "dereddened) or 1 (small, launch-bound)")
     ap.add_argument("--alg", type=int, choices=[1, 2], default=1,
                     help="profile score: 1 = Algorithm 1 (the headline), 2 = Algorithm 2")
-    ap.add_argument("--mode", choices=["search", "batch", "served", "null", "graph"], default="search",
+    ap.add_argument("--mode", choices=["search", "batch", "served", "null", "graph", "tune"], default="search",
                     help="search: the headline line (default); batch: batched against plain "
                          "searches over workload-4 series; served: the request server under "
                          "Poisson arrivals of workload-5 requests")
@@ -284,6 +284,26 @@ def run_graph(a) -> dict:
             "eager_ms": res["eager"], "speedup": res["eager"] / res["graph"], "outputs_equal": same}
 
 
+def run_tune(a) -> dict:
+    """Autotune the plan knobs of the chosen workload (tune.DEFAULT_CANDIDATES)
+    and report every candidate's time; the choice goes to the tuning cache."""
+    import torch
+
+    from paper_1703_05581_amd import synth, tune
+
+    series = synth.workload(a.workload, 0)
+    x = torch.from_numpy(series.data).cuda()
+    res = tune.autotune(series.plan, x, snr=a.alg, reps=max(1, a.steps))
+    default_ms = res["trials"][0][1]
+    return {"metric": "FFA autotuning of the plan knobs", "value": res["ms"], "unit": "ms",
+            "higher_is_better": False, "n_gpus": 1, "steps": a.steps,
+            "data": f"synthetic (seeded; workload {a.workload} of paper_1703_05581_amd.synth)",
+            "config": {"workload": WORKLOAD_TEXT[a.workload], "shape_class": tune.shape_class(series.plan, a.alg),
+                       "arch": tune.arch_name()},
+            "best_knobs": res["knobs"], "default_ms": default_ms, "speedup_vs_default": default_ms / res["ms"],
+            "trials": [{"knobs": k, "ms": ms} for k, ms in res["trials"]]}
+
+
 HIST_LO, HIST_BPU, HIST_BINS = -8.0, 256.0, 16384  # S/N -8 .. 56 in steps of 1/256
 
 
@@ -431,7 +451,7 @@ def main():
         import torch
 
         torch.cuda.init()
-        fn = {"batch": run_batch, "served": run_served, "null": run_null, "graph": run_graph}[a.mode]
+        fn = {"batch": run_batch, "served": run_served, "null": run_null, "graph": run_graph, "tune": run_tune}[a.mode]
         print(json.dumps(fn(a)))
         return
     import numpy as np
