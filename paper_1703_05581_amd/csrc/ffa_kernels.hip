@@ -273,6 +273,11 @@ __device__ __forceinline__ void butterfly(T* lds, int S, int P0, int H, int d) {
   const int nfull = P0 / kWave;
   const bool tail = nfull * kWave + lane < P0;
   const int room = S - P0 < P0 ? S - P0 : P0;  // bins a halo may hold
+  // 1, hidden from the compiler: adjacent 16-bit reads of one row would be
+  // merged into one wider read that is not 4-byte aligned, which the LDS
+  // serves slowly
+  int one = 1;
+  asm volatile("" : "+s"(one));
   int l = 1;
   while (l <= d) {
     const int half = 1 << (l - 1);
@@ -301,11 +306,12 @@ __device__ __forceinline__ void butterfly(T* lds, int S, int P0, int H, int d) {
         const T* p1 = X1 + v + lane;
         const T* p2 = X2 + 2 * v + lane;
         const T* p3 = X3 + 3 * v + lane;
+        const T* p3b = p3 + one;  // x3b and x3d: kept apart from x3a and x3c
         auto unit = [&](int j) {
           const T x0 = X0[j + lane];
           const T x1a = p1[j], x1b = p1[j + 1];
           const T x2a = p2[j], x2b = p2[j + 1], x2c = p2[j + 2];
-          const T x3a = p3[j], x3b = p3[j + 1], x3c = p3[j + 2], x3d = p3[j + 3];
+          const T x3a = p3[j], x3b = p3b[j], x3c = p3[j + 2], x3d = p3b[j + 2];
           const T a0 = x0 + x1a, a1 = x0 + x1b;
           X0[j + lane] = a0 + (x2a + x3a);
           X2[j + lane] = a0 + (x2b + x3b);
