@@ -30,6 +30,7 @@ DEFAULT_CANDIDATES = (
     {"FFA_RING_MB": "8192", "FFA_WINDOW_TILES": "65536"},
     {"FFA_RING_MB": "2048"},
     {"FFA_TILE_LDS": "131072"},
+    {"FFA_U16": "0"},
 )
 
 
