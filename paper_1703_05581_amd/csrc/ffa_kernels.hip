@@ -233,6 +233,18 @@ __device__ __forceinline__ double wave_dmax(double v) {
   return __longlong_as_double((long long)readlane64(bits(v), 63));
 }
 
+// Maximum over lanes 0..15 (the first row; other lanes are ignored), as a
+// wave-uniform value: four in-row exchange steps instead of six.
+__device__ __forceinline__ double row_dmax16(double v) {
+  auto mx = [](double a, uint64_t b) { return fmax(a, __longlong_as_double((long long)b)); };
+  auto bits = [](double a) { return (uint64_t)__double_as_longlong(a); };
+  v = mx(v, dpp64<kDppXor1>(bits(v)));
+  v = mx(v, dpp64<kDppXor2>(bits(v)));
+  v = mx(v, dpp64<kDppHalfMirror>(bits(v)));
+  v = mx(v, dpp64<kDppRowMirror>(bits(v)));
+  return __longlong_as_double((long long)readlane64(bits(v), 0));
+}
+
 // Order-preserving 32-bit keys: integer sums (non-negative, < 2^31) are their
 // own keys; a finite float maps to an unsigned integer with the same order.
 __device__ __forceinline__ uint32_t fkey(float f) {
@@ -925,10 +937,11 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   if constexpr (INT) num = (double)(2 * (2 * (int64_t)pk_l - (int64_t)wt.w * (int64_t)med2));
   else num = (double)fval(pk_l) - (double)wt.w * (double)med;
   const double a = live ? num * wt.isq : -INFINITY;
-  const double amax = wave_dmax(a);
+  const bool row0 = nw <= 16;  // every width's lane is in the first row
+  const double amax = row0 ? row_dmax16(a) : wave_dmax(a);
   const bool cand = live && a >= amax - 1e-12 * fabs(amax);
   const double sc = cand ? num / (scale * wt.sq) : -INFINITY;
-  const double best = wave_dmax(sc);
+  const double best = row0 ? row_dmax16(sc) : wave_dmax(sc);
   const uint64_t hit = __ballot(cand && sc == best);
   const int first = __ffsll((unsigned long long)hit) - 1;
   const int32_t bw = wt.width(first);
