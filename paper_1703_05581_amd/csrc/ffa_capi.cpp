@@ -153,7 +153,10 @@ extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, v
     const Phase& ph = p->fold_phases[(size_t)sp.fold_phase0 + pass];
     a.phases = dt->fold_phases + sp.fold_phase0 + pass;
     a.tile0 = ph.tile0;
-    const int lds = (int)(((int64_t)1 << ph.depth) * ph.stride * 4 + (ph.last ? (int64_t)kScratchBytes : 0));
+    // the pass's LDS rows at the element size it was planned with (a 16-bit
+    // first pass of a uint8 step keeps 2-byte rows)
+    const int64_t esz = ph.u16 ? 2 : 4;
+    const int lds = (int)(((int64_t)1 << ph.depth) * ph.stride * esz + (ph.last ? (int64_t)kScratchBytes : 0));
     s = check_hip(launch_tiles(a, ph.ntiles, lds, ph.P0, is_int, d_ws, st), "FFA kernel");
     if (s != FFA_OK) return s;
   }

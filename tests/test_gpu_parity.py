@@ -310,3 +310,28 @@ def test_u16_first_passes_agree(torch_cuda, ffa, monkeypatch):
         outs.append([t.clone() for t in plan.search(x)])
         torch_cuda.cuda.synchronize()
     assert torch_cuda.equal(outs[0][0], outs[1][0]) and torch_cuda.equal(outs[0][1], outs[1][1])
+
+
+def test_fold_u16_first_pass_steps(torch_cuda, ffa, oracle_mod):
+    """ffa_fold of uint8 steps whose first pass keeps 16-bit rows: the fold
+    sizes each pass's LDS at the element size the planner used, so these
+    steps fold, bit-exact against the oracle."""
+    from tile_emu import phases
+
+    from paper_1703_05581_amd import synth
+
+    s = synth.workload2(0)
+    pa = s.plan
+    plan = ffa.Plan.from_args(pa)
+    ph = phases(plan)
+    u16_steps = sorted(set(int(v) for v in ph["step"][ph["u16"] == 1]))
+    assert len(u16_steps) > 100, len(u16_steps)
+    op = oracle_mod.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
+    x = torch_cuda.from_numpy(s.data).cuda()
+    ws = plan.workspace()
+    picks = u16_steps[:: max(1, len(u16_steps) // 6)][:6] + [u16_steps[-1]]
+    for st in picks:
+        print("fold u16 step", st, plan.step(st), plan.passes(st), flush=True)
+        prof = plan.fold(x, st, ws=ws).cpu().numpy()
+        ref = oracle_mod.fold_step(s.data, int(op.f[st]), int(op.P0[st]), int(op.m[st]), int(op.M[st]))
+        check_profiles(prof, ref, True)
