@@ -376,10 +376,9 @@ def run_served(a) -> dict:
     plans = {}
     # the 16 GiB pool holds more large requests with 2 GiB rings than with
     # the default 4 GiB (more requests in flight, higher capacity)
-    with tune.knobs({"FFA_RING_MB": "2048"}):
-        for s in pool:
-            if s.plan.N not in plans:
-                plans[s.plan.N] = ffa.Plan.from_args(s.plan)
+    for s in pool:
+        if s.plan.N not in plans:
+            plans[s.plan.N] = tune.make_plan(s.plan, {"ring_mb": 2048})
     srv = ffa.Server(16 << 30, 4)
     reqs = [pool[i % len(pool)] for i in range(a.requests + 100)]
     # capacity: a closed burst of the same mix

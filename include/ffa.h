@@ -113,6 +113,36 @@ typedef struct {
 ffa_status ffa_plan_create(const ffa_plan_desc* desc, ffa_plan* out);
 ffa_status ffa_plan_destroy(ffa_plan plan);
 
+/* Launch options of a plan.  They change how the work is cut into tiles,
+ * passes and launches (and so the speed), never a result: every setting
+ * gives the same periodogram, bit for bit.  A zeroed struct selects the
+ * defaults, which is what ffa_plan_create uses.
+ *   tile_lds_bytes   LDS budget of one tile, 16384..163840 (0: 163840)
+ *   window_tiles     tiles (all passes) per window group, 1..2^24 (0: 32768)
+ *   ring_mb          budget of the intermediate ring in MiB, 1..2^20 (0: 4096)
+ *   steps_per_window > 0: that many steps per window group instead (0: by tiles)
+ *   no_u16           1: uint8 steps keep 32-bit rows in every pass (0: a first
+ *                    pass may keep exact 16-bit sums where they fit)
+ *   no_split_occupancy  1: one launch per window (0: one per LDS occupancy class)
+ *   select_iters, select_cand   exits of the median/MAD selection, for tests:
+ *                    counting rounds before key halving (0: 64; < 0: none)
+ *                    and candidates handed to the in-register select (0: 64,
+ *                    else 1..64)
+ * Out-of-range values give FFA_ERR_INVALID. */
+typedef struct {
+  int32_t tile_lds_bytes;
+  int32_t window_tiles;
+  int32_t ring_mb;
+  int32_t steps_per_window;
+  int32_t no_u16;
+  int32_t no_split_occupancy;
+  int32_t select_iters;
+  int32_t select_cand;
+} ffa_plan_opts;
+
+/* ffa_plan_create with launch options (opts NULL: the defaults). */
+ffa_status ffa_plan_create_opts(const ffa_plan_desc* desc, const ffa_plan_opts* opts, ffa_plan* out);
+
 /* Totals of a plan.  ws_bytes is the device workspace ffa_search and
  * ffa_fold need.  Any output pointer may be NULL. */
 ffa_status ffa_plan_query(ffa_plan plan, int64_t* n_trials, int32_t* n_steps,
@@ -257,15 +287,40 @@ ffa_status ffa_sigma_threshold(const uint64_t* hist, int32_t n_bins, float lo,
                                float bins_per_unit, double sigma, double* snr);
 
 /* Batched search: the periodograms of n series, each with its own plan (any
- * mix of sample types).  The series are spread over a few streams that the
- * library owns on the current GPU, which wait for earlier work on `stream`
- * and which `stream` waits for, so the call behaves as if it were enqueued on
- * `stream`.
- *   plans[i], d_series[i], d_snr[i], d_width[i]  host arrays of n entries
- *   d_ws   workspace of at least ffa_batch_workspace(n, plans) bytes,
- *          256-B aligned
- * Results equal those of ffa_search on each series.  Errors as ffa_search;
- * after a launch error the work already enqueued still runs to its end. */
+ * mix of lengths, period ranges, sample types and algorithms).  Sec. 4 of
+ * the paper searches many dedispersed series of one observation; a batch
+ * runs them as one work queue.  The steps of all its series are cut into
+ * window groups of about window_tiles tiles, whatever series they belong to,
+ * so one launch runs the tiles of many series (one queue per kind of
+ * arithmetic: exact integer or float folds, Algorithm 1 or 2).
+ *
+ * ffa_batch_create plans a batch of the n plans (host only; the plans must
+ * outlive the batch, which keeps pointers to them).  Device tables are made
+ * on the first search on a GPU.  ffa_batch_query gives the workspace bytes a
+ * search needs, the tiles and the kernel launches of one search (any output
+ * pointer may be NULL).  ffa_batch_destroy frees the batch; the caller makes
+ * sure no search of it is still running.
+ *
+ * ffa_batch_search enqueues the search of all n series on `stream`:
+ *   d_series[i], d_snr[i], d_width[i]  host arrays of n device pointers:
+ *          series i (N_i samples of plan i's type) and its periodogram
+ *          (n_trials_i floats and ints, as ffa_search writes them)
+ *   d_ws   workspace of at least the batch's ws_bytes, 256-B aligned
+ * Results equal those of ffa_search on each series, bit for bit.
+ * Errors: FFA_ERR_INVALID (NULL pointer, small workspace),
+ * FFA_ERR_NOMEM, FFA_ERR_DEVICE; after a launch error, work already enqueued
+ * still runs to its end.
+ *
+ * ffa_batch_workspace and ffa_search_batch do the same from the plan list
+ * itself: the library keeps the batches of the last few plan lists it was
+ * given (a destroyed plan never matches), so a repeated call does not plan
+ * again, and frees an evicted batch once its last search is done. */
+typedef struct ffa_batch_s* ffa_batch;
+ffa_status ffa_batch_create(int32_t n, const ffa_plan* plans, ffa_batch* out);
+ffa_status ffa_batch_destroy(ffa_batch batch);
+ffa_status ffa_batch_query(ffa_batch batch, size_t* ws_bytes, int64_t* n_tiles, int32_t* n_launches);
+ffa_status ffa_batch_search(ffa_batch batch, const void* const* d_series, float* const* d_snr,
+                            int32_t* const* d_width, void* d_ws, size_t ws_bytes, void* stream);
 ffa_status ffa_batch_workspace(int32_t n, const ffa_plan* plans,
                                size_t* ws_bytes);
 ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,

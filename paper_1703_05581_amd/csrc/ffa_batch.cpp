@@ -1,10 +1,24 @@
-// Batched search: the periodograms of many series, each with its own plan.
-// The series are spread over a few library-owned HIP streams, joined to the
-// caller's stream with events, so the launches of one series fill the GPU
-// while another's drain.
+// Batched search: the periodograms of many series, each with its own plan,
+// as one work queue.
+//
+// Every step of every series goes into one step list (series by series, each
+// in its plan's step order).  The list is cut into window groups like one
+// plan's (about window_tiles tiles each, within one shared intermediate
+// ring), so a launch holds the tiles of many series at once: small series no
+// longer run launches of a few thousand tiles, and the launch tails of one
+// series fill with another's tiles.  Plans that fold in different arithmetic
+// (exact integers or float) or score with different algorithms form separate
+// classes, each its own queue, since their tiles run different kernel
+// variants.  Each series keeps its plan's octave series in a region of its
+// own in the batch workspace; outputs go through a per-series table the
+// kernels index by Phase::series.
 #include <algorithm>
-#include <deque>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <memory>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "ffa_internal.h"
@@ -15,111 +29,399 @@ namespace {
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-// Streams and events of one device (default priority; never destroyed).
-struct StreamPool {
-  int device = -1;
-  hipStream_t streams[kBatchStreams] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[kBatchStreams] = {};
-  std::mutex mu;  // one batch enqueues on the pool at a time
+// Device copies of one class's tables.
+struct ClassDev {
+  Phase* phases = nullptr;
+  int32_t* tile_phase = nullptr;
+  int32_t* widths = nullptr;
+  double* sqrtw = nullptr;
 };
 
-ffa_status stream_pool(StreamPool** out) {
-  static std::mutex mu;
-  static std::deque<StreamPool> pools;
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
-  std::lock_guard<std::mutex> lk(mu);
-  for (auto& p : pools)
-    if (p.device == dev) {
-      *out = &p;
-      return FFA_OK;
+struct BatchDev {
+  int device = -1;
+  std::vector<ClassDev> cls;
+  hipEvent_t done = nullptr;  // recorded after each search (cached batches only)
+};
+
+struct BatchClass {
+  int32_t is_int = 0, alg = 1, select_iters = 64, select_cand = 64;
+  std::vector<Step> steps;
+  std::vector<Phase> nat;
+  Queue q;
+  int64_t ring_off = 0;
+  std::vector<int32_t> wtab;
+  std::vector<double> sqrtw;  // sqrt(width) of every entry, then 1/sqrt(width)
+};
+
+void free_class(ClassDev& c) {
+  if (c.phases) (void)hipFree(c.phases);
+  if (c.tile_phase) (void)hipFree(c.tile_phase);
+  if (c.widths) (void)hipFree(c.widths);
+  if (c.sqrtw) (void)hipFree(c.sqrtw);
+  c = ClassDev();
+}
+
+}  // namespace
+
+struct ffa_batch_s {
+  std::vector<ffa_plan> plans;  // not owned
+  std::vector<uint64_t> uids;
+  std::vector<int64_t> series_base;  // element offset of each series' region
+  int64_t outs_off = 0;              // element offset of the SeriesOut table
+  std::vector<BatchClass> classes;
+  int64_t n_tiles = 0;
+  int32_t n_launches = 0;
+  size_t ws_bytes = 0;
+  bool track_use = false;  // record an event after each search (cached batches)
+  std::mutex dev_mu;
+  std::deque<BatchDev> dev;
+};
+
+namespace {
+
+void free_batch_device(ffa_batch_s* b) {
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  for (auto& d : b->dev) {
+    if (d.device != cur) (void)hipSetDevice(d.device);
+    if (d.done) {
+      (void)hipEventSynchronize(d.done);
+      (void)hipEventDestroy(d.done);
     }
-  pools.emplace_back();
-  StreamPool& p = pools.back();
-  bool ok = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) == hipSuccess;
-  for (int j = 0; ok && j < kBatchStreams; ++j)
-    ok = hipStreamCreateWithFlags(&p.streams[j], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&p.join[j], hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
-    pools.pop_back();
-    return fail(FFA_ERR_DEVICE, "cannot create the batch streams");
+    for (auto& c : d.cls) free_class(c);
+    if (d.device != cur && cur >= 0) (void)hipSetDevice(cur);
   }
-  p.device = dev;
-  *out = &p;
+  b->dev.clear();
+}
+
+// Host planning of a batch: classes, steps, queues, workspace layout.
+ffa_status plan_batch(int32_t n, const ffa_plan* plans, ffa_batch_s** out) {
+  if (n < 1 || !plans) return fail(FFA_ERR_INVALID, "need at least one plan");
+  for (int32_t i = 0; i < n; ++i)
+    if (!plans[i]) return fail(FFA_ERR_INVALID, "null plan");
+  std::unique_ptr<ffa_batch_s> b(new (std::nothrow) ffa_batch_s());
+  if (!b) return fail(FFA_ERR_NOMEM, "batch allocation");
+  b->plans.assign(plans, plans + n);
+  for (int32_t i = 0; i < n; ++i) b->uids.push_back(plans[i]->uid);
+  // workspace: output table, then one series region per series
+  int64_t cur = 0;
+  b->outs_off = cur;
+  cur = round_up(cur + 4 * (int64_t)n, 64);  // SeriesOut is 16 B = 4 elements
+  for (int32_t i = 0; i < n; ++i) {
+    b->series_base.push_back(cur);
+    cur = round_up(cur + plans[i]->series_elems, 64);
+  }
+  // classes: (exact integer folds, algorithm, selection exits)
+  std::vector<int32_t> cls_of((size_t)n, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    const ffa_plan p = plans[i];
+    const int32_t alg = p->desc.snr == FFA_SNR_ALG2_OFFPULSE ? 2 : 1;
+    for (size_t c = 0; c < b->classes.size(); ++c) {
+      const BatchClass& k = b->classes[c];
+      if (k.is_int == p->acc_int && k.alg == alg && k.select_iters == p->select_iters &&
+          k.select_cand == p->select_cand)
+        cls_of[(size_t)i] = (int32_t)c;
+    }
+    if (cls_of[(size_t)i] < 0) {
+      BatchClass k;
+      k.is_int = p->acc_int;
+      k.alg = alg;
+      k.select_iters = p->select_iters;
+      k.select_cand = p->select_cand;
+      cls_of[(size_t)i] = (int32_t)b->classes.size();
+      b->classes.push_back(std::move(k));
+    }
+  }
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    BatchClass& k = b->classes[c];
+    // width tables of the class: each plan's widths at an offset
+    std::vector<int32_t> wbase((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+      if (cls_of[(size_t)i] != (int32_t)c) continue;
+      wbase[(size_t)i] = (int32_t)k.wtab.size();
+      k.wtab.insert(k.wtab.end(), plans[i]->wtab.begin(), plans[i]->wtab.end());
+    }
+    const int32_t nsq = (int32_t)k.wtab.size();
+    for (int32_t w : k.wtab) k.sqrtw.push_back(std::sqrt((double)w));
+    for (int32_t j = 0; j < nsq; ++j) k.sqrtw.push_back(1.0 / k.sqrtw[(size_t)j]);
+    // the launch knobs of the class: the largest windows and ring any of its
+    // plans asks for
+    QueueKnobs kn;
+    bool first = true;
+    for (int32_t i = 0; i < n; ++i) {
+      if (cls_of[(size_t)i] != (int32_t)c) continue;
+      const QueueKnobs& pk = plans[i]->knobs;
+      if (first) {
+        kn = pk;
+        first = false;
+      } else {
+        kn.window_tiles = std::max(kn.window_tiles, pk.window_tiles);
+        kn.ring_bytes = std::max(kn.ring_bytes, pk.ring_bytes);
+        if (kn.fixed_steps != pk.fixed_steps) kn.fixed_steps = 0;
+        kn.split_occupancy = kn.split_occupancy && pk.split_occupancy;
+      }
+    }
+    // steps and their natural-order phases, series by series
+    for (int32_t i = 0; i < n; ++i) {
+      if (cls_of[(size_t)i] != (int32_t)c) continue;
+      const ffa_plan p = plans[i];
+      for (const Step& ps : p->steps) {
+        Step s = ps;
+        s.series = i;
+        s.oct_off = b->series_base[(size_t)i] + p->oct_off[(size_t)s.octave];
+        s.in_end = s.oct_off + p->oct_len[(size_t)s.octave];
+        s.wofs = ps.wofs + wbase[(size_t)i];
+        s.fold_phase0 = (int32_t)k.nat.size();
+        const int32_t si = (int32_t)k.steps.size();
+        for (int32_t pass = 0; pass < s.n_passes; ++pass) {
+          Phase ph = p->nat_phases[(size_t)(ps.fold_phase0 + pass)];
+          ph.step = si;
+          ph.series = i;
+          ph.oct_off = s.oct_off;
+          ph.wofs = s.wofs;
+          ph.isqrt_ofs = nsq + s.wofs;
+          k.nat.push_back(ph);
+        }
+        k.steps.push_back(s);
+      }
+    }
+    ffa_status st = build_queue(k.steps, k.nat, kn, &k.q);
+    if (st != FFA_OK) return st;
+    if (!queue_valid(k.steps, k.q, k.is_int))
+      return fail(FFA_ERR_INVALID, "internal planning error: a batch tile reaches outside its buffers");
+    k.ring_off = round_up(cur, 64);
+    cur = k.ring_off + k.q.ring_elems;
+    b->n_tiles += k.q.n_tiles;
+    b->n_launches += (int32_t)k.q.launches.size();
+  }
+  b->ws_bytes = (size_t)round_up(cur * 4, (int64_t)kWsAlign);
+  *out = b.release();
   return FFA_OK;
 }
 
-// Batch workspace: one region per stream used, each large enough for the
-// largest plan's workspace.
-ffa_status batch_layout(int32_t n, const ffa_plan* plans, int32_t* regions, size_t* region_bytes) {
-  if (n < 1 || !plans) return fail(FFA_ERR_INVALID, "need at least one plan");
-  size_t r = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    if (!plans[i]) return fail(FFA_ERR_INVALID, "null plan");
-    r = std::max(r, plans[i]->ws_bytes);
+// Device tables of batch b on the current device (made on first use).
+ffa_status batch_device(ffa_batch_s* b, BatchDev** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(b->dev_mu);
+  for (auto& d : b->dev)
+    if (d.device == dev) {
+      *out = &d;
+      return FFA_OK;
+    }
+  BatchDev d;
+  d.device = dev;
+  auto release = [&] {
+    for (auto& c : d.cls) free_class(c);
+    if (d.done) (void)hipEventDestroy(d.done);
+  };
+  ffa_status st = FFA_OK;
+  if (b->track_use) st = check_hip(hipEventCreateWithFlags(&d.done, hipEventDisableTiming), "batch event");
+  for (const BatchClass& k : b->classes) {
+    if (st != FFA_OK) break;
+    ClassDev c;
+    const size_t pb = k.q.phases.size() * sizeof(Phase);
+    const size_t tb = k.q.tile_phase.size() * sizeof(int32_t);
+    const size_t wb = std::max<size_t>(k.wtab.size(), 1) * sizeof(int32_t);
+    const size_t sb = std::max<size_t>(k.sqrtw.size(), 1) * sizeof(double);
+    if (hipMalloc(&c.phases, pb) != hipSuccess || hipMalloc(&c.tile_phase, tb) != hipSuccess ||
+        hipMalloc(&c.widths, wb) != hipSuccess || hipMalloc(&c.sqrtw, sb) != hipSuccess) {
+      free_class(c);
+      st = fail(FFA_ERR_NOMEM, "batch tables: hipMalloc failed");
+      break;
+    }
+    d.cls.push_back(c);
+    st = check_hip(hipMemcpy(c.phases, k.q.phases.data(), pb, hipMemcpyHostToDevice), "upload batch phases");
+    if (st == FFA_OK)
+      st = check_hip(hipMemcpy(c.tile_phase, k.q.tile_phase.data(), tb, hipMemcpyHostToDevice),
+                     "upload batch tile map");
+    if (st == FFA_OK && !k.wtab.empty())
+      st = check_hip(hipMemcpy(c.widths, k.wtab.data(), k.wtab.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                     "upload batch widths");
+    if (st == FFA_OK && !k.sqrtw.empty())
+      st = check_hip(hipMemcpy(c.sqrtw, k.sqrtw.data(), k.sqrtw.size() * sizeof(double), hipMemcpyHostToDevice),
+                     "upload batch sqrt widths");
   }
-  *regions = std::min<int32_t>(n, kBatchStreams);
-  *region_bytes = (size_t)round_up((int64_t)r, (int64_t)kWsAlign);
+  if (st != FFA_OK) {
+    release();
+    return st;
+  }
+  b->dev.push_back(std::move(d));
+  *out = &b->dev.back();
+  return FFA_OK;
+}
+
+ffa_status run_batch(ffa_batch_s* b, const void* const* d_series, float* const* d_snr, int32_t* const* d_width,
+                     void* d_ws, size_t ws_bytes, hipStream_t st) {
+  if (!d_series || !d_snr || !d_width || !d_ws) return fail(FFA_ERR_INVALID, "null argument");
+  if (ws_bytes < b->ws_bytes) return fail(FFA_ERR_INVALID, "workspace smaller than the batch's ws_bytes");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) return fail(FFA_ERR_INVALID, "workspace not 256-byte aligned");
+  const size_t n = b->plans.size();
+  std::vector<SeriesOut> outs(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!d_series[i] || !d_snr[i] || !d_width[i]) return fail(FFA_ERR_INVALID, "null series or output");
+    outs[i] = SeriesOut{d_snr[i], d_width[i]};
+  }
+  BatchDev* dev = nullptr;
+  ffa_status s = batch_device(b, &dev);
+  if (s != FFA_OK) return s;
+  char* ws = reinterpret_cast<char*>(d_ws);
+  SeriesOut* outs_dev = reinterpret_cast<SeriesOut*>(ws + (size_t)b->outs_off * 4);
+  s = check_hip(launch_set_outs(outs_dev, outs.data(), (int32_t)n, st), "output table kernel");
+  // every series' octave series (centred float, or exact integer sums), each in its region
+  for (size_t i = 0; i < n && s == FFA_OK; ++i) {
+    const ffa_plan p = b->plans[i];
+    s = build_octaves(p, d_series[i], ws + (size_t)b->series_base[i] * 4, p->n_octaves - 1, 1, st);
+  }
+  // the queues, window by window
+  for (size_t c = 0; c < b->classes.size() && s == FFA_OK; ++c) {
+    const BatchClass& k = b->classes[c];
+    const ClassDev& cd = dev->cls[c];
+    TileArgs a{};
+    a.phases = cd.phases;
+    a.tile_phase = cd.tile_phase;
+    a.widths = cd.widths;
+    a.sqrtw = cd.sqrtw;
+    a.outs = outs_dev;
+    a.oct_base = 0;
+    a.ring_off = k.ring_off;
+    a.mode = kModeScore;
+    a.alg = k.alg;
+    a.select_iters = k.select_iters;
+    a.select_cand = k.select_cand;
+    for (const Launch& w : k.q.launches) {
+      if (w.ntiles == 0) continue;
+      a.tile0 = w.tile0;
+      s = check_hip(launch_tiles(a, w.ntiles, w.lds_bytes, w.max_P0, k.is_int, d_ws, st), "FFA kernel");
+      if (s != FFA_OK) break;
+    }
+  }
+  if (b->track_use && dev->done) {
+    const ffa_status e = check_hip(hipEventRecord(dev->done, st), "batch event record");
+    if (s == FFA_OK) s = e;
+  }
+  return s;
+}
+
+// Batches made by ffa_search_batch / ffa_batch_workspace, kept for reuse:
+// the most recently used few, keyed by their plans (plan uids are never
+// reused, so a destroyed plan never matches).  An evicted batch waits for its
+// last search before its tables are freed.
+constexpr size_t kCacheSize = 4;
+std::mutex g_cache_mu;
+std::list<std::shared_ptr<ffa_batch_s>> g_cache;
+
+ffa_status cached_batch(int32_t n, const ffa_plan* plans, std::shared_ptr<ffa_batch_s>* out) {
+  if (n < 1 || !plans) return fail(FFA_ERR_INVALID, "need at least one plan");
+  for (int32_t i = 0; i < n; ++i)
+    if (!plans[i]) return fail(FFA_ERR_INVALID, "null plan");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+    const ffa_batch_s& b = **it;
+    if (b.plans.size() != (size_t)n) continue;
+    bool same = true;
+    for (int32_t i = 0; i < n && same; ++i) same = b.plans[(size_t)i] == plans[i] && b.uids[(size_t)i] == plans[i]->uid;
+    if (same) {
+      g_cache.splice(g_cache.begin(), g_cache, it);
+      *out = g_cache.front();
+      return FFA_OK;
+    }
+  }
+  ffa_batch_s* raw = nullptr;
+  ffa_status s = plan_batch(n, plans, &raw);
+  if (s != FFA_OK) return s;
+  raw->track_use = true;
+  std::shared_ptr<ffa_batch_s> sp(raw, [](ffa_batch_s* b) {
+    free_batch_device(b);
+    delete b;
+  });
+  g_cache.push_front(sp);
+  while (g_cache.size() > kCacheSize) g_cache.pop_back();
+  *out = sp;
   return FFA_OK;
 }
 
 }  // namespace
 
+extern "C" ffa_status ffa_batch_create(int32_t n, const ffa_plan* plans, ffa_batch* out) {
+  if (!out) return fail(FFA_ERR_INVALID, "null argument");
+  *out = nullptr;
+  ffa_batch_s* b = nullptr;
+  ffa_status s = plan_batch(n, plans, &b);
+  if (s != FFA_OK) return s;
+  *out = b;
+  return FFA_OK;
+}
+
+extern "C" ffa_status ffa_batch_destroy(ffa_batch b) {
+  if (!b) return fail(FFA_ERR_INVALID, "null batch");
+  free_batch_device(b);
+  delete b;
+  return FFA_OK;
+}
+
+extern "C" ffa_status ffa_batch_query(ffa_batch b, size_t* ws_bytes, int64_t* n_tiles, int32_t* n_launches) {
+  if (!b) return fail(FFA_ERR_INVALID, "null batch");
+  if (ws_bytes) *ws_bytes = b->ws_bytes;
+  if (n_tiles) *n_tiles = b->n_tiles;
+  if (n_launches) *n_launches = b->n_launches;
+  return FFA_OK;
+}
+
+extern "C" ffa_status ffa_batch_search(ffa_batch b, const void* const* d_series, float* const* d_snr,
+                                       int32_t* const* d_width, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!b) return fail(FFA_ERR_INVALID, "null batch");
+  return run_batch(b, d_series, d_snr, d_width, d_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" ffa_status ffa_batch_workspace(int32_t n, const ffa_plan* plans, size_t* ws_bytes) {
   if (!ws_bytes) return fail(FFA_ERR_INVALID, "null argument");
-  int32_t regions = 0;
-  size_t rb = 0;
-  ffa_status s = batch_layout(n, plans, &regions, &rb);
+  std::shared_ptr<ffa_batch_s> b;
+  ffa_status s = cached_batch(n, plans, &b);
   if (s != FFA_OK) return s;
-  *ws_bytes = (size_t)regions * rb;
+  *ws_bytes = b->ws_bytes;
   return FFA_OK;
 }
 
 extern "C" ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans, const void* const* d_series,
                                        float* const* d_snr, int32_t* const* d_width, void* d_ws,
                                        size_t ws_bytes, void* stream) {
-  if (!d_series || !d_snr || !d_width || !d_ws) return fail(FFA_ERR_INVALID, "null argument");
-  int32_t regions = 0;
-  size_t rb = 0;
-  ffa_status s = batch_layout(n, plans, &regions, &rb);
+  std::shared_ptr<ffa_batch_s> b;
+  ffa_status s = cached_batch(n, plans, &b);
   if (s != FFA_OK) return s;
-  if (ws_bytes < (size_t)regions * rb) return fail(FFA_ERR_INVALID, "workspace smaller than ffa_batch_workspace");
-  if (reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) return fail(FFA_ERR_INVALID, "workspace not 256-byte aligned");
-  std::vector<const DeviceTables*> dts((size_t)n);
-  for (int32_t i = 0; i < n; ++i) {
-    if (!d_series[i] || !d_snr[i] || !d_width[i]) return fail(FFA_ERR_INVALID, "null series or output");
-    s = device_tables(plans[i], &dts[(size_t)i]);
-    if (s != FFA_OK) return s;
+  return run_batch(b.get(), d_series, d_snr, d_width, d_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+// Test hook (not in the public header): the queue of class c of a batch
+// (phases and launches), so host tests can walk it like a plan's.
+extern "C" int64_t ffa_debug_batch(ffa_batch b, int32_t c, void* phases, int64_t cap, int64_t* layout,
+                                   int64_t lcap) {
+  if (!b || c < 0 || c >= (int32_t)b->classes.size()) return -1;
+  const BatchClass& k = b->classes[(size_t)c];
+  const int64_t n = (int64_t)k.q.phases.size();
+  if (phases && cap >= n) std::memcpy(phases, k.q.phases.data(), (size_t)n * sizeof(Phase));
+  const int64_t nw = (int64_t)k.q.launches.size();
+  if (layout && lcap >= 8 + 4 * nw) {
+    layout[0] = k.ring_off;
+    layout[1] = k.q.ring_elems;
+    layout[2] = (int64_t)b->classes.size();
+    layout[3] = k.q.n_tiles;
+    layout[4] = k.q.lds_bytes;
+    layout[5] = k.q.max_P0;
+    layout[6] = (int64_t)b->ws_bytes;
+    layout[7] = k.q.lookahead;
+    for (int64_t i = 0; i < nw; ++i) {
+      const Launch& w = k.q.launches[(size_t)i];
+      layout[8 + 4 * i] = w.tile0;
+      layout[9 + 4 * i] = w.ntiles;
+      layout[10 + 4 * i] = w.lds_bytes;
+      layout[11 + 4 * i] = w.max_P0;
+    }
   }
-  StreamPool* pool = nullptr;
-  s = stream_pool(&pool);
-  if (s != FFA_OK) return s;
-  hipStream_t caller = reinterpret_cast<hipStream_t>(stream);
-  std::lock_guard<std::mutex> lk(pool->mu);
-  s = check_hip(hipEventRecord(pool->fork, caller), "record fork event");
-  if (s != FFA_OK) return s;
-  for (int32_t j = 0; j < regions; ++j) {
-    s = check_hip(hipStreamWaitEvent(pool->streams[j], pool->fork, 0), "fork wait");
-    if (s != FFA_OK) return s;
-  }
-  // Series i runs on stream i mod regions, in region i mod regions; the
-  // series of one stream run one after another, so they can share its region.
-  ffa_status first_error = FFA_OK;
-  for (int32_t i = 0; i < n && first_error == FFA_OK; ++i) {
-    const int32_t j = i % regions;
-    void* region = reinterpret_cast<char*>(d_ws) + (size_t)j * rb;
-    ffa_plan p = plans[i];
-    first_error = build_octaves(p, d_series[i], region, p->n_octaves - 1, 1, pool->streams[j]);
-    if (first_error == FFA_OK)
-      first_error = run_launches(p, dts[(size_t)i], d_snr[i], d_width[i], region, pool->streams[j]);
-  }
-  // join every stream, also after an error, so the caller's stream never
-  // runs ahead of work already enqueued
-  for (int32_t j = 0; j < regions; ++j) {
-    ffa_status e = check_hip(hipEventRecord(pool->join[j], pool->streams[j]), "record join event");
-    if (e == FFA_OK) e = check_hip(hipStreamWaitEvent(caller, pool->join[j], 0), "join wait");
-    if (first_error == FFA_OK) first_error = e;
-  }
-  return first_error;
+  return n;
+}
+
+extern "C" int64_t ffa_debug_batch_series_base(ffa_batch b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->series_base.size()) return -1;
+  return b->series_base[(size_t)i];
 }

@@ -22,7 +22,6 @@ constexpr int kThreads = 1024;            // threads per workgroup of the FFA ke
 constexpr size_t kLdsBytes = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr size_t kWsAlign = 256;
 constexpr size_t kScratchBytes = (kThreads / 64) * 64 * 4;  // per-wave selection scratch
-constexpr int kBatchStreams = 4;          // streams a batched search spreads its series over
 
 // sigma = K * MAD (paper Sec. 2.2.1): K is 1 / (75% quantile of the unit normal).
 constexpr double kMadK = 1.482602218505602;
@@ -35,7 +34,7 @@ enum : int32_t { kModeScore = 1, kModeProfiles = 2 };
 // h = k % ng.
 struct Phase {
   int64_t tile0;        // first tile of the phase in its plan's queue order
-  int64_t oct_off;      // pass 0: series-relative offset of the octave series
+  int64_t oct_off;      // pass 0: element offset of the octave series in the workspace
   int64_t first_trial;  // trial index of the step's trial 0
   int32_t ntiles;
   int32_t ng;           // groups with data per problem
@@ -55,8 +54,17 @@ struct Phase {
   int32_t launch;       // index of the launch that runs the phase
   int32_t u16;          // 1: the tile keeps its rows as 16-bit sums in LDS
   int32_t ring64;       // multi-pass step: its intermediates start at ring_off + 64*ring64
+  int32_t series;       // series of a batch (index of its output pointers); 0 for one plan
+  int32_t reserved;
 };
-static_assert(sizeof(Phase) == 96, "phase layout");
+static_assert(sizeof(Phase) == 104, "phase layout");
+
+// Periodogram outputs of one series of a batch (device table, one entry per
+// series, indexed by Phase::series).
+struct SeriesOut {
+  float* snr;
+  int32_t* width;
+};
 
 // Arguments of one launch of the FFA kernel: tiles tile0 .. tile0+grid-1 of a
 // plan's queue (or of one step's passes, for a fold).
@@ -67,6 +75,7 @@ struct TileArgs {
   const double* sqrtw;
   float* snr;
   int32_t* width;
+  const SeriesOut* outs;      // batch: per-series outputs (replaces snr/width); null otherwise
   void* profiles;             // fold: M*P0 output of the step
   int64_t tile0;
   int64_t oct_base;           // element offset of the series region in the workspace
@@ -91,6 +100,9 @@ struct Step {
   int64_t lds_budget = 0;     // LDS bytes a tile may use
   int32_t u16_first = 0;      // the first of two passes keeps 16-bit sums
   int64_t ring_pos = 0;       // multi-pass: element offset of its intermediates in the ring
+  int32_t series = 0;         // series of a batch
+  int64_t oct_off = 0;        // element offset (in the workspace) of the octave series it folds
+  int64_t in_end = 0;         // end of that octave series: pass 0 reads within [oct_off, in_end)
 };
 
 // One launch of a search: a window of the queue whose tiles depend only on
@@ -100,6 +112,42 @@ struct Launch {
   int32_t lds_bytes;
   int32_t max_P0;
 };
+
+// Launch knobs of a work queue (they change the launches, never a result).
+struct QueueKnobs {
+  int64_t window_tiles = 32768;          // target tiles per window group (all passes)
+  int64_t ring_bytes = int64_t(4096) << 20;  // intermediate ring budget
+  int64_t fixed_steps = 0;               // > 0: that many steps per window group instead
+  bool split_occupancy = true;           // one launch per LDS occupancy class in each window
+};
+
+// The work queue of a list of steps (one plan's, or every step of a batch of
+// plans): their passes' phases in queue order, the tile -> phase map, the
+// launches, and the intermediate ring the multi-pass steps share.
+struct Queue {
+  std::vector<Phase> phases;     // queue order: pass p of step group g in window g + p
+  std::vector<int32_t> tile_phase;
+  std::vector<Launch> launches;
+  int64_t n_tiles = 0;
+  int64_t ring_elems = 0;
+  int32_t max_passes = 1;
+  int32_t lookahead = 1;         // steps in the largest window group
+  int32_t lds_bytes = 0;
+  int32_t max_P0 = 0;
+};
+
+// Orders the phases of `steps` into a queue.  `nat` holds every step's passes
+// in order (steps[i].fold_phase0 indexes it).  Sets each multi-pass step's
+// ring_pos and the phases' ring64.  Returns FFA_ERR_UNSUPPORTED when the
+// queue has 2^31 tiles or more.
+ffa_status build_queue(std::vector<Step>& steps, std::vector<Phase>& nat, const QueueKnobs& kn, Queue* q);
+// Every tile of the queue reads and writes inside its buffers and reads only
+// what an earlier launch wrote (checked on the host before any launch).
+// acc_int: the queue folds exact integer sums (16-bit first passes allowed).
+bool queue_valid(const std::vector<Step>& steps, const Queue& q, int acc_int);
+// Bytes of LDS a phase's tile uses (its rows at the planned element size, and
+// the selection scratch on a scoring pass).
+int64_t phase_lds(const Phase& ph);
 
 // A step as the candidate sifting needs it (trial -> period).
 struct StepDev {
@@ -126,11 +174,14 @@ struct DeviceTables {
 struct ffa_plan_s {
   ffa_plan_desc desc;
   std::vector<int32_t> user_widths;
+  uint64_t uid = 0;                     // unique per plan created in the process
   std::vector<ffa::Step> steps;
+  std::vector<ffa::Phase> nat_phases;   // per step, its passes in order (ring placement unset)
   std::vector<ffa::Phase> phases;       // queue order: pass p of step group g in window g + p
   std::vector<ffa::Phase> fold_phases;  // per step, its passes in order
   std::vector<int32_t> tile_phase;      // queue tile -> index in phases
   std::vector<ffa::Launch> launches;     // launches of a search, in order
+  ffa::QueueKnobs knobs;                // the knobs the queue was built with
   std::vector<int32_t> wtab;            // widths of every step, concatenated
   std::vector<double> sqrtw;            // sqrt(width), same layout, then 1/sqrt(width)
   int64_t n_trials = 0;
@@ -198,6 +249,9 @@ bool tiles_fit(int is_int, int max_P0, int lds_bytes, int alg);
 hipError_t launch_tiles(const TileArgs& a, int64_t ntiles, int lds_bytes, int max_P0, int is_int,
                         void* ws, hipStream_t st);
 hipError_t launch_best(const float* snr, int64_t n, int64_t* best, hipStream_t st);
+// Writes the n entries of host array src to the device table dst (kernel
+// arguments carry the values, so nothing on the host must outlive the call).
+hipError_t launch_set_outs(SeriesOut* dst, const SeriesOut* src, int32_t n, hipStream_t st);
 constexpr int32_t kHistMaxBins = 16384;
 hipError_t launch_snr_histogram(const float* snr, int64_t n, float lo, float bins_per_unit, int32_t n_bins,
                                 uint64_t* hist, hipStream_t st);

@@ -1130,11 +1130,19 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
     wt.isq = lane < ph.nw ? isw[lane] : 1.0;
     const int wmax = (int)wave_umax((uint32_t)wt.w);
     const int64_t trial0 = ph.first_trial + ((int64_t)q << d);
+    // a batch's tiles write their own series' periodogram
+    float* snr_out = a.snr;
+    int32_t* width_out = a.width;
+    if (a.outs) {
+      const SeriesOut so = a.outs[ph.series];
+      snr_out = so.snr;
+      width_out = so.width;
+    }
     WavePrior wp{0.f, 0.f};
     for (int tt = wave; tt < R; tt += nwaves) {
       T* row = lds + (size_t)bitrev(tt, d) * S;
       const int64_t trial = trial0 + tt;
-      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, wt, ph.nw, kn, wp, a.snr + trial, a.width + trial);
+      score_dispatch<INT, EMAX, ALG>(row, scratch, P0, wmax, wt, ph.nw, kn, wp, snr_out + trial, width_out + trial);
     }
   }
 }
@@ -1341,6 +1349,17 @@ __device__ __forceinline__ uint64_t best_key(float v, int64_t i) {
 }
 
 __global__ void best_init_kernel(unsigned long long* __restrict__ acc) { *acc = 0ull; }
+
+// Output table of a batch, carried in the kernel arguments.
+constexpr int kOutsPerLaunch = 128;
+struct OutsChunk {
+  SeriesOut e[kOutsPerLaunch];
+};
+
+__global__ void set_outs_kernel(OutsChunk c, int32_t n, SeriesOut* __restrict__ dst) {
+  const int i = (int)threadIdx.x;
+  if (i < n) dst[i] = c.e[i];
+}
 
 __global__ __launch_bounds__(256) void best_max_kernel(const float* __restrict__ s, int64_t n,
                                                        unsigned long long* __restrict__ acc) {
@@ -1859,6 +1878,16 @@ hipError_t launch_snr_histogram(const float* snr, int64_t n, float lo, float bin
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   snr_hist_kernel<<<(unsigned)blocks, 1024, (size_t)n_bins * 4, st>>>(
       snr, n, lo, bins_per_unit, n_bins, reinterpret_cast<unsigned long long*>(hist));
+  return hipGetLastError();
+}
+
+hipError_t launch_set_outs(SeriesOut* dst, const SeriesOut* src, int32_t n, hipStream_t st) {
+  for (int32_t i0 = 0; i0 < n; i0 += kOutsPerLaunch) {
+    const int32_t k = std::min<int32_t>(kOutsPerLaunch, n - i0);
+    OutsChunk c{};
+    for (int32_t j = 0; j < k; ++j) c.e[j] = src[i0 + j];
+    set_outs_kernel<<<1, kOutsPerLaunch, 0, st>>>(c, k, dst + i0);
+  }
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 // use on a GPU (device_tables), so plans can be made and inspected without a
 // GPU.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -15,9 +16,6 @@ namespace ffa {
 namespace {
 
 thread_local std::string g_last_error;
-
-// Largest intermediate ring of a plan (bytes); the launches shrink to fit it.
-constexpr int64_t kRingBudget = int64_t(4096) << 20;
 
 int32_t next_pow2(int64_t m) {
   int32_t M = 1;
@@ -76,7 +74,7 @@ int64_t lds_of(const Step& s, int32_t d, bool last, int32_t esz = 4) {
 }
 int32_t esz_of(const Phase& ph) { return ph.u16 ? 2 : 4; }
 
-void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
+void split_passes(Step* s, int64_t lds_budget) {
   s->lds_budget = lds_budget;
   int32_t dfin = 1, dmid = 1;
   auto fits = [&](int32_t d, bool last) { return lds_of(*s, d, last) <= lds_budget; };
@@ -87,16 +85,7 @@ void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
     s->depth[0] = s->L;
     return;
   }
-  if (mode == 0) {  // deepest last pass, the rest shared by the earlier ones
-    const int32_t rest = s->L - dfin;
-    const int32_t np = (rest + dmid - 1) / dmid;
-    for (int32_t i = 0; i < np; ++i) s->depth[i] = rest / np + (i < rest % np ? 1 : 0);
-    s->depth[np] = dfin;
-    s->n_passes = np + 1;
-    return;
-  }
-  // fewest passes, depths as equal as the LDS allows (mode 1: deeper passes
-  // first, mode 2: deeper passes last)
+  // fewest passes, depths as equal as the LDS allows, deeper passes first
   int32_t np = 2;
   for (;; ++np) {
     int32_t left = s->L, ok = 1;
@@ -110,7 +99,6 @@ void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
   }
   int32_t dep[kMaxPasses + 8];
   for (int32_t i = 0; i < np; ++i) dep[i] = s->L / np + (i < s->L % np ? 1 : 0);
-  if (mode == 2) std::reverse(dep, dep + np);
   // respect the caps: move levels from a pass above its cap to others
   for (int iter = 0; iter < 64; ++iter) {
     bool moved = false;
@@ -131,14 +119,6 @@ void split_passes(Step* s, int64_t lds_budget, int32_t mode) {
   }
   for (int32_t i = 0; i < np; ++i) s->depth[i] = dep[i];
   s->n_passes = np;
-}
-
-int64_t env_int(const char* name, int64_t def, int64_t lo, int64_t hi) {
-  if (const char* e = std::getenv(name)) {
-    const long long v = std::strtoll(e, nullptr, 10);
-    if (v >= lo && v <= hi) return v;
-  }
-  return def;
 }
 
 // Ring space a multi-pass step's intermediates take: one M*P0 buffer, two
@@ -211,28 +191,35 @@ std::vector<int32_t> group_steps(const std::vector<Step>& steps, int64_t target,
   return grp;
 }
 
-// Every tile a phase can produce must read and write inside its buffers (the
+}  // namespace
+
+int64_t phase_lds(const Phase& ph) {
+  return (int64_t(1) << ph.depth) * ph.stride * esz_of(ph) + (ph.last ? (int64_t)kScratchBytes : 0);
+}
+
+// Every tile a phase can produce must read and write inside its buffers (its
 // octave series, its step's two intermediate buffers in the ring, its own
 // trials, one workgroup's LDS), and every tile it reads must come from an
-// earlier launch.  Checked once per plan, before anything can be launched.
-bool phases_valid(const ffa_plan_s* p) {
-  const size_t ns = p->steps.size();
+// earlier launch.  Checked once per queue, before anything can be launched.
+bool queue_valid(const std::vector<Step>& steps, const Queue& q, int acc_int) {
+  const size_t ns = steps.size();
   std::vector<int32_t> first_win(ns, -1), last_win(ns, -1);
   std::vector<int32_t> pass_win(ns * kMaxPasses, -1);
   int64_t expect = 0;
   int32_t prev_launch = 0;
-  for (size_t i = 0; i < p->phases.size(); ++i) {
-    const Phase& ph = p->phases[i];
+  for (size_t i = 0; i < q.phases.size(); ++i) {
+    const Phase& ph = q.phases[i];
     if (ph.tile0 != expect || ph.ntiles < 1) return false;
     expect += ph.ntiles;
     if (ph.step < 0 || ph.step >= (int32_t)ns) return false;
-    if (ph.launch < prev_launch || ph.launch >= (int32_t)p->launches.size()) return false;
+    if (ph.launch < prev_launch || ph.launch >= (int32_t)q.launches.size()) return false;
     prev_launch = ph.launch;
-    const Launch& w = p->launches[(size_t)ph.launch];
+    const Launch& w = q.launches[(size_t)ph.launch];
     if (ph.tile0 < w.tile0 || ph.tile0 + ph.ntiles > w.tile0 + w.ntiles) return false;
-    const Step& s = p->steps[ph.step];
+    const Step& s = steps[ph.step];
     const int32_t dp = ph.depth;
     if (ph.pass < 0 || ph.pass >= s.n_passes || dp != s.depth[ph.pass] || dp < 1 || dp > 24) return false;
+    if (ph.series != s.series) return false;
     int32_t D = 0;
     for (int32_t j = 0; j < ph.pass; ++j) D += s.depth[j];
     const bool last = ph.pass == s.n_passes - 1;
@@ -243,32 +230,32 @@ bool phases_valid(const ffa_plan_s* p) {
     if ((int64_t)ph.ntiles != Q * ph.ng || ph.ng < 1 || ph.vin < 1) return false;
     if (ph.halo < std::min<int64_t>(R / 2, s.P0) || ph.halo > s.P0) return false;
     if (ph.stride < s.P0 + ph.halo || (last && ph.stride < s.P0 + s.wmax + 1)) return false;
-    if (ph.u16 && (ph.pass != 0 || last || !p->acc_int || s.octave + dp > 8)) return false;
-    const int64_t lds = R * ph.stride * esz_of(ph) + (last ? (int64_t)kScratchBytes : 0);
+    if (ph.u16 && (ph.pass != 0 || last || !acc_int || s.octave + dp > 8)) return false;
+    const int64_t lds = phase_lds(ph);
     if (lds > (int64_t)kLdsBytes || lds > w.lds_bytes || ph.P0 > w.max_P0) return false;
     if (ph.wofs != s.wofs || ph.nw != s.nw || (last && s.nw < 1)) return false;
     if (s.n_passes > 1 && (s.ring_pos < 0 || s.ring_pos % 64 || (int64_t)ph.ring64 * 64 != s.ring_pos ||
-                           s.ring_pos + ring_region(s) > p->ring_elems || ring_region(s) < MP * (s.n_passes > 2 ? 2 : 1)))
+                           s.ring_pos + ring_region(s) > q.ring_elems || ring_region(s) < MP * (s.n_passes > 2 ? 2 : 1)))
       return false;
     const int64_t Gin = (int64_t)s.M >> D;
     for (int64_t k = 0; k < ph.ntiles; ++k) {
-      if (p->tile_phase[(size_t)(ph.tile0 + k)] != (int32_t)i) return false;
-      const int64_t q = k / ph.ng, h = k % ph.ng;
+      if (q.tile_phase[(size_t)(ph.tile0 + k)] != (int32_t)i) return false;
+      const int64_t qq = k / ph.ng, h = k % ph.ng;
       const int64_t valid = std::min<int64_t>(R, ph.vin - (h << dp));
       if (valid < 1) return false;
-      const int64_t src = (q * Gin + (h << dp)) * s.P0;  // relative to the input buffer
+      const int64_t src = (qq * Gin + (h << dp)) * s.P0;  // relative to the input buffer
       if (ph.pass == 0) {
-        if (ph.oct_off != p->oct_off[s.octave]) return false;
+        if (ph.oct_off != s.oct_off || s.oct_off < 0) return false;
         if (src < 0 || src + valid * s.P0 > (int64_t)s.m * s.P0) return false;
-        if (ph.oct_off + (int64_t)s.m * s.P0 > p->series_elems) return false;
+        if (s.oct_off + (int64_t)s.m * s.P0 > s.in_end) return false;
       } else if (src < 0 || src + valid * s.P0 > MP) {
         return false;
       }
       if (!last) {
         const int64_t Gout = Gin >> dp;
-        const int64_t dst = ((q << dp) * Gout + h) * s.P0;
+        const int64_t dst = ((qq << dp) * Gout + h) * s.P0;
         if (Gout < 1 || dst < 0 || dst + (R - 1) * Gout * s.P0 + s.P0 > MP) return false;
-      } else if ((q << dp) + R > s.M) {
+      } else if ((qq << dp) + R > s.M) {
         return false;
       }
     }
@@ -280,21 +267,21 @@ bool phases_valid(const ffa_plan_s* p) {
     if (ph.pass == 0) first_win[(size_t)ph.step] = ph.launch;
     if (last) last_win[(size_t)ph.step] = ph.launch;
   }
-  if (expect != p->n_tiles || (int64_t)p->tile_phase.size() != p->n_tiles) return false;
+  if (expect != q.n_tiles || (int64_t)q.tile_phase.size() != q.n_tiles) return false;
   // ring: two multi-pass steps whose launches overlap hold disjoint ranges
   std::vector<size_t> multi;
   for (size_t si = 0; si < ns; ++si) {
     if (first_win[si] < 0 || last_win[si] < 0) return false;
-    if (p->steps[si].n_passes > 1) multi.push_back(si);
+    if (steps[si].n_passes > 1) multi.push_back(si);
   }
   std::stable_sort(multi.begin(), multi.end(), [&](size_t a, size_t b) { return first_win[a] < first_win[b]; });
   std::vector<size_t> live;
   for (size_t si : multi) {
-    const Step& s = p->steps[si];
+    const Step& s = steps[si];
     live.erase(std::remove_if(live.begin(), live.end(), [&](size_t o) { return last_win[o] < first_win[si]; }),
                live.end());
     for (size_t o : live) {
-      const Step& t = p->steps[o];
+      const Step& t = steps[o];
       if (s.ring_pos < t.ring_pos + ring_region(t) && t.ring_pos < s.ring_pos + ring_region(s)) return false;
     }
     live.push_back(si);
@@ -302,7 +289,75 @@ bool phases_valid(const ffa_plan_s* p) {
   return true;
 }
 
-}  // namespace
+// Queue order: windows of consecutive step groups (about window_tiles tiles
+// each, within the ring budget), pass p of group g in window g + p, each
+// window one launch per occupancy class.  The previous pass of a step is then
+// always in an earlier window.
+ffa_status build_queue(std::vector<Step>& steps, std::vector<Phase>& nat, const QueueKnobs& kn, Queue* q) {
+  *q = Queue();
+  int64_t tiles_total = 0;
+  for (const Step& s : steps) {
+    tiles_total += s.total_tiles;
+    q->max_passes = std::max(q->max_passes, s.n_passes);
+    q->lds_bytes = std::max(q->lds_bytes, s.lds_bytes);
+    q->max_P0 = std::max(q->max_P0, s.P0);
+  }
+  q->n_tiles = tiles_total;
+  if (tiles_total >= (int64_t(1) << 31)) return fail(FFA_ERR_UNSUPPORTED, "too many tiles in one queue");
+  const std::vector<int32_t> grp =
+      group_steps(steps, kn.window_tiles, kn.ring_bytes / 4, q->max_passes, kn.fixed_steps);
+  q->ring_elems = place_ring(steps, grp, q->max_passes);
+  {
+    int32_t most = 0;
+    for (size_t i0 = 0, i1 = 0; i0 < grp.size(); i0 = i1) {
+      while (i1 < grp.size() && grp[i1] == grp[i0]) ++i1;
+      most = std::max<int32_t>(most, (int32_t)(i1 - i0));
+    }
+    q->lookahead = most;
+  }
+  for (Phase& ph : nat) ph.ring64 = (int32_t)(steps[(size_t)ph.step].ring_pos / 64);
+  // occupancy class: workgroups per CU that the phase's LDS footprint allows
+  auto occ_class = [&](const Phase& ph) {
+    if (!kn.split_occupancy) return (int32_t)0;
+    return (int32_t)std::min<int64_t>(4, (int64_t)kLdsBytes / std::max<int64_t>(phase_lds(ph), 1));
+  };
+  struct Key {
+    int64_t key;  // window
+    int32_t pass, step, cls;
+  };
+  std::vector<Key> order;
+  order.reserve(nat.size());
+  for (size_t i = 0; i < nat.size(); ++i)
+    order.push_back({(int64_t)grp[(size_t)nat[i].step] + nat[i].pass, nat[i].pass, nat[i].step, occ_class(nat[i])});
+  std::stable_sort(order.begin(), order.end(), [](const Key& a, const Key& b) {
+    if (a.key != b.key) return a.key < b.key;  // window
+    if (a.cls != b.cls) return a.cls < b.cls;
+    return a.step != b.step ? a.step < b.step : a.pass < b.pass;
+  });
+  int64_t t0 = 0, cur_win = -1;
+  int32_t cur_cls = -1;
+  q->tile_phase.reserve((size_t)tiles_total);
+  q->phases.reserve(nat.size());
+  for (const Key& k : order) {
+    Phase ph = nat[(size_t)(steps[(size_t)k.step].fold_phase0 + k.pass)];
+    if (k.key != cur_win || k.cls != cur_cls) {
+      q->launches.push_back(Launch{t0, 0, 0, 0});
+      cur_win = k.key;
+      cur_cls = k.cls;
+    }
+    Launch& ln = q->launches.back();
+    ph.launch = (int32_t)(q->launches.size() - 1);
+    ph.tile0 = t0;
+    ln.ntiles += ph.ntiles;
+    ln.lds_bytes = std::max<int32_t>(ln.lds_bytes, (int32_t)phase_lds(ph));
+    ln.max_P0 = std::max(ln.max_P0, ph.P0);
+    const int32_t idx = (int32_t)q->phases.size();
+    q->tile_phase.insert(q->tile_phase.end(), (size_t)ph.ntiles, idx);
+    t0 += ph.ntiles;
+    q->phases.push_back(ph);
+  }
+  return FFA_OK;
+}
 
 ffa_status fail(ffa_status st, const std::string& msg) {
   g_last_error = msg;
@@ -383,6 +438,10 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
 using namespace ffa;
 
 extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
+  return ffa_plan_create_opts(d, nullptr, out);
+}
+
+extern "C" ffa_status ffa_plan_create_opts(const ffa_plan_desc* d, const ffa_plan_opts* opts_in, ffa_plan* out) {
   if (!d || !out) return fail(FFA_ERR_INVALID, "null argument");
   *out = nullptr;
   if (d->N < 2) return fail(FFA_ERR_INVALID, "N must be >= 2");
@@ -403,20 +462,33 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   if (d->dered_stride < 0) return fail(FFA_ERR_INVALID, "dered_stride must be >= 0");
   if (d->dtype == FFA_IN_U8 && d->dered_window == 0 && 255.0 * (double)d->N >= 2147483648.0)
     return fail(FFA_ERR_UNSUPPORTED, "uint8 series longer than (2^31-1)/255 samples");
+  ffa_plan_opts opts{};
+  if (opts_in) opts = *opts_in;
+  if (opts.tile_lds_bytes != 0 && (opts.tile_lds_bytes < 16384 || opts.tile_lds_bytes > (int32_t)kLdsBytes))
+    return fail(FFA_ERR_INVALID, "tile_lds_bytes must be 0 or in [16384, 163840]");
+  if (opts.window_tiles < 0 || opts.window_tiles > (1 << 24))
+    return fail(FFA_ERR_INVALID, "window_tiles must be in [0, 2^24]");
+  if (opts.ring_mb < 0 || opts.ring_mb > (1 << 20)) return fail(FFA_ERR_INVALID, "ring_mb must be in [0, 2^20]");
+  if (opts.steps_per_window < 0 || opts.steps_per_window > 4096)
+    return fail(FFA_ERR_INVALID, "steps_per_window must be in [0, 4096]");
+  if ((opts.no_u16 != 0 && opts.no_u16 != 1) || (opts.no_split_occupancy != 0 && opts.no_split_occupancy != 1))
+    return fail(FFA_ERR_INVALID, "no_u16 and no_split_occupancy must be 0 or 1");
+  if (opts.select_cand < 0 || opts.select_cand > 64) return fail(FFA_ERR_INVALID, "select_cand must be in [0, 64]");
 
   ffa_plan_s* p = new (std::nothrow) ffa_plan_s();
   if (!p) return fail(FFA_ERR_NOMEM, "plan allocation");
+  static std::atomic<uint64_t> next_uid{1};
+  p->uid = next_uid.fetch_add(1);
   p->desc = *d;
   p->user_widths.assign(d->widths, d->widths + d->n_widths);
   p->desc.widths = nullptr;
 
   // LDS per tile: the whole workgroup LDS by default; a smaller budget gives
   // smaller tiles (more passes) at higher occupancy.
-  const int64_t lds_budget = env_int("FFA_TILE_LDS", (int64_t)kLdsBytes, 16384, (int64_t)kLdsBytes);
-  const int32_t split_mode = (int32_t)env_int("FFA_SPLIT_MODE", 1, 0, 2);
+  const int64_t lds_budget = opts.tile_lds_bytes ? (int64_t)opts.tile_lds_bytes : (int64_t)kLdsBytes;
   // 16-bit first passes (uint8 input without dereddening): see below
   const bool int_mode = d->dtype == FFA_IN_U8 && d->dered_window == 0;
-  const bool allow_u16 = int_mode && env_int("FFA_U16", 1, 0, 1) != 0;
+  const bool allow_u16 = int_mode && !opts.no_u16;
 
   // --- steps (octave f = 2^o; P0 in [B, 2B) with pmin <= P0*f*tsamp < pmax)
   const int64_t B = d->bins_min;
@@ -458,7 +530,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
         p->wtab.push_back(w);
         p->sqrtw.push_back(std::sqrt((double)w));
       }
-      split_passes(&s, lds_budget, split_mode);
+      split_passes(&s, lds_budget);
       // A two-pass step whose last pass needs more than half the CU's LDS
       // runs one workgroup per CU there.  For uint8 input the first pass can
       // hold its sums in 16 bits while 255 * 2^(octave + depth) < 2^16; the
@@ -533,13 +605,11 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   p->series_elems = cur;
 
   // --- phases: one per (step, pass), tiles Q * ng
-  struct Key {
-    int64_t key;  // window
-    int32_t pass, step, cls;
-  };
-  std::vector<Key> order;
-  std::vector<Phase> nat;  // natural order: step, then pass
-  int64_t tiles_total = 0;
+  for (Step& s : p->steps) {
+    s.oct_off = p->oct_off[(size_t)s.octave];
+    s.in_end = s.oct_off + p->oct_len[(size_t)s.octave];
+  }
+  std::vector<Phase>& nat = p->nat_phases;  // natural order: step, then pass
   for (int32_t si = 0; si < (int32_t)p->steps.size(); ++si) {
     Step& s = p->steps[si];
     int32_t D = 0;
@@ -557,7 +627,7 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
         return fail(FFA_ERR_UNSUPPORTED, "step too large");
       }
       Phase ph{};
-      ph.oct_off = p->oct_off[s.octave];
+      ph.oct_off = s.oct_off;
       ph.first_trial = s.first_trial;
       ph.ntiles = (int32_t)nt;
       ph.ng = (int32_t)ng;
@@ -575,80 +645,44 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
       ph.wofs = s.wofs;
       ph.nw = s.nw;
       ph.isqrt_ofs = nsq + s.wofs;
+      ph.series = 0;
       s.tiles[pass] = (int32_t)nt;
       s.total_tiles += (int32_t)nt;
-      s.lds_bytes = std::max<int32_t>(s.lds_bytes, (int32_t)lds_of(s, dp, last, esz_of(ph)));
+      s.lds_bytes = std::max<int32_t>(s.lds_bytes, (int32_t)phase_lds(ph));
       nat.push_back(ph);
       D += dp;
     }
-    tiles_total += s.total_tiles;
-    p->max_passes = std::max(p->max_passes, s.n_passes);
-    p->lds_bytes = std::max(p->lds_bytes, s.lds_bytes);
-    p->max_P0 = std::max(p->max_P0, s.P0);
   }
-  p->n_tiles = tiles_total;
-  if (tiles_total >= (int64_t(1) << 31)) {
-    delete p;
-    return fail(FFA_ERR_UNSUPPORTED, "too many tiles in one search");
-  }
-  // Queue order: windows of consecutive step groups (about FFA_WINDOW_TILES
-  // tiles each, within the ring budget FFA_RING_MB), pass p of group g in
-  // window g + p, each window one launch per occupancy class.  The previous
-  // pass of a step is then always in an earlier window.
-  const int64_t target = env_int("FFA_WINDOW_TILES", 32768, 1, 1 << 24);
-  const int64_t budget = env_int("FFA_RING_MB", kRingBudget >> 20, 1, int64_t(1) << 20) << 20;
-  const int64_t fixed = env_int("FFA_LOOKAHEAD", 0, 0, 4096);
-  const std::vector<int32_t> grp = group_steps(p->steps, target, budget / 4, p->max_passes, fixed);
-  p->ring_elems = place_ring(p->steps, grp, p->max_passes);
+  p->knobs.window_tiles = opts.window_tiles ? opts.window_tiles : 32768;
+  p->knobs.ring_bytes = (opts.ring_mb ? (int64_t)opts.ring_mb : 4096) << 20;
+  p->knobs.fixed_steps = opts.steps_per_window;
+  p->knobs.split_occupancy = !opts.no_split_occupancy;
   {
-    int32_t most = 0;
-    for (size_t i0 = 0, i1 = 0; i0 < grp.size(); i0 = i1) {
-      while (i1 < grp.size() && grp[i1] == grp[i0]) ++i1;
-      most = std::max<int32_t>(most, (int32_t)(i1 - i0));
+    Queue q;
+    const ffa_status qs = build_queue(p->steps, nat, p->knobs, &q);
+    if (qs != FFA_OK) {
+      delete p;
+      return qs;
     }
-    p->lookahead = most;  // steps in the largest group
-  }
-  for (Phase& ph : nat) ph.ring64 = (int32_t)(p->steps[(size_t)ph.step].ring_pos / 64);
-  // occupancy class: workgroups per CU that the phase's LDS footprint allows
-  const bool split = env_int("FFA_SPLIT_OCCUPANCY", 1, 0, 1) != 0;
-  auto occ_class = [&](const Phase& ph) {
-    if (!split) return (int32_t)0;
-    const int64_t lds = lds_of(p->steps[ph.step], ph.depth, ph.last != 0, esz_of(ph));
-    return (int32_t)std::min<int64_t>(4, (int64_t)kLdsBytes / std::max<int64_t>(lds, 1));
-  };
-  for (size_t i = 0; i < nat.size(); ++i)
-    order.push_back({(int64_t)grp[(size_t)nat[i].step] + nat[i].pass, nat[i].pass, nat[i].step, occ_class(nat[i])});
-  std::stable_sort(order.begin(), order.end(), [](const Key& a, const Key& b) {
-    if (a.key != b.key) return a.key < b.key;  // window
-    if (a.cls != b.cls) return a.cls < b.cls;
-    return a.step != b.step ? a.step < b.step : a.pass < b.pass;
-  });
-  int64_t t0 = 0, cur_win = -1;
-  int32_t cur_cls = -1;
-  p->tile_phase.reserve((size_t)tiles_total);
-  for (const Key& k : order) {
-    Phase ph = nat[p->steps[k.step].fold_phase0 + k.pass];
-    if (k.key != cur_win || k.cls != cur_cls) {
-      p->launches.push_back(Launch{t0, 0, 0, 0});
-      cur_win = k.key;
-      cur_cls = k.cls;
+    if (!queue_valid(p->steps, q, p->acc_int)) {
+      delete p;
+      return fail(FFA_ERR_INVALID, "internal planning error: a tile reaches outside its buffers");
     }
-    Launch& ln = p->launches.back();
-    ph.launch = (int32_t)(p->launches.size() - 1);
-    ph.tile0 = t0;
-    ln.ntiles += ph.ntiles;
-    ln.lds_bytes = std::max<int32_t>(ln.lds_bytes, (int32_t)lds_of(p->steps[ph.step], ph.depth, ph.last != 0, esz_of(ph)));
-    ln.max_P0 = std::max(ln.max_P0, ph.P0);
-    const int32_t idx = (int32_t)p->phases.size();
-    for (int32_t j = 0; j < ph.ntiles; ++j) p->tile_phase.push_back(idx);
-    t0 += ph.ntiles;
-    p->phases.push_back(ph);
+    p->phases = std::move(q.phases);
+    p->tile_phase = std::move(q.tile_phase);
+    p->launches = std::move(q.launches);
+    p->n_tiles = q.n_tiles;
+    p->ring_elems = q.ring_elems;
+    p->max_passes = q.max_passes;
+    p->lookahead = q.lookahead;
+    p->lds_bytes = q.lds_bytes;
+    p->max_P0 = q.max_P0;
   }
   // fold order: each step's passes in order, tiles counted from the step's start
   for (const Step& s : p->steps) {
     int64_t f0 = 0;
     for (int32_t pass = 0; pass < s.n_passes; ++pass) {
-      Phase ph = nat[s.fold_phase0 + pass];
+      Phase ph = nat[(size_t)(s.fold_phase0 + pass)];
       ph.tile0 = f0;
       ph.launch = pass;
       f0 += ph.ntiles;
@@ -664,13 +698,9 @@ extern "C" ffa_status ffa_plan_create(const ffa_plan_desc* d, ffa_plan* out) {
   p->ws_bytes = (size_t)round_up(
       std::max<int64_t>(p->ring_off + p->ring_elems, p->ring_off + p->sift_elems) * 4,
       (int64_t)kWsAlign);
-  // test knobs: force the selection's fallback paths
-  if (const char* e = std::getenv("FFA_SELECT_ITERS")) p->select_iters = std::max(0, std::atoi(e));
-  if (const char* e = std::getenv("FFA_SELECT_CAND")) p->select_cand = std::min(64, std::max(1, std::atoi(e)));
-  if (!phases_valid(p)) {
-    delete p;
-    return fail(FFA_ERR_INVALID, "internal planning error: a tile reaches outside its buffers");
-  }
+  // the selection's exits (tests force its fallback paths)
+  p->select_iters = opts.select_iters == 0 ? 64 : std::max(0, opts.select_iters);
+  p->select_cand = opts.select_cand == 0 ? 64 : opts.select_cand;
   *out = p;
   return FFA_OK;
 }

@@ -39,10 +39,10 @@ FFA_SNR_ALG2_OFFPULSE = 2
 
 # every symbol include/ffa.h declares
 EXPORTS = (
-    "ffa_plan_create", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
+    "ffa_plan_create", "ffa_plan_create_opts", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
     "ffa_plan_periods", "ffa_prepare", "ffa_search_prepared", "ffa_search", "ffa_fold", "ffa_best",
     "ffa_sift", "ffa_snr_histogram", "ffa_sigma_gauss", "ffa_sigma_threshold", "ffa_batch_workspace",
-    "ffa_search_batch", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
+    "ffa_search_batch", "ffa_batch_create", "ffa_batch_destroy", "ffa_batch_query", "ffa_batch_search", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
     "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
 )
 
@@ -62,6 +62,24 @@ class PlanDesc(ctypes.Structure):
         ("dered_window", ctypes.c_int32),
         ("dered_stride", ctypes.c_int32),
     ]
+
+
+class PlanOpts(ctypes.Structure):
+    """ffa_plan_opts: launch options (zero = default); they never change a result."""
+
+    _fields_ = [
+        ("tile_lds_bytes", ctypes.c_int32),
+        ("window_tiles", ctypes.c_int32),
+        ("ring_mb", ctypes.c_int32),
+        ("steps_per_window", ctypes.c_int32),
+        ("no_u16", ctypes.c_int32),
+        ("no_split_occupancy", ctypes.c_int32),
+        ("select_iters", ctypes.c_int32),
+        ("select_cand", ctypes.c_int32),
+    ]
+
+
+OPT_NAMES = tuple(f[0] for f in PlanOpts._fields_)
 
 
 class SiftParams(ctypes.Structure):
@@ -93,6 +111,7 @@ _sz = ctypes.c_size_t
 _P = ctypes.POINTER
 
 _lib.ffa_plan_create.argtypes = [_P(PlanDesc), _P(_vp)]
+_lib.ffa_plan_create_opts.argtypes = [_P(PlanDesc), _P(PlanOpts), _P(_vp)]
 _lib.ffa_plan_destroy.argtypes = [_vp]
 _lib.ffa_plan_query.argtypes = [_vp, _P(_i64), _P(_i32), _P(_sz)]
 _lib.ffa_plan_step.argtypes = [_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i64)]
@@ -110,6 +129,10 @@ _lib.ffa_sigma_threshold.argtypes = [_P(ctypes.c_uint64), _i32, ctypes.c_float, 
                                      ctypes.c_double, _P(ctypes.c_double)]
 _lib.ffa_batch_workspace.argtypes = [_i32, _P(_vp), _P(_sz)]
 _lib.ffa_search_batch.argtypes = [_i32, _P(_vp), _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
+_lib.ffa_batch_create.argtypes = [_i32, _P(_vp), _P(_vp)]
+_lib.ffa_batch_destroy.argtypes = [_vp]
+_lib.ffa_batch_query.argtypes = [_vp, _P(_sz), _P(_i64), _P(_i32)]
+_lib.ffa_batch_search.argtypes = [_vp, _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
 _lib.ffa_server_create.argtypes = [_sz, _i32, _P(_vp)]
 _lib.ffa_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int, _P(_i64)]
 _lib.ffa_server_wait.argtypes = [_vp, _i64, _i64, _vp, _vp, _P(ctypes.c_double)]
@@ -159,12 +182,23 @@ class StepInfo:
     first_trial: int
 
 
+def plan_opts(opts: dict | None) -> PlanOpts | None:
+    """A PlanOpts from a dict of its field names (None or {}: the defaults)."""
+    if not opts:
+        return None
+    bad = set(opts) - set(OPT_NAMES)
+    if bad:
+        raise ValueError(f"unknown plan options {sorted(bad)}")
+    return PlanOpts(**{k: int(v) for k, v in opts.items()})
+
+
 class Plan:
-    """A search plan (ffa_plan_create).  ``dtype`` is "f32" or "u8"."""
+    """A search plan (ffa_plan_create).  ``dtype`` is "f32" or "u8";
+    ``opts`` a dict of ffa_plan_opts fields (launch options)."""
 
     def __init__(self, N: int, tsamp: float, pmin: float, pmax: float, bins_min: int,
                  widths=None, dtype: str = "f32", snr: int = FFA_SNR_ALG1_MAD, max_octaves: int = 0,
-                 dered_window: int = 0, dered_stride: int = 0):
+                 dered_window: int = 0, dered_stride: int = 0, opts: dict | None = None):
         self._h = _vp()
         w = list(widths) if widths else []
         self._warr = (ctypes.c_int32 * max(len(w), 1))(*w)
@@ -173,7 +207,10 @@ class Plan:
                         n_widths=len(w), bins_min=bins_min, max_octaves=max_octaves,
                         dtype=FFA_IN_U8 if dtype == "u8" else FFA_IN_F32, snr=snr,
                         dered_window=dered_window, dered_stride=dered_stride)
-        _check(_lib.ffa_plan_create(ctypes.byref(desc), ctypes.byref(self._h)), "ffa_plan_create")
+        o = plan_opts(opts)
+        _check(_lib.ffa_plan_create_opts(ctypes.byref(desc), ctypes.byref(o) if o is not None else None,
+                                         ctypes.byref(self._h)), "ffa_plan_create_opts")
+        self.opts = dict(opts or {})
         self.N = N
         self.tsamp = tsamp
         self.dtype = dtype
@@ -184,10 +221,10 @@ class Plan:
         self.n_trials, self.n_steps, self.ws_bytes = nt.value, ns.value, ws.value
 
     @classmethod
-    def from_args(cls, pa, snr: int = FFA_SNR_ALG1_MAD) -> "Plan":
+    def from_args(cls, pa, snr: int = FFA_SNR_ALG1_MAD, opts: dict | None = None) -> "Plan":
         """From a ``synth.PlanArgs``."""
         return cls(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min, pa.widths, pa.dtype, snr,
-                   pa.max_octaves, getattr(pa, "dered_window", 0), getattr(pa, "dered_stride", 0))
+                   pa.max_octaves, getattr(pa, "dered_window", 0), getattr(pa, "dered_stride", 0), opts)
 
     @property
     def handle(self) -> int:
@@ -407,8 +444,7 @@ def batch_workspace_bytes(plans) -> int:
 
 def search_batch(plans, series, ws=None, outs=None, stream=None):
     """ffa_search_batch: periodograms of many series (cuda tensors), one plan
-    each, spread over the library's streams.  Returns a list of (snr, width)
-    tensors."""
+    each, run as one work queue.  Returns a list of (snr, width) tensors."""
     import torch
 
     n = len(plans)
@@ -431,6 +467,71 @@ def search_batch(plans, series, ws=None, outs=None, stream=None):
     wo = (_vp * n)(*[o[1].data_ptr() for o in outs])
     _check(_lib.ffa_search_batch(n, ph, sp, so, wo, base, avail, _stream_ptr(stream)), "ffa_search_batch")
     return outs
+
+
+class Batch:
+    """A planned batch of searches (ffa_batch_create): one work queue over the
+    steps of every series.  The plans must outlive it."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        if not self.plans:
+            raise ValueError("need at least one plan")
+        h = _vp()
+        arr = (_vp * len(self.plans))(*[p.handle for p in self.plans])
+        _check(_lib.ffa_batch_create(len(self.plans), arr, ctypes.byref(h)), "ffa_batch_create")
+        self._h = h
+        ws, nt, nl = _sz(), _i64(), _i32()
+        _check(_lib.ffa_batch_query(self._h, ctypes.byref(ws), ctypes.byref(nt), ctypes.byref(nl)),
+               "ffa_batch_query")
+        self.ws_bytes, self.n_tiles, self.n_launches = ws.value, nt.value, nl.value
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def workspace(self, device=None):
+        import torch
+
+        return torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device or "cuda")
+
+    def outputs(self, device=None):
+        import torch
+
+        dev = device or "cuda"
+        return [(torch.empty(p.n_trials, dtype=torch.float32, device=dev),
+                 torch.empty(p.n_trials, dtype=torch.int32, device=dev)) for p in self.plans]
+
+    def search(self, series, outs=None, ws=None, stream=None):
+        """ffa_batch_search of ``series`` (cuda tensors, one per plan).
+        Returns the list of (snr, width) tensors."""
+        n = len(self.plans)
+        if len(series) != n:
+            raise ValueError("need one series per plan")
+        for p, x in zip(self.plans, series):
+            p._check_series(x)
+        if outs is None:
+            outs = self.outputs(series[0].device)
+        if ws is None:
+            ws = self.workspace(series[0].device)
+        base = Plan._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        sp = (_vp * n)(*[x.data_ptr() for x in series])
+        so = (_vp * n)(*[o[0].data_ptr() for o in outs])
+        wo = (_vp * n)(*[o[1].data_ptr() for o in outs])
+        _check(_lib.ffa_batch_search(self._h, sp, so, wo, base, avail, _stream_ptr(stream)), "ffa_batch_search")
+        return outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.ffa_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
 
 
 class Server:

@@ -1,36 +1,35 @@
-"""Autotuning of a plan's launch knobs, cached per GPU architecture and
+"""Autotuning of a plan's launch options, cached per GPU architecture and
 shape class.
 
-The planner reads four knobs when a plan is created: the LDS budget of a
-tile (``FFA_TILE_LDS``, which sets the pass split and the tile depth), the
-target tiles per window group (``FFA_WINDOW_TILES``), the ring budget
-(``FFA_RING_MB``) and 16-bit first passes for uint8 input (``FFA_U16``).
-None of them changes a periodogram: uint8 searches stay bit-exact and float
-searches agree within rounding.  ``autotune`` times a search of the caller's
-series under each candidate setting and keeps the fastest; ``tuned_plan``
-creates a plan with the cached setting of its shape class (the defaults if
-there is none).
+A setting is a dict of ``ffa_plan_opts`` fields, passed to the planner at
+plan creation: the LDS budget of a tile (``tile_lds_bytes``, which sets the
+pass split and the tile depth, so the rows each workgroup holds), the target
+tiles per window group (``window_tiles``), the ring budget (``ring_mb``) and
+16-bit first passes for uint8 input (``no_u16``).  None of them changes a
+periodogram: uint8 searches stay bit-exact and float searches agree within
+rounding.  ``autotune`` times a search of the caller's series under each
+candidate setting and keeps the fastest; ``tuned_plan`` creates a plan with
+the cached setting of its shape class (the defaults if there is none).
 """
 from __future__ import annotations
 
 import json
 import math
 import os
-from contextlib import contextmanager
 
 from . import ffa
 
-KNOBS = ("FFA_TILE_LDS", "FFA_WINDOW_TILES", "FFA_RING_MB", "FFA_U16")
+KNOBS = ("tile_lds_bytes", "window_tiles", "ring_mb", "no_u16")
 
 # Candidate settings tried by default (the first is the built-in default).
 DEFAULT_CANDIDATES = (
     {},
-    {"FFA_WINDOW_TILES": "65536"},
-    {"FFA_WINDOW_TILES": "16384"},
-    {"FFA_RING_MB": "8192", "FFA_WINDOW_TILES": "65536"},
-    {"FFA_RING_MB": "2048"},
-    {"FFA_TILE_LDS": "131072"},
-    {"FFA_U16": "0"},
+    {"window_tiles": 65536},
+    {"window_tiles": 16384},
+    {"ring_mb": 8192, "window_tiles": 65536},
+    {"ring_mb": 2048},
+    {"tile_lds_bytes": 131072},
+    {"no_u16": 1},
 )
 
 
@@ -54,28 +53,10 @@ def arch_name() -> str:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
 
 
-@contextmanager
-def knobs(setting: dict):
-    """Set the planner's knobs for the plans created inside the block."""
-    saved = {k: os.environ.get(k) for k in KNOBS}
-    try:
-        for k in KNOBS:
-            if k in setting:
-                os.environ[k] = str(setting[k])
-            else:
-                os.environ.pop(k, None)
-        yield
-    finally:
-        for k, v in saved.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
-
-
 def make_plan(pa, setting: dict, snr: int = ffa.FFA_SNR_ALG1_MAD) -> ffa.Plan:
-    with knobs(setting):
-        return ffa.Plan.from_args(pa, snr=snr)
+    """A plan with the launch options of ``setting`` (only KNOBS are taken)."""
+    opts = {k: int(v) for k, v in (setting or {}).items() if k in KNOBS}
+    return ffa.Plan.from_args(pa, snr=snr, opts=opts)
 
 
 def load_cache(path: str | None = None) -> dict:

@@ -73,3 +73,12 @@ def check_profiles(prof_g: np.ndarray, prof_o: np.ndarray, exact: bool) -> float
     rel = (np.abs(prof_g.astype(np.float64) - prof_o) / scale).max()
     assert rel <= PROFILE_RTOL, f"profile relative error {rel}"
     return float(rel)
+
+
+def pulsar_snr(periods, snr, period_s, rel=1e-3):
+    """Largest S/N over the trials whose period lies within a relative
+    ``rel`` of ``period_s`` (an injected pulsar's own peak, wherever the
+    periodogram's maximum is)."""
+    near = np.abs(periods / period_s - 1.0) < rel
+    assert near.any(), period_s
+    return float(np.max(snr[near]))

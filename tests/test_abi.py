@@ -120,21 +120,58 @@ def test_null_arguments_rejected_before_gpu():
 
 
 def test_batch_workspace():
-    """One workspace region per batch stream (at most 4), each the largest
-    plan's workspace; any mix of sample types; an empty batch is refused."""
+    """A batch workspace holds the output table, every series' own region of
+    octave series and one intermediate ring per queue; ffa_batch_workspace
+    equals an explicit batch's size; the batch's queue is walked like a
+    plan's (tile_emu); an empty batch or a null plan is refused."""
+    from tile_emu import check_batch
+
     a = ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, [1, 2], "u8")
     b = ffa.Plan(200000, 1e-3, 0.5, 1.0, 500, [1, 2], "f32")
     ws = ctypes.c_size_t()
     lib = ffa.lib()
-    for plans, regions in (([a], 1), ([a, b], 2), ([a, b, a, b, a, b], 4)):
+    for plans in ([a], [a, b], [a, b, a, b, a, b]):
         arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
         assert lib.ffa_batch_workspace(len(plans), arr, ctypes.byref(ws)) == ffa.FFA_OK
-        region = -(-max(p.ws_bytes for p in plans) // 256) * 256
-        assert ws.value == regions * region
+        bt = ffa.Batch(plans)
+        assert ws.value == bt.ws_bytes
+        assert bt.n_tiles == sum(len(tile_phases(p)) for p in plans)
+        qs = check_batch(bt)
+        assert len(qs) == len({p.dtype for p in plans})
+        bt.close()
     arr = (ctypes.c_void_p * 1)(a.handle)
     assert lib.ffa_batch_workspace(0, arr, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
     assert lib.ffa_batch_workspace(1, None, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
     assert lib.ffa_search_batch(1, arr, None, None, None, None, 0, None) == ffa.FFA_ERR_INVALID
+    arr2 = (ctypes.c_void_p * 2)(a.handle, None)
+    assert lib.ffa_batch_workspace(2, arr2, ctypes.byref(ws)) == ffa.FFA_ERR_INVALID
+
+
+def tile_phases(plan):
+    from tile_emu import layout
+
+    return range(int(layout(plan)["n_tiles"]))
+
+
+def test_batch_of_random_plans_walks_clean():
+    """Batches of random plans (both sample types, both algorithms, tiny ring
+    budgets that make the shared arena wrap) pass the host walk of every
+    tile's reads, writes and launch order."""
+    from tile_emu import check_batch
+
+    g = np.random.default_rng(7)
+    W10 = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+    for rep in range(3):
+        plans = []
+        for i in range(6):
+            N = int(g.choice([20000, 65536, 150000, 300000]))
+            B = int(g.choice([64, 100, 256, 500]))
+            pmin = B * 1e-3 * float(g.uniform(1.0, 1.5))
+            pmax = pmin * float(g.uniform(2.0, 12.0))
+            opts = {"ring_mb": 4, "window_tiles": 500} if rep == 1 else {}
+            plans.append(ffa.Plan(N, 1e-3, pmin, pmax, B, None if i % 3 == 0 else W10,
+                                  "u8" if g.random() < 0.5 else "f32", snr=1 + int(g.random() < 0.3), opts=opts))
+        check_batch(ffa.Batch(plans))
 
 
 def test_server_argument_errors_before_gpu():

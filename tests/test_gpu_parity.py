@@ -37,7 +37,7 @@ def _sample_steps(plan_o, count: int) -> list[int]:
 
 
 def run_case(torch, ffa, oracle, x, N, tsamp, pmin, pmax, B, widths, dtype, steps_max=None,
-             check_fold=0, max_octaves=0, alg=1, dered_window=0, dered_stride=0):
+             check_fold=0, max_octaves=0, alg=1, dered_window=0, dered_stride=0, opts=None):
     # Algorithm 2's variance is summed in a different order than the oracle's,
     # and a dereddened series is real-valued, so both are compared within the
     # float tolerance also for uint8 input.
@@ -45,7 +45,7 @@ def run_case(torch, ffa, oracle, x, N, tsamp, pmin, pmax, B, widths, dtype, step
     print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype} alg{alg} "
           f"dered={dered_window}/{dered_stride}", flush=True)
     plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, snr=alg, max_octaves=max_octaves,
-                    dered_window=dered_window, dered_stride=dered_stride)
+                    dered_window=dered_window, dered_stride=dered_stride, opts=opts)
     W = oracle.dered_default_window(tsamp, pmin, pmax) if dered_window == -1 else dered_window
     xt = torch.from_numpy(x).cuda()
     snr, wid = plan.search(xt)
@@ -208,26 +208,25 @@ def test_best(torch_cuda, ffa):
         assert ffa.best(torch_cuda.from_numpy(v).cuda()) == _first_max(v), v[:8]
 
 
-@pytest.mark.parametrize("knob", [("FFA_SELECT_ITERS", "0"), ("FFA_SELECT_CAND", "1"),
-                                  ("FFA_SELECT_CAND", "8")])
+@pytest.mark.parametrize("knob", [("select_iters", -1), ("select_cand", 1), ("select_cand", 8)])
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
-def test_selection_paths(torch_cuda, ffa, oracle_mod, knob, dtype, monkeypatch):
+def test_selection_paths(torch_cuda, ffa, oracle_mod, knob, dtype):
     """The median/MAD selection's other exits: the full-sort fallback (no
     counting rounds), bisection down to one candidate, and a small in-lane
     select; each must give the same periodogram."""
     from paper_1703_05581_amd import synth
 
-    monkeypatch.setenv(*knob)
+    opts = dict([knob])
     N = 30000
     x = synth.random_series(5 + N, N, dtype)
-    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.2, 0.52, 200, W10, dtype, steps_max=12)
+    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.2, 0.52, 200, W10, dtype, steps_max=12, opts=opts)
     xs = (x // 16 * 16) if dtype == "u8" else np.round(x * 4) / 4  # many ties
     run_case(torch_cuda, ffa, oracle_mod, xs.astype(x.dtype), N, 1e-3, 0.2, 0.52, 200, W10, dtype,
-             steps_max=6)
+             steps_max=6, opts=opts)
 
 
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
-def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype, monkeypatch):
+def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype):
     """The periodogram does not depend on how the queue is cut into launches
     or where the ring places each step: one step per window group, three, a
     4 MB ring with small groups (the arena wraps many times) and the default
@@ -237,15 +236,9 @@ def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype, monkeypatch):
     N = 300000
     x = torch_cuda.from_numpy(synth.random_series(77, N, dtype)).cuda()
     outs = []
-    keys = ("FFA_LOOKAHEAD", "FFA_RING_MB", "FFA_WINDOW_TILES")
-    for env in ({"FFA_LOOKAHEAD": "1"}, {"FFA_LOOKAHEAD": "3"}, {"FFA_RING_MB": "4", "FFA_WINDOW_TILES": "500"}, {}):
-        for k in keys:
-            if k in env:
-                monkeypatch.setenv(k, env[k])
-            else:
-                monkeypatch.delenv(k, raising=False)
-        plan = ffa.Plan(N, 1e-3, 0.2, 2.0, 100, W10, dtype)
-        print("queue", env, flush=True)
+    for opts in ({"steps_per_window": 1}, {"steps_per_window": 3}, {"ring_mb": 4, "window_tiles": 500}, {}):
+        plan = ffa.Plan(N, 1e-3, 0.2, 2.0, 100, W10, dtype, opts=opts)
+        print("queue", opts, flush=True)
         outs.append([t.clone() for t in plan.search(x)])
         torch_cuda.cuda.synchronize()
     for o in outs[1:]:
@@ -291,7 +284,7 @@ def test_alg2_workload2_sampled(torch_cuda, ffa, oracle_mod):
              list(pa.widths), "u8", steps_max=16, alg=2)
 
 
-def test_u16_first_passes_agree(torch_cuda, ffa, monkeypatch):
+def test_u16_first_passes_agree(torch_cuda, ffa):
     """uint8 steps whose first pass keeps 16-bit sums give the same
     periodogram, bit for bit, as with 32-bit rows everywhere."""
     from tile_emu import phases
@@ -302,8 +295,7 @@ def test_u16_first_passes_agree(torch_cuda, ffa, monkeypatch):
     x = torch_cuda.from_numpy(s.data).cuda()
     outs = []
     for flag in ("1", "0"):
-        monkeypatch.setenv("FFA_U16", flag)
-        plan = ffa.Plan.from_args(s.plan)
+        plan = ffa.Plan.from_args(s.plan, opts={"no_u16": 0 if flag == "1" else 1})
         n16 = int(phases(plan)["u16"].sum())
         assert (n16 > 0) == (flag == "1"), n16
         print("u16", flag, "phases", n16, flush=True)

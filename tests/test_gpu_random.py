@@ -51,14 +51,14 @@ def _case(seed, oracle):
 
 
 @pytest.mark.parametrize("seed", range(32))
-def test_random_configuration(torch_cuda, ffa, oracle_mod, monkeypatch, seed):
+def test_random_configuration(torch_cuda, ffa, oracle_mod, seed):
     from paper_1703_05581_amd import synth
 
     c = _case(1000 + seed, oracle_mod)
     print("random case", c, flush=True)
-    monkeypatch.setenv("FFA_TILE_LDS", str(c["lds"]))
     x = synth.random_series(c["seed"], c["N"], c["dtype"])
     if c["dered"] and c["dtype"] == "f32":
         x = (x + 5.0 * np.sin(np.arange(c["N"]) / 900.0)).astype(np.float32)
     run_case(torch_cuda, ffa, oracle_mod, x, c["N"], c["tsamp"], c["pmin"], c["pmax"], c["B"], c["widths"],
-             c["dtype"], steps_max=10, check_fold=1, alg=c["alg"], dered_window=c["dered"])
+             c["dtype"], steps_max=10, check_fold=1, alg=c["alg"], dered_window=c["dered"],
+             opts={"tile_lds_bytes": c["lds"]})

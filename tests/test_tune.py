@@ -1,8 +1,7 @@
-"""The plan autotuner: shape classes, the cache and the knob scope on the
-host, and on the GPU that every candidate setting gives the same periodogram
-(uint8: bit for bit) and that the cached choice is what tuned_plan uses."""
-import os
-
+"""The plan autotuner: shape classes, the cache and the launch options on
+the host, and on the GPU that every candidate setting gives the same
+periodogram (uint8: bit for bit) and that the cached choice is what
+tuned_plan uses."""
 import pytest
 
 from paper_1703_05581_amd import synth, tune
@@ -15,25 +14,27 @@ def test_shape_class_and_cache(tmp_path):
     assert tune.shape_class(synth.plan_args(3)).startswith("f32/alg1/dered/n23/b256/")
     path = str(tmp_path / "cache.json")
     assert tune.load_cache(path) == {}
-    tune.save_cache({"gfx950": {c: {"knobs": {"FFA_WINDOW_TILES": "65536"}, "ms": 1.0}}}, path)
-    assert tune.cached_setting(pa, arch="gfx950", path=path) == {"FFA_WINDOW_TILES": "65536"}
+    tune.save_cache({"gfx950": {c: {"knobs": {"window_tiles": 65536}, "ms": 1.0}}}, path)
+    assert tune.cached_setting(pa, arch="gfx950", path=path) == {"window_tiles": 65536}
     assert tune.cached_setting(synth.plan_args(1), arch="gfx950", path=path) is None
 
 
-def test_knobs_scope_restores_environment(monkeypatch):
-    monkeypatch.setenv("FFA_RING_MB", "1234")
-    monkeypatch.delenv("FFA_WINDOW_TILES", raising=False)
-    with tune.knobs({"FFA_WINDOW_TILES": "77"}):
-        assert os.environ["FFA_WINDOW_TILES"] == "77"
-        assert "FFA_RING_MB" not in os.environ  # a setting names every knob it keeps
-    assert os.environ["FFA_RING_MB"] == "1234"
-    assert "FFA_WINDOW_TILES" not in os.environ
+def test_settings_are_plan_options():
+    """A setting reaches the planner through ffa_plan_opts, not the process
+    environment: two plans made with different settings coexist."""
+    pa = synth.plan_args(2)
+    a = tune.make_plan(pa, {"window_tiles": 500})
+    b = tune.make_plan(pa, {})
+    assert a.opts == {"window_tiles": 500} and b.opts == {}
+    from tile_emu import layout
+
+    assert len(layout(a)["launches"]) > len(layout(b)["launches"])
 
 
 def test_settings_change_the_plan_layout():
     pa = synth.plan_args(2)
     a = tune.make_plan(pa, {})
-    b = tune.make_plan(pa, {"FFA_RING_MB": "2048"})
+    b = tune.make_plan(pa, {"ring_mb": 2048})
     assert a.n_trials == b.n_trials and a.ws_bytes > b.ws_bytes
 
 
@@ -47,7 +48,7 @@ def test_autotune_candidates_agree(tmp_path):
                         dered_window=0, dered_stride=0)
     x = torch.from_numpy(synth.random_series(5, pa.N, "u8")).cuda()
     path = str(tmp_path / "cache.json")
-    cands = ({}, {"FFA_WINDOW_TILES": "500"}, {"FFA_TILE_LDS": "49152", "FFA_RING_MB": "64"}, {"FFA_U16": "0"})
+    cands = ({}, {"window_tiles": 500}, {"tile_lds_bytes": 49152, "ring_mb": 64}, {"no_u16": 1})
     res = tune.autotune(pa, x, candidates=cands, reps=2, path=path)
     print("autotune", res, flush=True)
     assert len(res["trials"]) == len(cands) and res["knobs"] in [dict(c) for c in cands]
