@@ -72,15 +72,15 @@ typedef enum { FFA_SNR_ALG1_MAD = 1, FFA_SNR_ALG2_OFFPULSE = 2 } ffa_snr;
  *              4*pmin in samples (rounded); > 0 = that many samples.  Every
  *              octave series is filtered with the same number of its own
  *              samples, so the window doubles relative to the input with
- *              each downsampling.  The filter: at knots every dered_stride
- *              samples, the median of the window's samples starting
- *              window/2 before the knot (clipped to the series; an even
- *              count takes the mean of the middle two); the baseline is the
- *              linear interpolation between knots (the last knot's median
- *              after it) and is subtracted.  A dereddened search runs in
- *              float32 also for uint8 input.
- *   dered_stride  knot spacing: 0 = window/8 (at least 1); 1 = the plain
- *              per-sample running median.
+ *              each downsampling.  The filter subtracts from each sample the
+ *              median of the window's samples starting window/2 before it
+ *              (clipped to the series; an even count takes the mean of the
+ *              middle two).  A dereddened search runs in float32 also for
+ *              uint8 input.
+ *   dered_stride  0 or 1: that running median at every sample (exact);
+ *              > 1: a faster approximation, the median only at knots every
+ *              dered_stride samples with the baseline interpolated linearly
+ *              between them (the last knot's median after it).
  *
  * Steps: for each octave f = 1, 2, 4, ... and each integer P0 in [B, 2B)
  * with pmin <= P0*f*tsamp < pmax, one FFA execution folds m = floor(N_f/P0)

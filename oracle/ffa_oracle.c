@@ -418,33 +418,107 @@ int32_t oracle_dered_default_window(double tsamp, double pmin, double pmax) {
   return (int32_t)llround(w);
 }
 
-/* Running-median dereddening of one series (Sec. 2.3.1), as read here:
- *   - knots t_c = c*stride, c = 0 .. (n-1)/stride;
- *   - at each knot, the median of the `window` samples starting window/2
- *     before it, clipped to the series (an even count takes the mean of the
- *     two middle values);
- *   - the baseline between two knots is their linear interpolation; after the
- *     last knot it is that knot's median;
- *   - the output is the series minus the baseline.
- * stride = 1 is the plain per-sample running median; stride 0 selects the
- * default window/8 (at least 1).  Returns 0, or -1 on bad arguments. */
+/* Window of the running median at sample i (Sec. 2.3.1, as read here): the
+ * `window` samples starting window/2 before i, clipped to the series. */
+static void dered_window_at(int64_t i, int64_t n, int32_t window, int64_t* lo, int64_t* hi) {
+  int64_t a = i - window / 2, b = a + window;
+  *lo = a < 0 ? 0 : a;
+  *hi = b > n ? n : b;
+}
+
+/* Median of a sorted run of cnt values: the middle one, or the mean of the
+ * two middle ones for an even count. */
+static double sorted_median(const double* v, int64_t cnt) {
+  return cnt % 2 ? v[cnt / 2] : 0.5 * (v[cnt / 2 - 1] + v[cnt / 2]);
+}
+
+/* Exact running median of x: med[i] = median of the window at i, for every
+ * sample.  The window's values are kept sorted while it slides one sample
+ * at a time: the sample that leaves is found by binary search and removed,
+ * the one that enters is inserted in order.  The series is cut into chunks
+ * (in parallel), each starting from a freshly sorted copy of its first
+ * window. */
+static void running_median_f64(const double* x, int64_t n, int32_t window, double* med) {
+  const int64_t chunk = 16384;
+  const int64_t nch = (n + chunk - 1) / chunk;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t c = 0; c < nch; ++c) {
+    const int64_t i0 = c * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+    int64_t lo, hi;
+    dered_window_at(i0, n, window, &lo, &hi);
+    /* room for the window, and for one insertion per sample of the chunk */
+    double* buf = (double*)malloc(sizeof(double) * (size_t)(window + chunk + 1));
+    int64_t cnt = hi - lo;
+    memcpy(buf, x + lo, sizeof(double) * (size_t)cnt);
+    qsort(buf, (size_t)cnt, sizeof(double), cmp_f64);
+    for (int64_t i = i0; i < i1; ++i) {
+      med[i] = sorted_median(buf, cnt);
+      if (i + 1 == i1) break;
+      int64_t lo2, hi2;
+      dered_window_at(i + 1, n, window, &lo2, &hi2);
+      if (lo2 > lo) { /* x[lo] leaves: remove one entry of its value */
+        const double v = x[lo];
+        int64_t a = 0, b = cnt; /* first entry >= v */
+        while (a < b) {
+          int64_t m = (a + b) / 2;
+          if (buf[m] < v) a = m + 1;
+          else b = m;
+        }
+        if (a < cnt) { /* always: x[lo] is in the window */
+          memmove(buf + a, buf + a + 1, sizeof(double) * (size_t)(cnt - a - 1));
+          --cnt;
+        }
+      }
+      if (hi2 > hi) { /* x[hi] enters: insert it in order */
+        const double v = x[hi];
+        int64_t a = 0, b = cnt; /* first entry > v */
+        while (a < b) {
+          int64_t m = (a + b) / 2;
+          if (buf[m] <= v) a = m + 1;
+          else b = m;
+        }
+        memmove(buf + a + 1, buf + a, sizeof(double) * (size_t)(cnt - a));
+        buf[a] = v;
+        ++cnt;
+      }
+      lo = lo2;
+      hi = hi2;
+    }
+    free(buf);
+  }
+}
+
+/* Running-median dereddening of one series (Sec. 2.3.1: a dynamic running
+ * median filter), as read here:
+ *   - the baseline at sample i is the median of the `window` samples starting
+ *     window/2 before i, clipped to the series (an even count takes the mean
+ *     of the two middle values); the output is the series minus it;
+ *   - stride 0 or 1 is that filter exactly, at every sample;
+ *   - stride > 1 is a cheaper approximation of it: the median only at knots
+ *     t_c = c*stride, c = 0 .. (n-1)/stride, the baseline between two knots
+ *     their linear interpolation, after the last knot that knot's median.
+ * Returns 0, or -1 on bad arguments. */
 int oracle_deredden_f64(const double* x, int64_t n, int32_t window, int32_t stride,
                         double* out) {
   if (n < 1 || window < 1 || stride < 0) return -1;
-  if (stride == 0) stride = window / 8 > 0 ? window / 8 : 1;
+  if (stride <= 1) {
+    double* med = (double*)malloc(sizeof(double) * (size_t)n);
+    running_median_f64(x, n, window, med);
+    for (int64_t i = 0; i < n; ++i) out[i] = x[i] - med[i];
+    free(med);
+    return 0;
+  }
   int64_t nk = (n - 1) / stride + 1;
   double* med = (double*)malloc(sizeof(double) * (size_t)nk);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t c = 0; c < nk; ++c) {
-    int64_t t = c * stride;
-    int64_t lo = t - window / 2, hi = lo + window;
-    if (lo < 0) lo = 0;
-    if (hi > n) hi = n;
+    int64_t lo, hi;
+    dered_window_at(c * stride, n, window, &lo, &hi);
     int64_t cnt = hi - lo;
     double* buf = (double*)malloc(sizeof(double) * (size_t)cnt);
     memcpy(buf, x + lo, sizeof(double) * (size_t)cnt);
     qsort(buf, (size_t)cnt, sizeof(double), cmp_f64);
-    med[c] = cnt % 2 ? buf[cnt / 2] : 0.5 * (buf[cnt / 2 - 1] + buf[cnt / 2]);
+    med[c] = sorted_median(buf, cnt);
     free(buf);
   }
   for (int64_t i = 0; i < n; ++i) {

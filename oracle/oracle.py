@@ -272,7 +272,8 @@ def search(series: np.ndarray, p: Plan, widths=None, alg: int = ALG1, steps=None
 
     ``steps`` selects a subset of step indices; entries of other steps are NaN / -1.
     ``dered_window`` > 0 dereddens every octave series first (window in its
-    own samples; ``dered_stride`` 0 = window/8).
+    own samples; ``dered_stride`` 0 or 1 = the exact running median at every
+    sample, > 1 = medians at knots that far apart, interpolated).
     """
     lib = _load()
     if series.dtype == np.uint8:

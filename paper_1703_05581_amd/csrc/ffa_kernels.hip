@@ -1310,6 +1310,301 @@ __global__ __launch_bounds__(kKnotThreads) void knot_median_kernel(const T* __re
   if (tid == 0) med[c] = m;
 }
 
+// ------------------------------------------- exact running median (stride 1)
+//
+// The median of the window at every sample, in blocks of kRmBlock
+// consecutive outputs per workgroup.  The windows of a block overlap in a
+// core C (the samples every one of them holds); output i's window is C plus
+// at most kRmBlock - 1 fringe samples.  So the rank-k value of window i lies
+// between the core's values of rank k - f_i and k (f_i its fringe count),
+// and every median of the block lies in [v_a, v_b], the core's values of the
+// smallest and largest such ranks.  The union's values in [v_a, v_b] form a
+// small pool, sorted once; output i's median is the value of rank
+// k - below_i among the pool entries inside its window, below_i being the
+// count of its window's values under v_a.  Each selection is exact; blocks
+// whose pool would overflow (many equal values), whose windows share no core
+// (windows shorter than the block) or that are too long to stage in LDS
+// select every output's median directly instead.
+
+constexpr int kRmBlock = 256;     // outputs (and threads) per workgroup
+constexpr int kRmPool = 1024;     // pool entries
+constexpr int kRmStageMax = 16384;  // window values staged in LDS (doubles)
+
+struct RmShared {
+  double pool_v[kRmPool];
+  int32_t pool_p[kRmPool];
+  double cand[kRmBlock];
+  int32_t scanL[kRmBlock], scanR[kRmBlock];
+  int32_t wred[kRmBlock / kWave], wred2[kRmBlock / kWave];
+  int64_t wred64[kRmBlock / kWave];
+  double dred[kRmBlock / kWave];
+  int32_t pool_n, flag;
+  double res;
+};
+
+// Block-wide reductions (every thread returns the result).
+__device__ __forceinline__ int64_t rm_sum(RmShared& sh, int64_t v) {
+  v = wave_sum(v);
+  if (lane_id() == 0) sh.wred64[wave_id()] = v;
+  __syncthreads();
+  int64_t t = 0;
+  for (int w = 0; w < kRmBlock / kWave; ++w) t += sh.wred64[w];
+  __syncthreads();
+  return t;
+}
+__device__ __forceinline__ double rm_min(RmShared& sh, double v) {
+  v = -wave_dmax(-v);
+  if (lane_id() == 0) sh.dred[wave_id()] = v;
+  __syncthreads();
+  double t = sh.dred[0];
+  for (int w = 1; w < kRmBlock / kWave; ++w) t = fmin(t, sh.dred[w]);
+  __syncthreads();
+  return t;
+}
+__device__ __forceinline__ double rm_max(RmShared& sh, double v) {
+  v = wave_dmax(v);
+  if (lane_id() == 0) sh.dred[wave_id()] = v;
+  __syncthreads();
+  double t = sh.dred[0];
+  for (int w = 1; w < kRmBlock / kWave; ++w) t = fmax(t, sh.dred[w]);
+  __syncthreads();
+  return t;
+}
+
+// The rank-r (0-based) value of the `cnt` values get(0 .. cnt-1), exact.  A
+// value bracket [a, b] with count(< a) = ca <= r < count(<= b) = cb is halved
+// until at most kRmBlock values lie in it (or no double lies strictly inside
+// it); those are then ranked directly.  Every thread returns the result.
+template <typename Get>
+__device__ double rm_kth(RmShared& sh, Get get, int64_t cnt, int64_t r) {
+  const int tid = threadIdx.x;
+  double mn = INFINITY, mx = -INFINITY;
+  for (int64_t j = tid; j < cnt; j += kRmBlock) {
+    const double v = get(j);
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  double a = rm_min(sh, mn), b = rm_max(sh, mx);
+  int64_t ca = 0, cb = cnt;
+  for (int it = 0; it < 2200; ++it) {
+    if (a == b) return a;
+    const double mid = a + 0.5 * (b - a);
+    if (cb - ca <= kRmBlock || !(mid > a && mid < b)) {
+      // gather the values in [a, b] and rank them
+      if (tid == 0) sh.pool_n = 0;
+      __syncthreads();
+      for (int64_t j = tid; j < cnt; j += kRmBlock) {
+        const double v = get(j);
+        if (v >= a && v <= b) {
+          const int at = atomicAdd(&sh.pool_n, 1);
+          if (at < kRmBlock) sh.cand[at] = v;
+        }
+      }
+      __syncthreads();
+      const int m = sh.pool_n;
+      if (m <= kRmBlock) {
+        const int64_t want = r - ca;  // rank inside the bracket
+        if (tid < m) {
+          const double v = sh.cand[tid];
+          int less = 0, eq = 0;
+          for (int q = 0; q < m; ++q) {
+            less += sh.cand[q] < v;
+            eq += sh.cand[q] == v;
+          }
+          if (less <= want && want < less + eq) sh.res = v;  // equal values write the same
+        }
+        __syncthreads();
+        const double res = sh.res;
+        __syncthreads();
+        return res;
+      }
+      // more than kRmBlock values, no double strictly between a and b: the
+      // bracket holds only the values a and b
+      __syncthreads();
+      int64_t le = 0;
+      for (int64_t j = tid; j < cnt; j += kRmBlock) le += get(j) <= a;
+      le = rm_sum(sh, le);
+      return le > r ? a : b;
+    }
+    int64_t c = 0;  // count(<= mid)
+    for (int64_t j = tid; j < cnt; j += kRmBlock) c += get(j) <= mid;
+    c = rm_sum(sh, c);
+    if (c > r) {
+      b = mid;
+      cb = c;
+    } else {
+      a = nextafter(mid, INFINITY);
+      ca = c;
+    }
+  }
+  return a;  // not reached: each round narrows the bracket to a finite set of doubles
+}
+
+// One block of outputs: med[i] for i in [blockIdx.x * kRmBlock, ...).
+// use_stage: the launch gave the workgroup LDS for kRmStageMax values.
+template <typename T>
+__global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __restrict__ x, int64_t n,
+                                                                  int32_t window, int use_stage,
+                                                                  double* __restrict__ med) {
+  extern __shared__ __align__(16) unsigned char rm_lds[];
+  RmShared& sh = *reinterpret_cast<RmShared*>(rm_lds);
+  double* stage = reinterpret_cast<double*>(rm_lds + ((sizeof(RmShared) + 15) & ~(size_t)15));
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kRmBlock;
+  const int64_t i1 = i0 + kRmBlock < n ? i0 + kRmBlock : n;
+  const int64_t h = window / 2;
+  auto wlo = [&](int64_t i) { const int64_t v = i - h; return v < 0 ? (int64_t)0 : v; };
+  auto whi = [&](int64_t i) { const int64_t v = i - h + window; return v > n ? n : v; };
+  const int64_t Ulo = wlo(i0), Uhi = whi(i1 - 1);  // the union of the block's windows
+  const int64_t Clo = wlo(i1 - 1), Chi = whi(i0);  // their common core
+  const int64_t nU = Uhi - Ulo;
+  const bool staged = use_stage && nU <= kRmStageMax;
+  if (staged)
+    for (int64_t j = tid; j < nU; j += kRmBlock) stage[j] = (double)x[Ulo + j];
+  __syncthreads();
+  auto val = [&](int64_t pos) -> double { return staged ? stage[pos - Ulo] : (double)x[pos]; };
+  const int64_t i = i0 + tid;
+  const bool live = i < i1;
+  const int64_t lo_i = live ? wlo(i) : 0, hi_i = live ? whi(i) : 1;
+  const int64_t cnt_i = hi_i - lo_i;
+  const int64_t k1 = (cnt_i - 1) / 2, k2 = cnt_i / 2;
+  const int64_t nC = Chi - Clo;
+  bool direct = !staged || nC < 1;
+  double v_a = 0.0, v_b = 0.0;
+  int64_t below = 0;
+  if (!direct) {
+    // ranks of the core that bound every median of the block: the rank-k
+    // value of window i lies between the core's values of rank k - f_i and
+    // k (f_i fringe samples), so [v_a, v_b] below holds every median; with a
+    // rank k - f_i below 0 (a core under half the window) there is no lower
+    // bound, and with k past the core none above
+    const int64_t f_i = cnt_i - nC;
+    const double ra_d = rm_min(sh, live ? (double)(k1 - f_i) : INFINITY);
+    const double rb_d = rm_max(sh, live ? (double)k2 : -INFINITY);
+    auto core = [&](int64_t j) { return stage[Clo - Ulo + j]; };
+    v_a = ra_d >= 0.0 ? rm_kth(sh, core, nC, (int64_t)ra_d) : -INFINITY;
+    v_b = rb_d < (double)nC ? rm_kth(sh, core, nC, (int64_t)rb_d) : INFINITY;
+    // the pool: the union's values in [v_a, v_b]; and the values below v_a
+    if (tid == 0) {
+      sh.pool_n = 0;
+      sh.flag = 0;
+    }
+    __syncthreads();
+    int64_t core_below = 0;
+    for (int64_t j = tid; j < nU; j += kRmBlock) {
+      const double v = stage[j];
+      const int64_t pos = Ulo + j;
+      if (v >= v_a && v <= v_b) {
+        const int at = atomicAdd(&sh.pool_n, 1);
+        if (at < kRmPool) {
+          sh.pool_v[at] = v;
+          sh.pool_p[at] = (int32_t)j;
+        }
+      }
+      if (pos >= Clo && pos < Chi) core_below += v < v_a;
+    }
+    core_below = rm_sum(sh, core_below);
+    // values below v_a in the left fringe [Ulo, Clo) and the right one
+    // [Chi, Uhi), each at most kRmBlock - 1 samples: exclusive prefix counts
+    const int64_t nL = Clo - Ulo, nR = Uhi - Chi;
+    const uint32_t bl = tid < nL ? (stage[tid] < v_a ? 1u : 0u) : 0u;
+    const uint32_t br = tid < nR ? (stage[Chi - Ulo + tid] < v_a ? 1u : 0u) : 0u;
+    const uint32_t sl = wave_scan(bl), sr = wave_scan(br);
+    if (lane_id() == kWave - 1) {
+      sh.wred[wave_id()] = (int32_t)sl;
+      sh.wred2[wave_id()] = (int32_t)sr;
+    }
+    __syncthreads();
+    int32_t baseL = 0, baseR = 0;
+    for (int w = 0; w < wave_id(); ++w) {
+      baseL += sh.wred[w];
+      baseR += sh.wred2[w];
+    }
+    int32_t totalL = 0;
+    for (int w = 0; w < kRmBlock / kWave; ++w) totalL += sh.wred[w];
+    __syncthreads();
+    sh.scanL[tid] = baseL + (int32_t)sl - (int32_t)bl;  // exclusive prefix
+    sh.scanR[tid] = baseR + (int32_t)sr - (int32_t)br;
+    __syncthreads();
+    const int pn = sh.pool_n;
+    if (pn > kRmPool) {
+      direct = true;
+    } else {
+      if (live) {
+        const int64_t left = lo_i < Clo ? (int64_t)(totalL - sh.scanL[lo_i - Ulo]) : 0;
+        const int64_t right = hi_i > Chi ? (int64_t)sh.scanR[hi_i - Chi] : 0;
+        below = core_below + left + right;
+      }
+      // bitonic sort of the pool by (value, position), padded to a power of two
+      int np2 = 1;
+      while (np2 < pn) np2 <<= 1;
+      for (int j = pn + tid; j < np2; j += kRmBlock) {
+        sh.pool_v[j] = INFINITY;
+        sh.pool_p[j] = 0x7fffffff;
+      }
+      __syncthreads();
+      for (int k = 2; k <= np2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+          for (int t = tid; t < np2; t += kRmBlock) {
+            const int u = t ^ jj;
+            if (u > t) {
+              const bool up = (t & k) == 0;
+              const double va = sh.pool_v[t], vb = sh.pool_v[u];
+              const int32_t pa = sh.pool_p[t], pb = sh.pool_p[u];
+              const bool gt = va > vb || (va == vb && pa > pb);
+              if (gt == up) {
+                sh.pool_v[t] = vb;
+                sh.pool_v[u] = va;
+                sh.pool_p[t] = pb;
+                sh.pool_p[u] = pa;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      // walk: the entries inside this output's window, in value order
+      if (live) {
+        const int64_t t1 = k1 - below, t2 = k2 - below;
+        const int32_t plo = (int32_t)(lo_i - Ulo), phi = (int32_t)(hi_i - Ulo);
+        int64_t c = 0;
+        double m1 = 0.0, m2 = 0.0;
+        for (int j = 0; j < pn; ++j) {
+          const int32_t pp = sh.pool_p[j];
+          if (pp >= plo && pp < phi) {
+            if (c == t1) m1 = sh.pool_v[j];
+            if (c == t2) {
+              m2 = sh.pool_v[j];
+              break;
+            }
+            ++c;
+          }
+        }
+        med[i] = (cnt_i % 2) ? m1 : 0.5 * (m1 + m2);
+      }
+    }
+  }
+  if (direct) {
+    // every output of the block selected on its own, cooperatively
+    for (int64_t u = i0; u < i1; ++u) {
+      const int64_t lo = wlo(u), hi = whi(u), c = hi - lo;
+      auto win = [&](int64_t j) { return val(lo + j); };
+      const double m1 = rm_kth(sh, win, c, (c - 1) / 2);
+      const double m = (c % 2) ? m1 : 0.5 * (m1 + rm_kth(sh, win, c, c / 2));
+      if (tid == 0) med[u] = m;
+    }
+  }
+}
+
+// out[i] = x[i] - med[i], in double, rounded once to float32 (`out` may alias
+// `x` for a 4-byte type: each thread reads its element first).
+template <typename T>
+__global__ void median_subtract_kernel(const T* x, int64_t n, const double* __restrict__ med, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = (float)((double)x[i] - med[i]);
+}
+
 // out[i] = x[i] - baseline(i), in double, rounded once to float32.  `out` may
 // alias `x` when both are 4-byte types (each thread reads its element first).
 template <typename T>
@@ -1723,11 +2018,25 @@ hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, i
   if (nk > 0x7fffffff) return hipErrorInvalidValue;
   const int tpb = 256;
   const unsigned gs = (unsigned)((n + tpb - 1) / tpb);
-#define FFA_DERED(TT)                                                                          \
-  do {                                                                                         \
-    const TT* x = reinterpret_cast<const TT*>(w + src_off);                                    \
-    knot_median_kernel<TT><<<(unsigned)nk, kKnotThreads, 0, st>>>(x, n, window, stride, med);  \
-    dered_subtract_kernel<TT><<<gs, tpb, 0, st>>>(x, n, stride, nk, med, out);                 \
+  // exact running median (stride 1): blocks of kRmBlock outputs, the union
+  // of their windows staged in LDS when it fits
+  const int64_t nb = (n + kRmBlock - 1) / kRmBlock;
+  const int64_t stage_n = std::min<int64_t>((int64_t)window + kRmBlock - 1, n);
+  const int use_stage = stage_n <= kRmStageMax ? 1 : 0;
+  const size_t rm_lds = ((sizeof(RmShared) + 15) & ~(size_t)15) + (use_stage ? (size_t)stage_n * sizeof(double) : 0);
+  if (stride == 1 && nb > 0x7fffffff) return hipErrorInvalidValue;
+#define FFA_DERED(TT)                                                                              \
+  do {                                                                                             \
+    const TT* x = reinterpret_cast<const TT*>(w + src_off);                                        \
+    if (stride == 1) {                                                                             \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&running_median_kernel<TT>),         \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);       \
+      running_median_kernel<TT><<<(unsigned)nb, kRmBlock, rm_lds, st>>>(x, n, window, use_stage, med); \
+      median_subtract_kernel<TT><<<gs, tpb, 0, st>>>(x, n, med, out);                              \
+    } else {                                                                                       \
+      knot_median_kernel<TT><<<(unsigned)nk, kKnotThreads, 0, st>>>(x, n, window, stride, med);    \
+      dered_subtract_kernel<TT><<<gs, tpb, 0, st>>>(x, n, stride, nk, med, out);                   \
+    }                                                                                              \
   } while (0)
   if (src_type == 0) FFA_DERED(int32_t);
   else if (src_type == 1) FFA_DERED(float);

@@ -579,7 +579,7 @@ extern "C" ffa_status ffa_plan_create_opts(const ffa_plan_desc* d, const ffa_pla
                                    : std::min(2.0 * d->pmax_s / d->tsamp_s, 4.0 * d->pmin_s / d->tsamp_s);
     w = std::max(1.0, std::min(w, 2147483647.0));
     p->dered_W = (int32_t)std::llround(w);
-    p->dered_stride = d->dered_stride > 0 ? d->dered_stride : std::max(1, p->dered_W / 8);
+    p->dered_stride = d->dered_stride > 1 ? d->dered_stride : 1;  // 0 or 1: the exact running median
   }
   p->acc_int = d->dtype == FFA_IN_U8 && p->dered_W == 0;
   p->dered_oct0 = p->steps.front().octave;

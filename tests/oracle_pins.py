@@ -348,17 +348,34 @@ def pin_dered_ramp(o):
 
 
 def pin_dered_library(o):
-    """Stride 1 is the plain running median: inside the series it equals
-    scipy's median filter (centred window of odd length)."""
+    """The default filter (stride 0, and stride 1) is the plain running
+    median: inside the series it equals scipy's median filter (centred window
+    of odd length)."""
     from scipy.signal import medfilt
 
     g = np.random.default_rng(24)
-    x = g.standard_normal(3000) + np.sin(np.arange(3000) / 150.0) * 3
-    for W in (5, 31, 201):
-        out = o.deredden(x, W, 1)
+    x = g.standard_normal(40000) + np.sin(np.arange(40000) / 150.0) * 3
+    for W in (5, 31, 201, 3001):
         ref = x - medfilt(x, W)
         h = W // 2
-        assert np.abs(out[h:-h] - ref[h:-h]).max() < 1e-12, W
+        for stride in (0, 1):
+            out = o.deredden(x, W, stride)
+            assert np.abs(out[h:-h] - ref[h:-h]).max() < 1e-12, (W, stride)
+
+
+def pin_dered_bruteforce(o):
+    """Every sample, edges included, against numpy's median of its clipped
+    window [i - W/2, i - W/2 + W), for odd and even windows, a window longer
+    than the series, and integer values with many ties."""
+    g = np.random.default_rng(27)
+    for x in (g.standard_normal(700) * 5 + np.arange(700) * 0.01,
+              g.integers(0, 6, 600).astype(np.float64)):
+        n = x.size
+        for W in (1, 2, 7, 64, 65, 300, 2 * n + 3):
+            out = o.deredden(x, W, 0)
+            for i in range(n):
+                lo, hi = max(0, i - W // 2), min(n, i - W // 2 + W)
+                assert out[i] == x[i] - np.median(x[lo:hi]), (W, i)
 
 
 def pin_dered_default_window(o):
@@ -636,6 +653,7 @@ ALL_PINS = [
     pin_alg2_snr_level,
     pin_dered_ramp,
     pin_dered_library,
+    pin_dered_bruteforce,
     pin_dered_default_window,
     pin_dered_offset_and_constant,
     pin_dered_search_recovers,

@@ -33,20 +33,22 @@ def _drift_series(seed, N, dtype, amp=1.0):
     return x.astype(np.float32)
 
 
-# (window, stride): the paper's default, the plain per-sample running median,
-# an odd window with a short stride, an even window, one longer than the series
-WINDOWS = [(-1, 0), (301, 1), (37, 5), (200, 0), (500000, 0)]
+# (window, stride): the paper's default (the exact running median), the same
+# with stride 1, an odd and an even window, windows shorter than the kernel's
+# block of outputs, one too long to stage in LDS, one longer than the series,
+# and the knot approximation with short and long strides
+WINDOWS = [(-1, 0), (301, 1), (200, 0), (37, 0), (2, 0), (20000, 0), (500000, 0), (37, 5), (1001, 125)]
 
 
 @pytest.mark.parametrize("win", WINDOWS, ids=[f"W{w}_s{s}" for w, s in WINDOWS])
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_dered_search_and_fold(torch_cuda, ffa, oracle_mod, win, dtype):
     N = 100000
-    # A window longer than the series removes only a constant (the median of
-    # the whole series), so a swing would stay in the float32 fold, whose
-    # rounding then exceeds the 1e-4 S/N tolerance; that case checks the
-    # clipped window on a series without a swing.
-    x = _drift_series(5 + win[0] % 97, N, dtype, amp=0.0 if win[0] > N else 1.0)
+    # A window as long as the swing's period (or longer than the series)
+    # cannot follow the swing, so most of it would stay in the float32 fold,
+    # whose rounding then exceeds the 1e-4 S/N tolerance; those windows are
+    # checked on a series without a swing.
+    x = _drift_series(5 + win[0] % 97, N, dtype, amp=0.0 if win[0] >= 20000 else 1.0)
     run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.3, 1.5, 150, W10, dtype, steps_max=24,
              check_fold=3, dered_window=win[0], dered_stride=win[1])
 
@@ -71,3 +73,15 @@ def test_dered_recovers_pulsar(torch_cuda, ffa, oracle_mod):
                        "f32", dered_window=-1)
     op = oracle_mod.plan(N, ts, pmin, pmax, B)
     assert abs(op.periods()[summ["best_trial"]] / ts - P) < 0.5
+
+
+def test_dered_many_ties(torch_cuda, ffa, oracle_mod):
+    """uint8 input with only a few distinct values: the running median's
+    candidate pool overflows and every output is selected on its own, still
+    equal to the oracle."""
+    g = np.random.default_rng(31)
+    N = 60000
+    x = (127 + g.integers(0, 3, N)).astype(np.uint8)
+    x[20000:21000] = 200  # a block of one value
+    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.3, 1.2, 150, W10, "u8", steps_max=12,
+             check_fold=2, dered_window=1500, dered_stride=0)

@@ -37,9 +37,13 @@ MUTATIONS = [
      "for (int32_t i = 0; i < n_ex; ++i) if (start + i >= 0 && start + i < P0) excl[start + i] = 1;"),
     ("alg2_last_max", "if (bx[j] > bx[jmax]) jmax = j;", "if (bx[j] >= bx[jmax]) jmax = j;"),
     ("alg2_full_width_noise", "if (cnt > 0 && w < P0) {", "if (cnt > 0) {"),
-    ("dered_window_late", "int64_t lo = t - window / 2, hi = lo + window;", "int64_t lo = t, hi = lo + window;"),
-    ("dered_even_upper", "med[c] = cnt % 2 ? buf[cnt / 2] : 0.5 * (buf[cnt / 2 - 1] + buf[cnt / 2]);",
-     "med[c] = buf[cnt / 2];"),
+    ("dered_window_late", "int64_t a = i - window / 2, b = a + window;", "int64_t a = i, b = a + window;"),
+    ("dered_even_upper", "return cnt % 2 ? v[cnt / 2] : 0.5 * (v[cnt / 2 - 1] + v[cnt / 2]);",
+     "return v[cnt / 2];"),
+    ("dered_remove_largest", "          memmove(buf + a, buf + a + 1, sizeof(double) * (size_t)(cnt - a - 1));",
+     "          (void)a;"),
+    ("dered_enter_previous", "        const double v = x[hi];", "        const double v = x[hi - 1];"),
+    ("dered_no_slide_in", "      if (hi2 > hi) {", "      if (hi2 > hi + 1) {"),
     ("dered_no_interp", "if (c + 1 < nk) b += (med[c + 1] - med[c])", "if (c + 1 < 0) b += (med[c + 1] - med[c])"),
     ("dered_default_2x", "double w4 = 4.0 * pmin / tsamp;", "double w4 = 2.0 * pmin / tsamp;"),
     ("hist_round", "      b = (int32_t)floorf(x);", "      b = (int32_t)roundf(x);"),
