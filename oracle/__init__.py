@@ -1,6 +1,7 @@
 """CPU oracle of the FFA search (test infrastructure only).
 
-Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+Only the test-suite (with its fixture scripts under tests/golden/),
+``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` import this package.  It shares no code with the GPU library.
 """
 from .oracle import (  # noqa: F401
@@ -22,6 +23,7 @@ from .oracle import (  # noqa: F401
     mad_constant,
     plan,
     search,
+    score_profiles,
     sift,
     sigma_gauss,
     sigma_threshold,

@@ -29,11 +29,10 @@
  * Parity status: plan, downsampling, fold and Alg. 1 are pinned by the
  * `-m "not gpu"` tests (worked example, closed forms, invariants, library
  * routines, impulse response, injected-pulse recovery).  Alg. 2 is pinned to
- * its stated readings (window of round(P0/5) boxcar positions starting
- * floor(n_ex/2) before the first maximum, wrapping; population sigma) by
- * hand-worked examples, invariances and the top-hat S/N level; the paper
- * prints no example that fixes those readings, so against the paper itself
- * Alg. 2 is "parity unpinned".
+ * its stated readings by hand-worked examples, invariances and the top-hat
+ * S/N level, and against the paper by its white-noise calibration
+ * (Sec. 4.1.2): both algorithms' 5-sigma S/N on white-noise profiles match
+ * the paper's 6.6 and 7.1.
  */
 #include <math.h>
 #include <stdint.h>
@@ -243,18 +242,25 @@ static double median_f64(const double* v, int32_t n, double* scratch) {
   return 0.5 * (scratch[n / 2 - 1] + scratch[n / 2]);
 }
 
-/* Sum of the w bins starting at j, wrapping around the profile (the profile
- * is one period, so the boxcar is circular). */
-static double box_f64(const double* F, int32_t P0, int32_t j, int32_t w) {
-  double s = 0.0;
-  for (int32_t i = 0; i < w; ++i) s += F[(j + i) % P0];
-  return s;
+/* The circular boxcar of width w: out[j] = sum of the w bins starting at bin
+ * j, wrapping around the profile (the profile is one period), for every j.
+ * Each box is a difference of two running totals of the profile taken
+ * twice over: C[k] = F[0] + ... + F[(k-1) mod P0], box = C[j+w] - C[j]
+ * (exact for integers). */
+static void boxes_f64(const double* F, int32_t P0, int32_t w, double* out) {
+  double* C = (double*)malloc(sizeof(double) * (size_t)(P0 + w + 1));
+  C[0] = 0.0;
+  for (int32_t k = 0; k < P0 + w; ++k) C[k + 1] = C[k] + F[k % P0];
+  for (int32_t j = 0; j < P0; ++j) out[j] = C[j + w] - C[j];
+  free(C);
 }
 
-static int64_t box_i64(const int64_t* F, int32_t P0, int32_t j, int32_t w) {
-  int64_t s = 0;
-  for (int32_t i = 0; i < w; ++i) s += F[(j + i) % P0];
-  return s;
+static void boxes_i64(const int64_t* F, int32_t P0, int32_t w, int64_t* out) {
+  int64_t* C = (int64_t*)malloc(sizeof(int64_t) * (size_t)(P0 + w + 1));
+  C[0] = 0;
+  for (int32_t k = 0; k < P0 + w; ++k) C[k + 1] = C[k] + F[k % P0];
+  for (int32_t j = 0; j < P0; ++j) out[j] = C[j + w] - C[j];
+  free(C);
 }
 
 /* Algorithm 1 (Sec. 2.2.1).  Normalise the profile by its median and K*MAD
@@ -279,14 +285,14 @@ double oracle_alg1_f64(const double* F, int32_t P0, const int32_t* widths,
   double sigma = ORACLE_K * mad;
   double best = 0.0;
   int have = 0;
+  double* bx = (double*)malloc(sizeof(double) * (size_t)P0);
   for (int32_t wi = 0; wi < nw; ++wi) {
     int32_t w = widths[wi];
     if (w < 1 || w > P0) continue;
-    double peak = box_f64(F, P0, 0, w);
-    for (int32_t j = 1; j < P0; ++j) {
-      double s = box_f64(F, P0, j, w);
-      if (s > peak) peak = s;
-    }
+    boxes_f64(F, P0, w, bx);
+    double peak = bx[0];
+    for (int32_t j = 1; j < P0; ++j)
+      if (bx[j] > peak) peak = bx[j];
     double snr = (peak - (double)w * med) / (sigma * sqrt((double)w));
     if (!have || snr > best) {
       best = snr;
@@ -294,6 +300,7 @@ double oracle_alg1_f64(const double* F, int32_t P0, const int32_t* widths,
       have = 1;
     }
   }
+  free(bx);
   return have ? best : 0.0;
 }
 
@@ -323,14 +330,14 @@ double oracle_alg1_i64(const int64_t* F, int32_t P0, const int32_t* widths,
   if (mad4 == 0) return 0.0;
   double best = 0.0;
   int have = 0;
+  int64_t* bx = (int64_t*)malloc(sizeof(int64_t) * (size_t)P0);
   for (int32_t wi = 0; wi < nw; ++wi) {
     int32_t w = widths[wi];
     if (w < 1 || w > P0) continue;
-    int64_t peak = box_i64(F, P0, 0, w);
-    for (int32_t j = 1; j < P0; ++j) {
-      int64_t s = box_i64(F, P0, j, w);
-      if (s > peak) peak = s;
-    }
+    boxes_i64(F, P0, w, bx);
+    int64_t peak = bx[0];
+    for (int32_t j = 1; j < P0; ++j)
+      if (bx[j] > peak) peak = bx[j];
     int64_t num = 2 * (2 * peak - (int64_t)w * med2);
     double den = (ORACLE_K * (double)mad4) * sqrt((double)w);
     double snr = (double)num / den;
@@ -340,58 +347,81 @@ double oracle_alg1_i64(const int64_t* F, int32_t P0, const int32_t* widths,
       have = 1;
     }
   }
+  free(bx);
   return have ? best : 0.0;
 }
 
 /* ------------------------------------------------------ Algorithm 2 (f64) */
 
-/* Algorithm 2 (Sec. 2.2.2).  For each width: boxcar the raw profile, find the
- * maximum I_max, exclude a window of 20% of the profile centred on it, take
- * the mean I_av and standard deviation sigma of the remaining 80%, and score
- * A = (I_max - I_av) / sigma (Eq. 5).  The score is the maximum over widths.
- *
- * Readings (the paper does not fix them): the window is placed in the
- * boxcar-output index space, covers n_ex = round(P0/5) positions starting
- * floor(n_ex/2) before the first maximum, wraps around the profile, and sigma
- * is the population standard deviation.  sigma = 0 gives score 0.  A width
- * equal to P0 makes every boxcar the whole profile: the output is constant,
- * sigma is exactly 0 and so is the score (summing in floating point would
- * leave only rounding noise to divide by).
- * The "Ref" variant of Sec. 2.2.2 / Sec. 2.4 is this with one width. */
+/* Algorithm 2 (Sec. 2.2.2, Eq. 5): the boxcar first, then the off-pulse
+ * statistics.  For each width w:
+ *   - B_w[j] = sum of the w profile bins from bin j (circular), I_max its
+ *     maximum, at the first position j* where it occurs;
+ *   - the on-pulse window: L = max(round(P0/5), w) profile bins centred on
+ *     the box that gave I_max (bins j* .. j*+w-1, centre j* + (w-1)/2), so
+ *     starting at bin j* + floor((w - L)/2), wrapping: 20% of the profile,
+ *     or the box itself where it is wider;
+ *   - I_av and sigma: mean and population standard deviation of the profile
+ *     bins outside the window (the remaining 80%);
+ *   - A_w = (I_max - w*I_av) / (sigma*sqrt(w)): Eq. 5 for the boxcar sum,
+ *     whose off-pulse level is w*I_av and whose noise is sigma*sqrt(w).
+ * A_2 = max over widths (first width on ties); sigma = 0 (a flat off-pulse
+ * region, or no two bins left outside the window) gives 0.
+ * Readings: the paper names the quantities, not the profile they are taken
+ * from, the window's placement or the normalisation of the boxcar.  These
+ * readings reproduce its white-noise calibration (Sec. 4.1.2: a 5-sigma
+ * detection at S/N 7.1), which statistics of the filtered profile do not.
+ * The "Ref" variant of Sec. 2.2.2 and Sec. 2.4 is this with one width. */
+
+/* The on-pulse window of a box of width w at j*: first bin and length. */
+static void alg2_window(int32_t P0, int32_t jstar, int32_t w, int32_t* start, int32_t* len) {
+  const int32_t n_ex = (2 * P0 + 5) / 10; /* round(P0/5) */
+  const int32_t L = w > n_ex ? w : n_ex;
+  int32_t d = w - L; /* <= 0: floor((w - L)/2) */
+  int32_t st = jstar + (d - (d & 1)) / 2;
+  *start = ((st % P0) + P0) % P0;
+  *len = L;
+}
+
 double oracle_alg2_f64(const double* F, int32_t P0, const int32_t* widths,
                        int32_t nw, int32_t* best_w) {
-  double* bx = (double*)malloc(sizeof(double) * (size_t)P0);
   char* excl = (char*)malloc((size_t)P0);
-  int32_t n_ex = (2 * P0 + 5) / 10;
+  double* bx = (double*)malloc(sizeof(double) * (size_t)P0);
   double best = 0.0;
   int have = 0;
   *best_w = 0;
   for (int32_t wi = 0; wi < nw; ++wi) {
     int32_t w = widths[wi];
     if (w < 1 || w > P0) continue;
+    boxes_f64(F, P0, w, bx);
     int32_t jmax = 0;
-    for (int32_t j = 0; j < P0; ++j) {
-      bx[j] = box_f64(F, P0, j, w);
-      if (bx[j] > bx[jmax]) jmax = j;
+    double imax = bx[0];
+    for (int32_t j = 1; j < P0; ++j) {
+      double b = bx[j];
+      if (b > imax) {
+        imax = b;
+        jmax = j;
+      }
     }
+    int32_t start, L;
+    alg2_window(P0, jmax, w, &start, &L);
     memset(excl, 0, (size_t)P0);
-    int32_t start = jmax - n_ex / 2;
-    for (int32_t i = 0; i < n_ex; ++i) excl[((start + i) % P0 + P0) % P0] = 1;
+    for (int32_t i = 0; i < L && i < P0; ++i) excl[(start + i) % P0] = 1;
     double s = 0.0;
     int32_t cnt = 0;
     for (int32_t j = 0; j < P0; ++j)
       if (!excl[j]) {
-        s += bx[j];
+        s += F[j];
         ++cnt;
       }
     double a = 0.0;
-    if (cnt > 0 && w < P0) {
+    if (cnt > 1) {
       double mean = s / cnt;
       double v = 0.0;
       for (int32_t j = 0; j < P0; ++j)
-        if (!excl[j]) v += (bx[j] - mean) * (bx[j] - mean);
+        if (!excl[j]) v += (F[j] - mean) * (F[j] - mean);
       double sd = sqrt(v / cnt);
-      a = sd > 0.0 ? (bx[jmax] - mean) / sd : 0.0;
+      a = sd > 0.0 ? (imax - (double)w * mean) / (sd * sqrt((double)w)) : 0.0;
     }
     if (!have || a > best) {
       best = a;
@@ -399,9 +429,89 @@ double oracle_alg2_f64(const double* F, int32_t P0, const int32_t* widths,
       have = 1;
     }
   }
-  free(bx);
   free(excl);
+  free(bx);
   return have ? best : 0.0;
+}
+
+/* Algorithm 2 on an exact integer profile (uint8 input).  With c kept bins,
+ * s1 their sum and s2 their sum of squares, I_av = s1/c and
+ * sigma = sqrt(c*s2 - s1^2)/c, so
+ *   A_w = (c*I_max - w*s1) / (sqrt(c*s2 - s1^2) * sqrt(w)),
+ * formed from exact integers (each below 2^63 for the sums a plan allows)
+ * and evaluated in double as num / (sqrt(D) * sqrt(w)). */
+double oracle_alg2_i64(const int64_t* F, int32_t P0, const int32_t* widths,
+                       int32_t nw, int32_t* best_w) {
+  char* excl = (char*)malloc((size_t)P0);
+  int64_t* bx = (int64_t*)malloc(sizeof(int64_t) * (size_t)P0);
+  double best = 0.0;
+  int have = 0;
+  *best_w = 0;
+  for (int32_t wi = 0; wi < nw; ++wi) {
+    int32_t w = widths[wi];
+    if (w < 1 || w > P0) continue;
+    boxes_i64(F, P0, w, bx);
+    int32_t jmax = 0;
+    int64_t imax = bx[0];
+    for (int32_t j = 1; j < P0; ++j) {
+      int64_t b = bx[j];
+      if (b > imax) {
+        imax = b;
+        jmax = j;
+      }
+    }
+    int32_t start, L;
+    alg2_window(P0, jmax, w, &start, &L);
+    memset(excl, 0, (size_t)P0);
+    for (int32_t i = 0; i < L && i < P0; ++i) excl[(start + i) % P0] = 1;
+    int64_t s1 = 0, s2 = 0, c = 0;
+    for (int32_t j = 0; j < P0; ++j)
+      if (!excl[j]) {
+        s1 += F[j];
+        s2 += F[j] * F[j];
+        ++c;
+      }
+    double a = 0.0;
+    if (c > 1) {
+      int64_t D = c * s2 - s1 * s1;
+      int64_t num = c * imax - (int64_t)w * s1;
+      a = D > 0 ? (double)num / (sqrt((double)D) * sqrt((double)w)) : 0.0;
+    }
+    if (!have || a > best) {
+      best = a;
+      *best_w = w;
+      have = 1;
+    }
+  }
+  free(excl);
+  free(bx);
+  return have ? best : 0.0;
+}
+
+/* Scores of n profiles of P0 bins each (row-major in `profiles`) with the
+ * given algorithm and widths (NULL/0: the default rule for P0), in parallel
+ * over profiles (threads <= 0: the OpenMP default).  For the false-alarm
+ * statistics of many noise profiles (Sec. 4.1.2). */
+int32_t oracle_default_widths(int32_t P0, int32_t* w);
+int oracle_score_profiles(const double* profiles, int64_t n, int32_t P0, const int32_t* widths,
+                          int32_t nw, int32_t alg, int32_t threads, float* snr) {
+  if (n < 0 || P0 < 1 || (alg != ORACLE_ALG1 && alg != ORACLE_ALG2)) return -1;
+  int32_t wbuf[32];
+  if (!widths || nw <= 0) {
+    nw = oracle_default_widths(P0, wbuf);
+    widths = wbuf;
+  }
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t bw = 0;
+    const double* F = profiles + (size_t)i * (size_t)P0;
+    snr[i] = (float)(alg == ORACLE_ALG1 ? oracle_alg1_f64(F, P0, widths, nw, &bw)
+                                        : oracle_alg2_f64(F, P0, widths, nw, &bw));
+  }
+  return 0;
 }
 
 /* ------------------------------------------------------ dereddening */
@@ -538,11 +648,11 @@ int oracle_deredden_f64(const double* x, int64_t n, int32_t window, int32_t stri
 static double score_profile(const void* prof, int is_int, int32_t P0,
                             const int32_t* widths, int32_t nw, int alg,
                             int32_t* best_w, double* dscratch) {
+  (void)dscratch;
   if (is_int) {
     const int64_t* F = (const int64_t*)prof;
     if (alg == ORACLE_ALG1) return oracle_alg1_i64(F, P0, widths, nw, best_w);
-    for (int32_t j = 0; j < P0; ++j) dscratch[j] = (double)F[j];
-    return oracle_alg2_f64(dscratch, P0, widths, nw, best_w);
+    return oracle_alg2_i64(F, P0, widths, nw, best_w);
   }
   const double* F = (const double*)prof;
   if (alg == ORACLE_ALG1) return oracle_alg1_f64(F, P0, widths, nw, best_w);

@@ -78,8 +78,10 @@ def _configure(lib):
         fn = getattr(lib, name)
         fn.restype = ctypes.c_double
         fn.argtypes = [f64p, ctypes.c_int32, i32p, ctypes.c_int32, i32p]
-    lib.oracle_alg1_i64.restype = ctypes.c_double
-    lib.oracle_alg1_i64.argtypes = [i64p, ctypes.c_int32, i32p, ctypes.c_int32, i32p]
+    for name in ("oracle_alg1_i64", "oracle_alg2_i64"):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_double
+        fn.argtypes = [i64p, ctypes.c_int32, i32p, ctypes.c_int32, i32p]
     lib.oracle_default_widths.restype = ctypes.c_int32
     lib.oracle_default_widths.argtypes = [ctypes.c_int32, i32p]
     lib.oracle_search.restype = ctypes.c_int
@@ -105,6 +107,9 @@ def _configure(lib):
     lib.oracle_snr_histogram.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_float,
                                          ctypes.c_float, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
     lib.oracle_mad_constant.restype = ctypes.c_double
+    lib.oracle_score_profiles.restype = ctypes.c_int
+    lib.oracle_score_profiles.argtypes = [f64p, ctypes.c_int64, ctypes.c_int32, i32p, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]
     return lib
 
 
@@ -242,10 +247,25 @@ def alg1(profile: np.ndarray, widths) -> tuple[float, int]:
     return _score(lib.oracle_alg1_f64, lib.oracle_alg1_i64, profile, widths)
 
 
+def score_profiles(profiles: np.ndarray, alg: int, widths=None, threads: int = 0) -> np.ndarray:
+    """Scores (float32) of the rows of ``profiles`` (n x P0, float64) with
+    Algorithm ``alg``; ``widths`` None = the default rule for P0."""
+    p = np.ascontiguousarray(profiles, dtype=np.float64)
+    n, P0 = p.shape
+    w = np.ascontiguousarray(widths if widths is not None else [], dtype=np.int32)
+    out = np.empty(n, np.float32)
+    rc = _load().oracle_score_profiles(_ptr(p, ctypes.c_double), n, P0,
+                                        _ptr(w, ctypes.c_int32) if w.size else None, w.size, alg, threads,
+                                        _ptr(out, ctypes.c_float))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
 def alg2(profile: np.ndarray, widths) -> tuple[float, int]:
-    """Algorithm 2 score and width of one profile."""
+    """Algorithm 2 score and width of one profile (integer profiles exactly)."""
     lib = _load()
-    return _score(lib.oracle_alg2_f64, None, profile, widths)
+    return _score(lib.oracle_alg2_f64, lib.oracle_alg2_i64, profile, widths)
 
 
 def dered_default_window(tsamp: float, pmin: float, pmax: float) -> int:

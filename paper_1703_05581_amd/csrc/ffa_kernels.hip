@@ -631,22 +631,34 @@ __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int
 }
 
 // Score one folded profile with Algorithm 2 (paper Sec. 2.2.2, Eq. 5): for
-// each width, the circular boxcar B_w of the raw profile, its maximum I_max at
-// the first position j*, and the mean I_av and population sigma of B_w
-// outside a window of n_ex = round(P0/5) positions starting floor(n_ex/2)
-// before j* (wrapping); score = max_w (I_max - I_av) / sigma, the first width
-// on ties, 0 when sigma = 0 (also for w = P0, where the boxcar is constant).  Integer boxes and their sum are exact; the
-// mean, the variance and the score are in double.
+// each width w, the circular boxcar of the profile, its maximum I_max at the
+// first position j*; an on-pulse window of L = max(round(P0/5), w) profile
+// bins centred on that box (starting at j* + floor((w - L)/2), wrapping); the
+// mean I_av and population sigma of the c = P0 - L profile bins outside it
+// (themselves a circular run, taken from the lane's own bins in registers,
+// mean first, then the squared deviations); and
+// A_w = (I_max - w*I_av) / (sigma*sqrt(w)).  Score = max_w A_w, the first
+// width on ties, 0 where sigma = 0.  Integer profiles are scored from exact
+// integers: with s1 and s2 the kept bins' sum and sum of squares,
+// A_w = (c*I_max - w*s1) / (sqrt(c*s2 - s1^2)*sqrt(w)).
 template <int E, bool INT>
 __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, int wmax,
                                            const WidthLanes& wt, int nw, float* snr_out,
                                            int32_t* width_out) {
+  using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
   const int lane = lane_id();
   // Up to 16 boxes per lane are held in registers; longer profiles re-read
   // them from the prefix sums in LDS in each sweep, in a plain loop.
   constexpr bool kRegs = E <= 16;
   constexpr int ER = kRegs ? E : 1;
+  T fv[E];  // the lane's profile bins, kept for the off-pulse statistics
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = r * kWave + lane;
+    fv[r] = (r < kFullRegs<E> || e < P0) ? row[e] : (T)0;
+  }
+  wave_lds_sync();
   A cex[ER];
   {
     A cex_all[E];
@@ -656,15 +668,10 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
       for (int r = 0; r < E; ++r) cex[r] = cex_all[r];
     }
   }
-  const int n_ex = (2 * P0 + 5) / 10;
-  const int cnt = P0 - n_ex;
+  const int n_ex = (2 * P0 + 5) / 10;  // round(P0/5)
   auto key_of = [](A v) -> uint32_t {
     if constexpr (INT) return (uint32_t)v;
     else return fkey(v);
-  };
-  auto as_double = [](A v) -> double {
-    if constexpr (INT) return (double)(uint32_t)v;
-    else return (double)v;
   };
   double best = 0.0;
   int32_t bw = 0;
@@ -675,7 +682,8 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
 #pragma unroll
       for (int r = 0; r < E; ++r) breg[r] = (A)row[r * kWave + lane + w] - cex[r];
     }
-    // f(e, box) for each bin e of this lane, ascending
+    // maximum and its first position
+    uint32_t mk = 0u, jf = 0xffffffffu;
     auto visit = [&](auto&& f) {
       if constexpr (kRegs) {
 #pragma unroll
@@ -685,8 +693,6 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
         for (int e = lane; e < P0; e += kWave) f(e, (A)row[e + w] - (A)row[e]);
       }
     };
-    // maximum and its first position
-    uint32_t mk = 0u, jf = 0xffffffffu;
     visit([&](int e, A b) {
       const uint32_t kv = key_of(b);
       if (kv > mk) {
@@ -696,43 +702,46 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
     });
     const uint32_t pk = wave_umax(mk);
     const int jstar = (int)wave_umin(mk == pk ? jf : 0xffffffffu);
-    int start = jstar - n_ex / 2;
-    start += start < 0 ? P0 : 0;
-    auto kept = [&](int e) {  // (e - start) mod P0 >= n_ex
-      int dj = e - start;
-      dj += dj < 0 ? P0 : 0;
-      return dj >= n_ex;
+    // the on-pulse window [start, start + L) and the kept run after it
+    const int L = w > n_ex ? w : n_ex;
+    int kb = jstar + ((w - L) >> 1) + L;  // start + L, start = j* + floor((w - L)/2)
+    kb += kb < 0 ? P0 : 0;
+    kb -= kb >= P0 ? P0 : 0;
+    const int c = P0 - L;
+    auto kept = [&](int r) {  // bin r*64 + lane is real and outside the window
+      const int e = r * kWave + lane;
+      int d = e - kb;
+      d += d < 0 ? P0 : 0;
+      return (r < kFullRegs<E> || e < P0) && d < c;
     };
-    // One pass over the kept boxes for their mean and population variance,
-    // as sums of d = box - c with c a kept box (the one half a profile from
-    // j*): a flat off-pulse region gives exactly 0, and for integer profiles
-    // the sum of d is exact.
-    const int q = (jstar + P0 / 2) % P0;
-    const A cbox = (A)row[q + w] - (A)row[q];  // the prefix sums give any box
-    double s1, s2 = 0.0;
-    {
-      // for integer profiles every box and d are integers below 2^32, and
-      // their sums below 2^53, so s1 is exact in double
-      // a box inside the window is replaced by c itself, so it adds an
-      // exact 0 to both sums
-      const double cd = as_double(cbox);
-      double t1 = 0.0;
-      visit([&](int e, A b) {
-        const double dv = as_double(kept(e) ? b : cbox) - cd;
-        t1 += dv;
+    double a = 0.0;
+    if constexpr (INT) {
+      int64_t s1 = 0, s2 = 0;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int64_t v = kept(r) ? (int64_t)fv[r] : 0;
+        s1 += v;
+        s2 += v * v;
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      const int64_t D = (int64_t)c * s2 - s1 * s1;
+      const int64_t num = (int64_t)c * (int64_t)pk - (int64_t)w * s1;
+      a = (c > 1 && D > 0) ? (double)num / (sqrt((double)D) * wt.sqrtw(i)) : 0.0;
+    } else if (c > 1) {
+      double s1 = 0.0;
+#pragma unroll
+      for (int r = 0; r < E; ++r) s1 += kept(r) ? (double)fv[r] : 0.0;
+      const double mean = wave_sum(s1) / (double)c;
+      double s2 = 0.0;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const double dv = kept(r) ? (double)fv[r] - mean : 0.0;
         s2 = fma(dv, dv, s2);
-      });
-      wave_sum2(t1, s2, s1, s2);
+      }
+      const double var = wave_sum(s2) / (double)c;
+      a = var > 0.0 ? ((double)fval(pk) - (double)w * mean) / (sqrt(var) * wt.sqrtw(i)) : 0.0;
     }
-    const double mrel = s1 / (double)cnt;  // kept mean - c
-    const double var = (s2 - s1 * mrel) / (double)cnt;
-    const double sd = var > 0.0 ? sqrt(var) : 0.0;
-    double peak;  // relative to c
-    if constexpr (INT) peak = (double)pk - as_double(cbox);
-    else peak = (double)fval(pk) - (double)cbox;
-    const double mean = mrel;
-    // w = P0: every box is the whole profile, so sigma is exactly 0
-    const double a = (sd > 0.0 && w < P0) ? (peak - mean) / sd : 0.0;
     if (i == 0 || a > best) {
       best = a;
       bw = w;

@@ -274,8 +274,10 @@ def pin_default_widths(o):
 
 def pin_alg2_worked_examples(o):
     """Hand-worked Algorithm 2 profiles (Sec. 2.2.2, Eq. 5) that fix the
-    window placement, its wrap-around, its rounding and the population
-    sigma of the stated readings."""
+    off-pulse statistics of the raw profile, the window's placement (floor
+    of the centring, wrap-around, round(P0/5) or the box when wider), the
+    first maximum, the population sigma and the w*I_av and sigma*sqrt(w)
+    scaling of the stated readings; integer profiles score the same."""
     g = _golden("alg2_worked_example.json")
     for case in g["cases"]:
         x = np.array(case["profile"], dtype=np.float64)
@@ -307,8 +309,8 @@ def pin_alg2_invariants(o):
 
 def pin_alg2_sigma_zero(o):
     """A flat off-pulse region has sigma = 0: score 0 by the stated reading.
-    So does a width equal to the profile length, whose boxcar output is the
-    profile total at every position, whatever the profile."""
+    So does a width equal to the profile length, whose window then holds the
+    whole profile, whatever the profile."""
     x = np.full(30, 4.0)
     x[12] = 50.0
     assert o.alg2(x, [1])[0] == 0.0

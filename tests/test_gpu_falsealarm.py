@@ -1,7 +1,8 @@
 """False-alarm statistics (paper Sec. 4.1.2) on the GPU: the S/N histogram
 against the oracle's, bit for bit, through the C ABI; a uint8 noise search
 histogrammed on each side; and the white-noise calibration at full size
-(workload 6, about 10^8 trials per algorithm) against the paper's figures."""
+(workload 6, about 10^8 trials per algorithm) against the paper's figures
+for both algorithms."""
 import numpy as np
 import pytest
 
@@ -99,15 +100,10 @@ def test_null_workload_sampled_steps(torch_cuda, ffa, oracle_mod):
 
 
 def test_null_calibration(torch_cuda, ffa):
-    """All 26 white-noise series with both algorithms: every trial counted,
-    S/N rising with sigma, and for Algorithm 1 the S/N of a 5-sigma detection
-    at the paper's white-noise figure (6.6; measured 6.625).  Algorithm 2's
-    tail depends on the widest boxcar relative to the profile (its sigma comes
-    from the filtered profile, whose off-pulse part holds few independent
-    values when the boxcar is wide): with the paper's width rule it reaches
-    11.5 at 5 sigma, not the paper's 7.1, which this reading matches only with
-    boxcars of at most 8-16 bins.  So Algorithm 2's figure is recorded, not
-    asserted."""
+    """All 26 white-noise series with both algorithms, every trial counted
+    (about 10^8 per algorithm, as in the paper): S/N rising with sigma, and
+    the S/N of a 5-sigma detection at the paper's white-noise figures, 6.6
+    for Algorithm 1 and 7.1 for Algorithm 2 (Sec. 4.1.2), within 0.3."""
     torch = torch_cuda
     from paper_1703_05581_amd import synth
 
@@ -115,6 +111,7 @@ def test_null_calibration(torch_cuda, ffa):
     pa = series[0].plan
     xs = [torch.from_numpy(s.data).cuda() for s in series]
     lo, bpu, nb = -8.0, 256.0, 16384
+    paper = {1: 6.6, 2: 7.1}
     for alg in (1, 2):
         plan = ffa.Plan.from_args(pa, snr=alg)
         outs = ffa.search_batch([plan] * len(xs), xs)
@@ -126,6 +123,5 @@ def test_null_calibration(torch_cuda, ffa):
         t = [ffa.sigma_threshold(hc, lo, bpu, k) for k in (0.0, 1.0, 2.0, 3.0, 4.0, 5.0)]
         print(f"alg{alg}: trials {int(hc.sum())}, S/N at 0..5 sigma {t}", flush=True)
         assert all(a < b for a, b in zip(t, t[1:])), t
-        if alg == 1:
-            assert abs(t[5] - 6.6) < 0.3, t[5]
+        assert abs(t[5] - paper[alg]) <= 0.3, (alg, t[5])
         del outs

@@ -38,10 +38,10 @@ def _sample_steps(plan_o, count: int) -> list[int]:
 
 def run_case(torch, ffa, oracle, x, N, tsamp, pmin, pmax, B, widths, dtype, steps_max=None,
              check_fold=0, max_octaves=0, alg=1, dered_window=0, dered_stride=0, opts=None):
-    # Algorithm 2's variance is summed in a different order than the oracle's,
-    # and a dereddened series is real-valued, so both are compared within the
-    # float tolerance also for uint8 input.
-    exact = dtype == "u8" and alg == 1 and dered_window == 0
+    # uint8 input is folded and scored from exact integers by both
+    # algorithms; a dereddened series is real-valued, so it is compared
+    # within the float tolerance also for uint8 input.
+    exact = dtype == "u8" and dered_window == 0
     print(f"case N={N} tsamp={tsamp} P=[{pmin},{pmax}) B={B} widths={widths} {dtype} alg{alg} "
           f"dered={dered_window}/{dered_stride}", flush=True)
     plan = ffa.Plan(N, tsamp, pmin, pmax, B, widths, dtype, snr=alg, max_octaves=max_octaves,
@@ -256,6 +256,13 @@ def test_alg2_small(torch_cuda, ffa, oracle_mod, case, dtype):
 
     N, tsamp, pmin, pmax, B, widths = case
     x = synth.random_series(11 + N, N, dtype)
+    if dtype == "f32":
+        # A box of nearly the whole profile leaves two or three bins to
+        # estimate sigma from (P0 = 34, w = 32 scores about 1600); float32
+        # profile rounding is then amplified about A^2-fold, past the 1e-4
+        # tolerance.  The paper's width rule stays below 0.4*P0.  uint8
+        # profiles, scored from exact integers, cover those widths bit for bit.
+        widths = [w for w in widths if 2 * w <= B]
     run_case(torch_cuda, ffa, oracle_mod, x, N, tsamp, pmin, pmax, B, widths, dtype,
              steps_max=30, alg=2)
 

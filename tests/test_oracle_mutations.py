@@ -19,8 +19,8 @@ MUTATIONS = [
      "o[j] = A[(size_t)src * P0 + (j + shift) % P0] +                      \\\n                   B[(size_t)src * P0 + j];"),
     ("median_lower", "return 0.5 * (scratch[n / 2 - 1] + scratch[n / 2]);", "return scratch[n / 2];"),
     ("k_rounded", "#define ORACLE_K 1.482602218505602", "#define ORACLE_K 1.4826"),
-    ("box_not_circular", "for (int32_t i = 0; i < w; ++i) s += F[(j + i) % P0];\n  return s;\n}\n\nstatic int64_t",
-     "for (int32_t i = 0; i < w && j + i < P0; ++i) s += F[j + i];\n  return s;\n}\n\nstatic int64_t"),
+    ("box_not_circular", "C[0] = 0.0;\n  for (int32_t k = 0; k < P0 + w; ++k) C[k + 1] = C[k] + F[k % P0];",
+     "C[0] = 0.0;\n  for (int32_t k = 0; k < P0 + w; ++k) C[k + 1] = C[k] + (k < P0 ? F[k] : 0.0);"),
     ("divide_by_width", "double snr = (peak - (double)w * med) / (sigma * sqrt((double)w));",
      "double snr = (peak - (double)w * med) / (sigma * (double)w);"),
     ("mad_about_zero", "for (int32_t j = 0; j < P0; ++j) dev[j] = fabs(F[j] - med);",
@@ -30,13 +30,19 @@ MUTATIONS = [
     ("rows_ceil", "int64_t m = Nf / P0;", "int64_t m = (Nf + P0 - 1) / P0;"),
     ("pad_one_more", "while (M < m) M <<= 1;", "while (M <= m) M <<= 1;"),
     ("default_width_rule", "if (5 * v > P0) break;", "if (5 * v >= P0) break;"),
-    ("alg2_window_late", "int32_t start = jmax - n_ex / 2;", "int32_t start = jmax - n_ex / 2 + 1;"),
+    ("alg2_window_trunc", "int32_t st = jstar + (d - (d & 1)) / 2;", "int32_t st = jstar + d / 2;"),
     ("alg2_sample_sigma", "double sd = sqrt(v / cnt);", "double sd = sqrt(v / (cnt - 1));"),
-    ("alg2_window_floor", "int32_t n_ex = (2 * P0 + 5) / 10;", "int32_t n_ex = P0 / 5;"),
-    ("alg2_window_no_wrap", "for (int32_t i = 0; i < n_ex; ++i) excl[((start + i) % P0 + P0) % P0] = 1;",
-     "for (int32_t i = 0; i < n_ex; ++i) if (start + i >= 0 && start + i < P0) excl[start + i] = 1;"),
-    ("alg2_last_max", "if (bx[j] > bx[jmax]) jmax = j;", "if (bx[j] >= bx[jmax]) jmax = j;"),
-    ("alg2_full_width_noise", "if (cnt > 0 && w < P0) {", "if (cnt > 0) {"),
+    ("alg2_window_floor", "const int32_t n_ex = (2 * P0 + 5) / 10; /* round(P0/5) */",
+     "const int32_t n_ex = P0 / 5;"),
+    ("alg2_window_20pct_only", "const int32_t L = w > n_ex ? w : n_ex;", "const int32_t L = n_ex;"),
+    ("alg2_window_no_wrap", "excl[(start + i) % P0] = 1;\n    double s = 0.0;",
+     "if (start + i < P0) excl[start + i] = 1;\n    double s = 0.0;"),
+    ("alg2_last_max", "double b = bx[j];\n      if (b > imax) {", "double b = bx[j];\n      if (b >= imax) {"),
+    ("alg2_no_sqrt_w", "a = sd > 0.0 ? (imax - (double)w * mean) / (sd * sqrt((double)w)) : 0.0;",
+     "a = sd > 0.0 ? (imax - (double)w * mean) / sd : 0.0;"),
+    ("alg2_level_not_scaled", "a = sd > 0.0 ? (imax - (double)w * mean) / (sd * sqrt((double)w)) : 0.0;",
+     "a = sd > 0.0 ? (imax - mean) / (sd * sqrt((double)w)) : 0.0;"),
+    ("alg2_int_level", "int64_t num = c * imax - (int64_t)w * s1;", "int64_t num = c * imax - s1;"),
     ("dered_window_late", "int64_t a = i - window / 2, b = a + window;", "int64_t a = i, b = a + window;"),
     ("dered_even_upper", "return cnt % 2 ? v[cnt / 2] : 0.5 * (v[cnt / 2 - 1] + v[cnt / 2]);",
      "return v[cnt / 2];"),
