@@ -1,14 +1,18 @@
 """Benchmark of the FFA search on one MI355X.
 
-Workload: one 2^20-sample uint8 series (tsamp 1 ms, N(128, 16^2) noise with
-three pulsars), base periods P0 in [256, 512) bins over octaves f = 1, 2, 4
-(0.256-2.048 s), ten boxcar widths; 768 FFA executions, 1,835,008 trials.
-One step = one search of that series: ffa_prepare (octave downsampling),
-ffa_search_prepared (every FFA butterfly level, Algorithm 1 scoring of every
-folded profile, periodogram written) and ffa_best (best trial), with the
-series already resident in HBM.
+Headline (default): the batched workload -- 256 float32 series of 2^18 to
+2^22 samples (tsamp 0.512 ms), each with its own period range (Pmin 0.2-1 s,
+Pmax 5-30 s), white plus power-law red noise, a pulsar in about 30% of
+them, each dereddened by its plan's exact running median (the paper's
+default window) -- searched as one batch (ffa_batch_prepare +
+ffa_batch_search_prepared: one work queue over every series' steps).  One
+step = one search of all 256 series, inputs resident in HBM.  Beside it:
+the plain path (ffa_search per series, one after another) on the same
+series, with its outputs checked equal; the served stream (Poisson requests
+of 2^20..2^23 float32 samples at 0.7 of the measured capacity, p50/p99);
+and one search of the 2^20-sample uint8 workload.
 
-Metric: trial*samples/s = sum over executions of M*(m*P0) per second.
+Metric: trial*samples/s = sum over FFA executions of M*(m*P0) per second.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one
 GPU.
@@ -38,7 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # form is used), in tera-operations per second.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 KERNEL_SRC = os.path.join(ROOT, "paper_1703_05581_amd", "csrc", "ffa_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ffa_tile_kernel.u8_2e20.traffic.md")
+TRAFFIC_FILES = {"batch256": os.path.join(ROOT, "profiles", "ffa_tile_kernel.batch256_f32.traffic.md"),
+                 "u8_2e20": os.path.join(ROOT, "profiles", "ffa_tile_kernel.u8_2e20.traffic.md")}
 COPY_BYTES = 256 << 20
 
 
@@ -62,12 +67,20 @@ def parse():
                          "dereddened) or 1 (small, launch-bound)")
     ap.add_argument("--alg", type=int, choices=[1, 2], default=1,
                     help="profile score: 1 = Algorithm 1 (the headline), 2 = Algorithm 2")
-    ap.add_argument("--mode", choices=["search", "batch", "served", "null", "graph", "tune"], default="search",
-                    help="search: the headline line (default); batch: batched against plain "
+    ap.add_argument("--mode", choices=["headline", "search", "batch", "served", "null", "graph", "tune"],
+                    default="headline",
+                    help="headline: the batched workload with plain, served and uint8 figures beside it "
+                         "(default); search: one workload's single search; batch: batched against plain "
                          "searches over workload-4 series; served: the request server under "
                          "Poisson arrivals of workload-5 requests")
-    ap.add_argument("--series", type=int, default=32, help="batch: series in the batch")
-    ap.add_argument("--requests", type=int, default=400, help="served: timed requests")
+    ap.add_argument("--series", type=int, default=256, help="headline and batch: series in the batch")
+    ap.add_argument("--plain-steps", type=int, default=3, help="headline: passes timed on the plain path")
+    ap.add_argument("--no-served", action="store_true", help="headline: skip the served stream")
+    ap.add_argument("--no-plain", action="store_true", help="headline: skip the plain path")
+    ap.add_argument("--no-u8", action="store_true", help="headline: skip the uint8 workload")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="headline: CPU time budget of the oracle baseline (whole series, in order)")
+    ap.add_argument("--requests", type=int, default=1000, help="served: timed requests")
     ap.add_argument("--load", type=float, nargs="+", default=[0.7],
                     help="served: offered loads / capacity, run in turn")
     return ap.parse_args()
@@ -80,6 +93,14 @@ WORKLOAD_TEXT = {
     3: "f32 series 2^23 samples (71.6 min at 0.512 ms) with red noise, 0.5-30 s, P0 256..511 at f=2..128, "
        "dereddened with the default 2 s window, 10 widths",
 }
+
+
+def host_threads() -> int:
+    """Host threads this process may use (all of them for the oracle)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def cpu_model() -> str:
@@ -123,11 +144,12 @@ def source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(which: str):
     """HBM bytes per search of the FFA kernel from the committed counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary of a workload, if it was taken on the current kernel source;
+    else None."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(TRAFFIC_FILES[which]).read()
     except OSError:
         return None
     h = re.search(r"^kernel_source_sha256_16: (\w+)", text, re.M)
@@ -364,7 +386,7 @@ def run_null(a) -> dict:
             "paper_5sigma_white_noise": {"alg1": 6.6, "alg2": 7.1}}
 
 
-def run_served(a) -> dict:
+def run_served(a, loads=None) -> dict:
     """Request server under Poisson arrivals at --load x its measured
     capacity; latency = submit to the end of the search on the GPU."""
     import numpy as np
@@ -390,7 +412,7 @@ def run_served(a) -> dict:
     import threading
 
     runs = []
-    for li, load in enumerate(a.load):
+    for li, load in enumerate(loads or a.load):
         rate = load * cap
         arrivals = synth.poisson_arrivals(7 + li, rate, len(reqs))
         lat, done = [], []
@@ -440,28 +462,186 @@ def run_served(a) -> dict:
                                    "P0 256..511 at f=1,2,4; 16 GiB pool, 4 streams"}}
 
 
-def main():
-    a = parse()
-    if a.pmc_summary:
-        pmc_summary(a.pmc_summary, a.searches)
-        return
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(no multi-GPU path is built)"}))
-        sys.exit(2)
-    if a.mode != "search":
-        import torch
+def load_workload4(count: int):
+    """The first ``count`` series of workload 4, generated in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
 
-        torch.cuda.init()
-        fn = {"batch": run_batch, "served": run_served, "null": run_null, "graph": run_graph, "tune": run_tune}[a.mode]
-        print(json.dumps(fn(a)))
-        return
+    from paper_1703_05581_amd import synth
+
+    with ThreadPoolExecutor(max(1, min(16, host_threads()))) as ex:
+        return list(ex.map(synth.workload4, range(count)))
+
+
+def run_headline(a) -> dict:
+    """The batched workload (all 256 series of workload 4 as one batch), the
+    plain path beside it, the served stream and the uint8 workload."""
+    import numpy as np
+    import torch
+
+    from paper_1703_05581_amd import ffa
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    series = load_workload4(a.series)
+    plans = [ffa.Plan.from_args(s.plan) for s in series]
+    xs = [torch.from_numpy(s.data).to(dev) for s in series]
+    gen_s = time.perf_counter() - t_gen
+    batch = ffa.Batch(plans)
+    outs = batch.outputs(dev)
+    ws = batch.workspace(dev)
+    ts, alg_bytes, alg_ops = 0, 0, 0
+    for s, p in zip(series, plans):
+        t, b, o = workload_units(p, False, len(s.plan.widths), 1)
+        ts, alg_bytes, alg_ops = ts + t, alg_bytes + b, alg_ops + o
+    trials = sum(p.n_trials for p in plans)
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        batch.prepare(xs, ws)
+        batch.search_prepared(outs, ws)
+    torch.cuda.synchronize()
+    # e0..e1 brackets the octave series and dereddening of every series,
+    # e1..e2 exactly the FFA kernel launches (and the output table) of a step
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1, e2 in ev:
+        e0.record(stream)
+        batch.prepare(xs, ws)
+        e1.record(stream)
+        batch.search_prepared(outs, ws)
+        e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev[0][0].elapsed_time(ev[-1][2]) / a.steps
+    sec = ms / 1e3
+    kern_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / a.steps
+    prep_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / a.steps
+    ksec = kern_ms / 1e3
+    out = {
+        "metric": "FFA trial*samples/s incl. boxcar S/N (batched vs plain); served p50/p99 latency",
+        "value": ts / sec,
+        "unit": "trial*samples/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded; workload 4 of paper_1703_05581_amd.synth)",
+        "config": {"workload": f"batched: {a.series} f32 series of 2^18..2^22 samples (tsamp 0.512 ms), "
+                               "own period ranges (Pmin 0.2-1 s, Pmax 5-30 s), white + red noise, exact "
+                               "running-median dereddening (default window), 10 widths, Algorithm 1, "
+                               "one batch (ffa_batch_search)",
+                   "series": a.series, "N_total": int(sum(p.N for p in plans)), "trials": int(trials),
+                   "executions": int(sum(p.n_steps for p in plans)), "trial_samples": int(ts),
+                   "batch_tiles": batch.n_tiles, "batch_launches": batch.n_launches},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "ffa_tile_kernel (all launches of one batched search)",
+            "achieved": alg_ops / ksec / 1e12,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": alg_ops / ksec / 1e12 / VALU_PEAK_TOPS,
+            "traffic": stored_traffic("batch256") if a.series == 256 else None,
+            "kernel_ms_per_search": kern_ms,
+        },
+        "prepare_ms_per_search": prep_ms,
+        "hbm": {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / sec / 1e9,
+                "frac_of_8TBs": alg_bytes / sec / 1e9 / HBM_PEAK_GBS},
+        "wall_s": wall,
+        "generate_s": gen_s,
+    }
+    if a.calibrate_copy:  # a plain copy of known size for the byte counters
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if not a.no_plain:
+        wsp = torch.empty(max(p.ws_bytes for p in plans) + 256, dtype=torch.uint8, device=dev)
+        pouts = [(torch.empty(p.n_trials, dtype=torch.float32, device=dev),
+                  torch.empty(p.n_trials, dtype=torch.int32, device=dev)) for p in plans]
+
+        def plain():
+            for p, x, o in zip(plans, xs, pouts):
+                p.search(x, o[0], o[1], wsp)
+
+        plain()
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for _ in range(a.plain_steps):
+            plain()
+        p1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = p0.elapsed_time(p1) / a.plain_steps
+        same = all(torch.equal(o[0], q[0]) and torch.equal(o[1], q[1]) for o, q in zip(outs, pouts))
+        out["plain"] = {"value": ts / (plain_ms / 1e3), "ms_per_step": plain_ms, "steps": a.plain_steps,
+                        "path": "ffa_search per series, one after another on one stream"}
+        out["speedup"] = plain_ms / ms
+        out["outputs_equal_plain"] = bool(same)
+        del wsp, pouts
+    # the oracle on whole series, in order, within the time budget; those
+    # series' GPU periodograms are checked against it on the way
+    if not a.no_cpu_baseline:
+        import oracle
+
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import check_periodogram, step_trials
+
+        threads = host_threads()
+        done, cpu_ts, cpu_s, worst, ok = 0, 0, 0.0, 0.0, True
+        for s, p, o in zip(series, plans, outs):
+            pa = s.plan
+            op = oracle.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
+            W = oracle.dered_default_window(pa.tsamp, pa.pmin, pa.pmax)
+            c0 = time.perf_counter()
+            so, wo = oracle.search(s.data, op, list(pa.widths), alg=1, threads=threads, dered_window=W,
+                                   dered_stride=pa.dered_stride)
+            cpu_s += time.perf_counter() - c0
+            cpu_ts += trial_samples(p)
+            done += 1
+            try:
+                summ = check_periodogram(oracle, s.data, op, list(pa.widths), o[0].cpu().numpy(),
+                                         o[1].cpu().numpy(), so, wo, step_trials(op, range(op.n_steps)),
+                                         exact=False, dered_window=W, dered_stride=pa.dered_stride)
+                worst = max(worst, summ["max_abs_dsnr"])
+            except AssertionError as e:  # reported, not raised: the line must still print
+                ok = False
+                out["check_error"] = str(e)[:300]
+            if cpu_s >= a.cpu_seconds:
+                break
+        out["cpu_baseline"] = {"value": cpu_ts / cpu_s, "unit": "trial*samples/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"series 0..{done - 1} of the {a.series} (whole searches, dereddening "
+                                         f"included), {cpu_ts:.3e} trial*samples in {cpu_s:.1f} s",
+                               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        out["check"] = {"series": done, "trials": int(sum(p.n_trials for p in plans[:done])),
+                        "max_abs_dsnr": worst, "within_tolerance": ok}
+    if not a.no_u8:
+        u8 = run_search(argparse.Namespace(**{**vars(a), "workload": 2, "alg": 1, "check": False}), cpu=False)
+        out["workload2_single_search"] = {
+            "workload": u8["config"]["workload"], "value": u8["value"], "ms_per_step": u8["ms_per_step"],
+            "dtype": "i32", "roofline": u8["roofline"], "hbm": u8["hbm"], "best_trial": u8["best_trial"]}
+    if not a.no_served:
+        srv = run_served(argparse.Namespace(**{**vars(a), "load": [0.7]}), loads=[0.7])
+        out["served"] = {k: srv[k] for k in ("p50_s", "p99_s", "capacity_hz", "requests", "warmup_requests", "config")}
+        out["served"]["served_trial_samples_per_s"] = srv["loads"][0]["served_trial_samples_per_s"]
+        out["served"]["load"] = 0.7
+    return out
+
+
+def run_search(a, cpu: bool = True) -> dict:
+    """One search of one workload per step (prepare, every FFA pass and the
+    scoring, best trial), with the series resident in HBM."""
     import numpy as np
     import torch
 
     from paper_1703_05581_amd import ffa, synth
 
-    torch.cuda.init()
     dev = torch.device("cuda:0")
     series = synth.workload(a.workload, 0)
     pa = series.plan
@@ -500,7 +680,7 @@ def main():
     prep_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / a.steps
     best_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / a.steps
     ksec = kern_ms / 1e3
-    traffic = stored_traffic() if a.workload == 2 and a.alg == 1 else None
+    traffic = stored_traffic("u8_2e20") if a.workload == 2 and a.alg == 1 else None
 
     out = {
         "metric": f"FFA trial*samples/s incl. boxcar S/N (Algorithm {a.alg})",
@@ -561,17 +741,13 @@ def main():
         out["hbm"]["frac_of_copy"] = out["hbm"]["achieved_GBs"] / copy_gbs
         del src, dst
 
-    if a.check or not a.no_cpu_baseline:
+    if a.check or (cpu and not a.no_cpu_baseline):
         import oracle
 
         op = oracle.plan(pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min)
         g = np.random.default_rng(1)
         sel = np.sort(g.choice(op.n_steps, size=min(a.cpu_steps, op.n_steps), replace=False))
-        try:
-            threads = len(os.sched_getaffinity(0))
-        except AttributeError:
-            threads = os.cpu_count() or 1
-        threads = max(1, min(threads, 16))
+        threads = host_threads()
         t0 = time.perf_counter()
         dw = oracle.dered_default_window(pa.tsamp, pa.pmin, pa.pmax) if pa.dered_window == -1 else pa.dered_window
         snr_o, w_o = oracle.search(series.data, op, list(pa.widths), alg=a.alg, steps=sel, threads=threads,
@@ -598,13 +774,34 @@ def main():
             from parity import check_periodogram, step_trials
 
             idx = step_trials(op, sel)
-            exact = a.alg == 1 and pa.dtype == "u8" and not pa.dered_window
+            exact = pa.dtype == "u8" and not pa.dered_window
             summ = check_periodogram(oracle, series.data, op, list(pa.widths), snr.cpu().numpy(),
                                      wid.cpu().numpy(), snr_o, w_o, idx, exact=exact, alg=a.alg,
                                      dered_window=dw, dered_stride=pa.dered_stride)
             out["check"] = (f"{idx.size} trials bit-exact" if exact else
                             f"{idx.size} trials, max |dS/N| {summ['max_abs_dsnr']:.2e}")
-    print(json.dumps(out))
+    return out
+
+
+def torch_init():
+    import torch
+
+    torch.cuda.init()
+
+
+def main():
+    a = parse()
+    if a.pmc_summary:
+        pmc_summary(a.pmc_summary, a.searches)
+        return
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(no multi-GPU path is built)"}))
+        sys.exit(2)
+    torch_init()
+    fn = {"headline": run_headline, "search": run_search, "batch": run_batch, "served": run_served,
+          "null": run_null, "graph": run_graph, "tune": run_tune}[a.mode]
+    print(json.dumps(fn(a)))
 
 
 if __name__ == "__main__":

@@ -321,6 +321,15 @@ ffa_status ffa_batch_destroy(ffa_batch batch);
 ffa_status ffa_batch_query(ffa_batch batch, size_t* ws_bytes, int64_t* n_tiles, int32_t* n_launches);
 ffa_status ffa_batch_search(ffa_batch batch, const void* const* d_series, float* const* d_snr,
                             int32_t* const* d_width, void* d_ws, size_t ws_bytes, void* stream);
+/* ffa_batch_search in two parts, like ffa_prepare and ffa_search_prepared:
+ * the octave series of every series (each in its region of d_ws), then
+ * every FFA pass and the scoring of every profile, reading what the last
+ * ffa_batch_prepare on the same workspace and batch left there.  Same
+ * arguments and errors as ffa_batch_search. */
+ffa_status ffa_batch_prepare(ffa_batch batch, const void* const* d_series, void* d_ws, size_t ws_bytes,
+                             void* stream);
+ffa_status ffa_batch_search_prepared(ffa_batch batch, float* const* d_snr, int32_t* const* d_width,
+                                     void* d_ws, size_t ws_bytes, void* stream);
 ffa_status ffa_batch_workspace(int32_t n, const ffa_plan* plans,
                                size_t* ws_bytes);
 ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,

@@ -724,14 +724,23 @@ int oracle_search(const void* series, int32_t dtype, int64_t N,
   }
   /* dynamic dereddening (Sec. 2.3.1): each octave series, built from the raw
    * one above, is filtered with the same window in its own samples, i.e. a
-   * window that doubles relative to the input with each downsampling */
+   * window that doubles relative to the input with each downsampling (the
+   * octaves below the steps' lowest only feed the halving, so they stay raw) */
   if (dered_window > 0) {
+    int32_t min_oct = max_oct;
+    for (int32_t q = 0; q < (n_sel > 0 && sel ? n_sel : n_steps); ++q) {
+      int32_t s = sel ? sel[q] : q, o = 0;
+      while ((1 << o) < f_arr[s]) ++o;
+      if (o < min_oct) min_oct = o;
+    }
     int64_t ln = N;
     for (int32_t o = 0; o <= max_oct; ++o) {
-      double* tmp = (double*)malloc(sizeof(double) * (size_t)(ln > 0 ? ln : 1));
-      if (ln > 0) oracle_deredden_f64((const double*)oct[o], ln, dered_window, dered_stride, tmp);
-      free(oct[o]);
-      oct[o] = tmp;
+      if (o >= min_oct) {
+        double* tmp = (double*)malloc(sizeof(double) * (size_t)(ln > 0 ? ln : 1));
+        if (ln > 0) oracle_deredden_f64((const double*)oct[o], ln, dered_window, dered_stride, tmp);
+        free(oct[o]);
+        oct[o] = tmp;
+      }
       ln /= 2;
     }
   }

@@ -251,29 +251,48 @@ ffa_status batch_device(ffa_batch_s* b, BatchDev** out) {
   return FFA_OK;
 }
 
-ffa_status run_batch(ffa_batch_s* b, const void* const* d_series, float* const* d_snr, int32_t* const* d_width,
-                     void* d_ws, size_t ws_bytes, hipStream_t st) {
-  if (!d_series || !d_snr || !d_width || !d_ws) return fail(FFA_ERR_INVALID, "null argument");
+ffa_status check_batch_ws(const ffa_batch_s* b, const void* d_ws, size_t ws_bytes) {
+  if (!d_ws) return fail(FFA_ERR_INVALID, "null workspace");
   if (ws_bytes < b->ws_bytes) return fail(FFA_ERR_INVALID, "workspace smaller than the batch's ws_bytes");
   if (reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) return fail(FFA_ERR_INVALID, "workspace not 256-byte aligned");
-  const size_t n = b->plans.size();
-  std::vector<SeriesOut> outs(n);
-  for (size_t i = 0; i < n; ++i) {
-    if (!d_series[i] || !d_snr[i] || !d_width[i]) return fail(FFA_ERR_INVALID, "null series or output");
-    outs[i] = SeriesOut{d_snr[i], d_width[i]};
-  }
-  BatchDev* dev = nullptr;
-  ffa_status s = batch_device(b, &dev);
+  return FFA_OK;
+}
+
+// Every series' octave series (centred float, or exact integer sums), each
+// in its region of the workspace.
+ffa_status prepare_batch(ffa_batch_s* b, const void* const* d_series, void* d_ws, size_t ws_bytes, hipStream_t st) {
+  if (!d_series) return fail(FFA_ERR_INVALID, "null argument");
+  ffa_status s = check_batch_ws(b, d_ws, ws_bytes);
   if (s != FFA_OK) return s;
+  const size_t n = b->plans.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!d_series[i]) return fail(FFA_ERR_INVALID, "null series");
   char* ws = reinterpret_cast<char*>(d_ws);
-  SeriesOut* outs_dev = reinterpret_cast<SeriesOut*>(ws + (size_t)b->outs_off * 4);
-  s = check_hip(launch_set_outs(outs_dev, outs.data(), (int32_t)n, st), "output table kernel");
-  // every series' octave series (centred float, or exact integer sums), each in its region
   for (size_t i = 0; i < n && s == FFA_OK; ++i) {
     const ffa_plan p = b->plans[i];
     s = build_octaves(p, d_series[i], ws + (size_t)b->series_base[i] * 4, p->n_octaves - 1, 1, st);
   }
-  // the queues, window by window
+  return s;
+}
+
+// The queues, window by window, on the octave series already in the workspace.
+ffa_status search_prepared_batch(ffa_batch_s* b, float* const* d_snr, int32_t* const* d_width, void* d_ws,
+                                 size_t ws_bytes, hipStream_t st) {
+  if (!d_snr || !d_width) return fail(FFA_ERR_INVALID, "null argument");
+  ffa_status s = check_batch_ws(b, d_ws, ws_bytes);
+  if (s != FFA_OK) return s;
+  const size_t n = b->plans.size();
+  std::vector<SeriesOut> outs(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!d_snr[i] || !d_width[i]) return fail(FFA_ERR_INVALID, "null output");
+    outs[i] = SeriesOut{d_snr[i], d_width[i]};
+  }
+  BatchDev* dev = nullptr;
+  s = batch_device(b, &dev);
+  if (s != FFA_OK) return s;
+  char* ws = reinterpret_cast<char*>(d_ws);
+  SeriesOut* outs_dev = reinterpret_cast<SeriesOut*>(ws + (size_t)b->outs_off * 4);
+  s = check_hip(launch_set_outs(outs_dev, outs.data(), (int32_t)n, st), "output table kernel");
   for (size_t c = 0; c < b->classes.size() && s == FFA_OK; ++c) {
     const BatchClass& k = b->classes[c];
     const ClassDev& cd = dev->cls[c];
@@ -301,6 +320,17 @@ ffa_status run_batch(ffa_batch_s* b, const void* const* d_series, float* const* 
     if (s == FFA_OK) s = e;
   }
   return s;
+}
+
+ffa_status run_batch(ffa_batch_s* b, const void* const* d_series, float* const* d_snr, int32_t* const* d_width,
+                     void* d_ws, size_t ws_bytes, hipStream_t st) {
+  if (!d_series || !d_snr || !d_width) return fail(FFA_ERR_INVALID, "null argument");
+  const size_t n = b->plans.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!d_series[i] || !d_snr[i] || !d_width[i]) return fail(FFA_ERR_INVALID, "null series or output");
+  ffa_status s = prepare_batch(b, d_series, d_ws, ws_bytes, st);
+  if (s != FFA_OK) return s;
+  return search_prepared_batch(b, d_snr, d_width, d_ws, ws_bytes, st);
 }
 
 // Batches made by ffa_search_batch / ffa_batch_workspace, kept for reuse:
@@ -372,6 +402,18 @@ extern "C" ffa_status ffa_batch_search(ffa_batch b, const void* const* d_series,
                                        int32_t* const* d_width, void* d_ws, size_t ws_bytes, void* stream) {
   if (!b) return fail(FFA_ERR_INVALID, "null batch");
   return run_batch(b, d_series, d_snr, d_width, d_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" ffa_status ffa_batch_prepare(ffa_batch b, const void* const* d_series, void* d_ws, size_t ws_bytes,
+                                        void* stream) {
+  if (!b) return fail(FFA_ERR_INVALID, "null batch");
+  return prepare_batch(b, d_series, d_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" ffa_status ffa_batch_search_prepared(ffa_batch b, float* const* d_snr, int32_t* const* d_width, void* d_ws,
+                                                size_t ws_bytes, void* stream) {
+  if (!b) return fail(FFA_ERR_INVALID, "null batch");
+  return search_prepared_batch(b, d_snr, d_width, d_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 extern "C" ffa_status ffa_batch_workspace(int32_t n, const ffa_plan* plans, size_t* ws_bytes) {

@@ -42,7 +42,8 @@ EXPORTS = (
     "ffa_plan_create", "ffa_plan_create_opts", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
     "ffa_plan_periods", "ffa_prepare", "ffa_search_prepared", "ffa_search", "ffa_fold", "ffa_best",
     "ffa_sift", "ffa_snr_histogram", "ffa_sigma_gauss", "ffa_sigma_threshold", "ffa_batch_workspace",
-    "ffa_search_batch", "ffa_batch_create", "ffa_batch_destroy", "ffa_batch_query", "ffa_batch_search", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
+    "ffa_search_batch", "ffa_batch_create", "ffa_batch_destroy", "ffa_batch_query", "ffa_batch_search",
+    "ffa_batch_prepare", "ffa_batch_search_prepared", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
     "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
 )
 
@@ -133,6 +134,8 @@ _lib.ffa_batch_create.argtypes = [_i32, _P(_vp), _P(_vp)]
 _lib.ffa_batch_destroy.argtypes = [_vp]
 _lib.ffa_batch_query.argtypes = [_vp, _P(_sz), _P(_i64), _P(_i32)]
 _lib.ffa_batch_search.argtypes = [_vp, _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
+_lib.ffa_batch_prepare.argtypes = [_vp, _P(_vp), _vp, _sz, _vp]
+_lib.ffa_batch_search_prepared.argtypes = [_vp, _P(_vp), _P(_vp), _vp, _sz, _vp]
 _lib.ffa_server_create.argtypes = [_sz, _i32, _P(_vp)]
 _lib.ffa_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int, _P(_i64)]
 _lib.ffa_server_wait.argtypes = [_vp, _i64, _i64, _vp, _vp, _P(ctypes.c_double)]
@@ -520,6 +523,31 @@ class Batch:
         so = (_vp * n)(*[o[0].data_ptr() for o in outs])
         wo = (_vp * n)(*[o[1].data_ptr() for o in outs])
         _check(_lib.ffa_batch_search(self._h, sp, so, wo, base, avail, _stream_ptr(stream)), "ffa_batch_search")
+        return outs
+
+    def prepare(self, series, ws, stream=None):
+        """ffa_batch_prepare: every series' octave series into ``ws``."""
+        n = len(self.plans)
+        if len(series) != n:
+            raise ValueError("need one series per plan")
+        for p, x in zip(self.plans, series):
+            p._check_series(x)
+        base = Plan._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        sp = (_vp * n)(*[x.data_ptr() for x in series])
+        _check(_lib.ffa_batch_prepare(self._h, sp, base, avail, _stream_ptr(stream)), "ffa_batch_prepare")
+
+    def search_prepared(self, outs, ws, stream=None):
+        """ffa_batch_search_prepared into ``outs`` (as from outputs())."""
+        n = len(self.plans)
+        if len(outs) != n:
+            raise ValueError("need one output pair per plan")
+        base = Plan._aligned(ws)
+        avail = ws.numel() - (base - ws.data_ptr())
+        so = (_vp * n)(*[o[0].data_ptr() for o in outs])
+        wo = (_vp * n)(*[o[1].data_ptr() for o in outs])
+        _check(_lib.ffa_batch_search_prepared(self._h, so, wo, base, avail, _stream_ptr(stream)),
+               "ffa_batch_search_prepared")
         return outs
 
     def close(self) -> None:

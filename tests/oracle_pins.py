@@ -335,6 +335,32 @@ def pin_alg2_snr_level(o):
     assert 0.85 < ratio < 1.2, ratio
 
 
+def pin_white_noise_calibration(o):
+    """Sec. 4.1.2: on white noise a 5-sigma detection is S/N 6.6 for
+    Algorithm 1 and 7.1 for Algorithm 2.  The fixture holds the oracle's
+    S/N at 0..5 sigma_gauss over 5e7 white-noise profiles drawn with the trial
+    weights of that search (written by tests/golden/make_null_calibration.py
+    from the oracle alone); its 5-sigma figures must match the paper's
+    within 0.3.  A fresh draw of 1e5 profiles through the current oracle
+    must reproduce the fixture at 1 and 2 sigma within 0.03, so the fixture
+    is the current oracle's."""
+    g = _golden("null_calibration.json")
+    t1, t2 = g["snr_at_sigma"]["alg1"], g["snr_at_sigma"]["alg2"]
+    assert abs(t1[5] - 6.6) <= 0.3, t1
+    assert abs(t2[5] - 7.1) <= 0.3, t2
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("make_null_calibration",
+                                                  os.path.join(GOLDEN, "make_null_calibration.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    hist = mod.calibrate(100_000, seed=424242)
+    for h, ref in zip(hist, (t1, t2)):
+        now = mod.thresholds(h)
+        for k in (1, 2):
+            assert abs(now[k] - ref[k]) <= 0.03, (k, now, ref)
+
+
 # ------------------------------------------------------- dereddening
 
 def pin_dered_ramp(o):
@@ -653,6 +679,7 @@ ALL_PINS = [
     pin_alg2_invariants,
     pin_alg2_sigma_zero,
     pin_alg2_snr_level,
+    pin_white_noise_calibration,
     pin_dered_ramp,
     pin_dered_library,
     pin_dered_bruteforce,

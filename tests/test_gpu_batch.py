@@ -130,6 +130,13 @@ def test_batch_object_mixed_classes(env):
             s1, w1 = p.search(x)
             torch.cuda.synchronize()
             assert torch.equal(outs[i][0], s1) and torch.equal(outs[i][1], w1), (rep, i, kinds[i])
+    # the same search in two calls (ffa_batch_prepare, ffa_batch_search_prepared)
+    outs2 = b.outputs()
+    b.prepare(xs, ws)
+    b.search_prepared(outs2, ws)
+    torch.cuda.synchronize()
+    for i in range(len(plans)):
+        assert torch.equal(outs2[i][0], outs[i][0]) and torch.equal(outs2[i][1], outs[i][1]), i
     b.close()
 
 
