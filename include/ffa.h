@@ -113,6 +113,11 @@ typedef struct {
 ffa_status ffa_plan_create(const ffa_plan_desc* desc, ffa_plan* out);
 ffa_status ffa_plan_destroy(ffa_plan plan);
 
+/* Makes the plan's device tables on the current GPU now (the first search on
+ * a GPU otherwise makes them).  Errors: FFA_ERR_UNSUPPORTED (a GPU with less
+ * than 160 KiB of LDS per workgroup), FFA_ERR_NOMEM, FFA_ERR_DEVICE. */
+ffa_status ffa_plan_upload(ffa_plan plan);
+
 /* Launch options of a plan.  They change how the work is cut into tiles,
  * passes and launches (and so the speed), never a result: every setting
  * gives the same periodogram, bit for bit.  A zeroed struct selects the
@@ -176,6 +181,20 @@ ffa_status ffa_plan_periods(ffa_plan plan, double* host_periods_s);
 ffa_status ffa_search(ffa_plan plan, const void* d_series, float* d_snr,
                       int32_t* d_width, void* d_ws, size_t ws_bytes,
                       void* stream);
+
+/* ffa_search for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a fixed 64 MiB array the library holds on each GPU for the
+ * life of the process, instead of d_ws, and nothing is allocated.  Every
+ * call on a GPU shares that array, so two calls that overlap on one GPU
+ * race (serialise them, e.g. on one stream); no contents carry over between
+ * calls.  The plan's device tables must already exist on the current GPU
+ * (ffa_plan_upload, or an earlier search).  Results equal ffa_search's.
+ * Errors: FFA_ERR_INVALID (NULL pointer, no device tables on this GPU),
+ * FFA_ERR_UNSUPPORTED (the plan's ws_bytes above 64 MiB: lower its ring_mb),
+ * FFA_ERR_DEVICE. */
+ffa_status ffa_search_noalloc(ffa_plan plan, const void* d_series, float* d_snr,
+                              int32_t* d_width, void* stream);
 
 /* ffa_search in two parts.  ffa_prepare builds the downsampled octave series
  * of `d_series` in the workspace (centred on the mean for float input);

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libffa.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["ffa_kernels.hip", "ffa_plan.cpp", "ffa_capi.cpp", "ffa_batch.cpp", "ffa_server.cpp", "ffa_stats.cpp"]
+SOURCES = ["ffa_kernels.hip", "ffa_plan.cpp", "ffa_capi.cpp", "ffa_batch.cpp", "ffa_server.cpp", "ffa_stats.cpp",
+           "ffa_noalloc.hip"]
 
 # Packed FP32 instructions are kept out of the generated code (-packed-fp32-ops).
 FLAGS = [

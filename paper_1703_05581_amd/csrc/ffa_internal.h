@@ -219,6 +219,9 @@ ffa_status check_hip(hipError_t e, const char* what);
 
 // Device tables of plan p on the current device (creates them on first use).
 ffa_status device_tables(ffa_plan p, const DeviceTables** out);
+// The same tables if they already exist on the current device (allocates
+// nothing); FFA_ERR_INVALID otherwise.
+ffa_status find_device_tables(ffa_plan p, const DeviceTables** out);
 
 ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave,
                          int center, hipStream_t st);

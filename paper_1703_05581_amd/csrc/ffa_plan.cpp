@@ -371,6 +371,18 @@ ffa_status check_hip(hipError_t e, const char* what) {
 
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
+ffa_status find_device_tables(ffa_plan p, const DeviceTables** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(p->dev_mu);
+  for (auto& t : p->dev)
+    if (t.device == dev) {
+      *out = &t;
+      return FFA_OK;
+    }
+  return fail(FFA_ERR_INVALID, "the plan has no device tables on this GPU yet (ffa_plan_upload makes them)");
+}
+
 ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
@@ -703,6 +715,12 @@ extern "C" ffa_status ffa_plan_create_opts(const ffa_plan_desc* d, const ffa_pla
   p->select_cand = opts.select_cand == 0 ? 64 : opts.select_cand;
   *out = p;
   return FFA_OK;
+}
+
+extern "C" ffa_status ffa_plan_upload(ffa_plan p) {
+  if (!p) return fail(FFA_ERR_INVALID, "null plan");
+  const DeviceTables* dt = nullptr;
+  return device_tables(p, &dt);
 }
 
 extern "C" ffa_status ffa_plan_destroy(ffa_plan p) {

@@ -39,7 +39,7 @@ FFA_SNR_ALG2_OFFPULSE = 2
 
 # every symbol include/ffa.h declares
 EXPORTS = (
-    "ffa_plan_create", "ffa_plan_create_opts", "ffa_plan_destroy", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
+    "ffa_plan_create", "ffa_plan_create_opts", "ffa_plan_destroy", "ffa_plan_upload", "ffa_search_noalloc", "ffa_plan_query", "ffa_plan_step", "ffa_plan_passes",
     "ffa_plan_periods", "ffa_prepare", "ffa_search_prepared", "ffa_search", "ffa_fold", "ffa_best",
     "ffa_sift", "ffa_snr_histogram", "ffa_sigma_gauss", "ffa_sigma_threshold", "ffa_batch_workspace",
     "ffa_search_batch", "ffa_batch_create", "ffa_batch_destroy", "ffa_batch_query", "ffa_batch_search",
@@ -114,6 +114,8 @@ _P = ctypes.POINTER
 _lib.ffa_plan_create.argtypes = [_P(PlanDesc), _P(_vp)]
 _lib.ffa_plan_create_opts.argtypes = [_P(PlanDesc), _P(PlanOpts), _P(_vp)]
 _lib.ffa_plan_destroy.argtypes = [_vp]
+_lib.ffa_plan_upload.argtypes = [_vp]
+_lib.ffa_search_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.ffa_plan_query.argtypes = [_vp, _P(_i64), _P(_i32), _P(_sz)]
 _lib.ffa_plan_step.argtypes = [_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i64)]
 _lib.ffa_plan_passes.argtypes = [_vp, _i32, _P(_i32), _P(_i32)]
@@ -293,6 +295,21 @@ class Plan:
         avail = ws.numel() - (base - ws.data_ptr())
         _check(_lib.ffa_search(self._h, series.data_ptr(), snr.data_ptr(), width.data_ptr(), base,
                                avail, _stream_ptr(stream)), "ffa_search")
+        return snr, width
+
+    def upload(self) -> None:
+        """ffa_plan_upload: the plan's device tables on the current GPU."""
+        _check(_lib.ffa_plan_upload(self._h), "ffa_plan_upload")
+
+    def search_noalloc(self, series, snr, width, stream=None):
+        """ffa_search_noalloc: the periodogram of ``series`` into ``snr`` and
+        ``width`` (preallocated), with the library's fixed scratch as the
+        workspace; nothing is allocated.  Needs upload() (or a search) first."""
+        self._check_series(series)
+        if snr.numel() != self.n_trials or width.numel() != self.n_trials:
+            raise ValueError("outputs must hold n_trials entries")
+        _check(_lib.ffa_search_noalloc(self._h, series.data_ptr(), snr.data_ptr(), width.data_ptr(),
+                                       _stream_ptr(stream)), "ffa_search_noalloc")
         return snr, width
 
     def prepare(self, series, ws, stream=None):
