@@ -1338,18 +1338,24 @@ __global__ __launch_bounds__(kKnotThreads) void knot_median_kernel(const T* __re
 constexpr int kRmBlock = 256;     // outputs (and threads) per workgroup
 constexpr int kRmPool = 1024;     // pool entries
 constexpr int kRmStageMax = 16384;  // window values staged in LDS (doubles)
+constexpr int kRmBins = 1024;      // buckets of the pass that bounds the medians
 
 struct RmShared {
   double pool_v[kRmPool];
-  int32_t pool_p[kRmPool];
+  int16_t pool_p[kRmPool];    // union index of each pool entry
+  int16_t core_at[kRmPool];   // pool index of the r-th core entry, in value order
+  int16_t fr_at[kRmPool];     // pool index of the j-th fringe entry, in value order
+  int16_t fr_p[kRmPool];      // its union index
   double cand[kRmBlock];
   int32_t scanL[kRmBlock], scanR[kRmBlock];
   int32_t wred[kRmBlock / kWave], wred2[kRmBlock / kWave];
-  int64_t wred64[kRmBlock / kWave];
+  int64_t wred64[kRmBlock / kWave], wred64b[kRmBlock / kWave];
   double dred[kRmBlock / kWave];
-  int32_t pool_n, flag;
+  uint32_t hist[kRmBins];
+  int32_t pool_n, n_core, n_fr, qa, qb;
   double res;
 };
+static_assert(kRmStageMax <= 32767 && kRmPool <= 32767, "16-bit indices of the running median");
 
 // Block-wide reductions (every thread returns the result).
 __device__ __forceinline__ int64_t rm_sum(RmShared& sh, int64_t v) {
@@ -1360,6 +1366,23 @@ __device__ __forceinline__ int64_t rm_sum(RmShared& sh, int64_t v) {
   for (int w = 0; w < kRmBlock / kWave; ++w) t += sh.wred64[w];
   __syncthreads();
   return t;
+}
+__device__ __forceinline__ void rm_sum2(RmShared& sh, int64_t& a, int64_t& b) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane_id() == 0) {
+    sh.wred64[wave_id()] = a;
+    sh.wred64b[wave_id()] = b;
+  }
+  __syncthreads();
+  int64_t ta = 0, tb = 0;
+  for (int w = 0; w < kRmBlock / kWave; ++w) {
+    ta += sh.wred64[w];
+    tb += sh.wred64b[w];
+  }
+  __syncthreads();
+  a = ta;
+  b = tb;
 }
 __device__ __forceinline__ double rm_min(RmShared& sh, double v) {
   v = -wave_dmax(-v);
@@ -1490,14 +1513,74 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
     const int64_t f_i = cnt_i - nC;
     const double ra_d = rm_min(sh, live ? (double)(k1 - f_i) : INFINITY);
     const double rb_d = rm_max(sh, live ? (double)k2 : -INFINITY);
-    auto core = [&](int64_t j) { return stage[Clo - Ulo + j]; };
-    v_a = ra_d >= 0.0 ? rm_kth(sh, core, nC, (int64_t)ra_d) : -INFINITY;
-    v_b = rb_d < (double)nC ? rm_kth(sh, core, nC, (int64_t)rb_d) : INFINITY;
-    // the pool: the union's values in [v_a, v_b]; and the values below v_a
-    if (tid == 0) {
-      sh.pool_n = 0;
-      sh.flag = 0;
+    // Bounds v_a <= C_(ra) and v_b >= C_(rb) in one counting pass: the core's
+    // values go into kRmBins equal buckets between its minimum and maximum
+    // (the bucket index is monotone in the value, so equal values share a
+    // bucket and every bucket lies above the ones below it); v_a is the
+    // smallest value in the bucket holding rank ra, v_b the largest in the
+    // one holding rank rb, so count(< v_a) <= ra < rb < count(<= v_b).
+    const double* core = stage + (Clo - Ulo);
+    const bool skip1 = !(ra_d >= 0.0), skip2 = !(rb_d < (double)nC);
+    const int64_t ra = skip1 ? 0 : (int64_t)ra_d, rb = skip2 ? 0 : (int64_t)rb_d;
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t j = tid; j < nC; j += kRmBlock) {
+      mn = fmin(mn, core[j]);
+      mx = fmax(mx, core[j]);
     }
+    mn = rm_min(sh, mn);
+    mx = rm_max(sh, mx);
+    v_a = mn;
+    v_b = mx;
+    if (mx > mn) {
+      const double scale = (double)kRmBins / (mx - mn);
+      auto bucket = [&](double v) {
+        const int q = (int)((v - mn) * scale);
+        return q < kRmBins - 1 ? q : kRmBins - 1;
+      };
+      for (int q = tid; q < kRmBins; q += kRmBlock) sh.hist[q] = 0u;
+      __syncthreads();
+      for (int64_t j = tid; j < nC; j += kRmBlock) atomicAdd(&sh.hist[bucket(core[j])], 1u);
+      __syncthreads();
+      // exclusive prefix counts of the buckets, kRmBins / kRmBlock per thread
+      constexpr int kPerB = kRmBins / kRmBlock;
+      uint32_t hv[kPerB], own = 0;
+#pragma unroll
+      for (int q = 0; q < kPerB; ++q) {
+        hv[q] = sh.hist[tid * kPerB + q];
+        own += hv[q];
+      }
+      const uint32_t inc = wave_scan(own);
+      if (lane_id() == kWave - 1) sh.wred[wave_id()] = (int32_t)inc;
+      __syncthreads();
+      int64_t run = (int64_t)inc - own;
+      for (int w = 0; w < wave_id(); ++w) run += sh.wred[w];
+      if (tid == 0) {
+        sh.qa = 0;
+        sh.qb = kRmBins - 1;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kPerB; ++q) {
+        if (!skip1 && run <= ra && ra < run + (int64_t)hv[q]) sh.qa = tid * kPerB + q;
+        if (!skip2 && run <= rb && rb < run + (int64_t)hv[q]) sh.qb = tid * kPerB + q;
+        run += hv[q];
+      }
+      __syncthreads();
+      const int qa = sh.qa, qb = sh.qb;
+      double lo_a = INFINITY, hi_b = -INFINITY;
+      for (int64_t j = tid; j < nC; j += kRmBlock) {
+        const double v = core[j];
+        const int q = bucket(v);
+        if (q == qa) lo_a = fmin(lo_a, v);
+        if (q == qb) hi_b = fmax(hi_b, v);
+      }
+      v_a = rm_min(sh, lo_a);
+      v_b = rm_max(sh, hi_b);
+    }
+    if (skip1) v_a = -INFINITY;
+    if (skip2) v_b = INFINITY;
+    // the pool: the union's values in [v_a, v_b]; and the values below v_a
+    if (tid == 0) sh.pool_n = 0;
     __syncthreads();
     int64_t core_below = 0;
     for (int64_t j = tid; j < nU; j += kRmBlock) {
@@ -1507,7 +1590,7 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
         const int at = atomicAdd(&sh.pool_n, 1);
         if (at < kRmPool) {
           sh.pool_v[at] = v;
-          sh.pool_p[at] = (int32_t)j;
+          sh.pool_p[at] = (int16_t)j;
         }
       }
       if (pos >= Clo && pos < Chi) core_below += v < v_a;
@@ -1549,7 +1632,7 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
       while (np2 < pn) np2 <<= 1;
       for (int j = pn + tid; j < np2; j += kRmBlock) {
         sh.pool_v[j] = INFINITY;
-        sh.pool_p[j] = 0x7fffffff;
+        sh.pool_p[j] = 0x7fff;
       }
       __syncthreads();
       for (int k = 2; k <= np2; k <<= 1) {
@@ -1559,7 +1642,7 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
             if (u > t) {
               const bool up = (t & k) == 0;
               const double va = sh.pool_v[t], vb = sh.pool_v[u];
-              const int32_t pa = sh.pool_p[t], pb = sh.pool_p[u];
+              const int16_t pa = sh.pool_p[t], pb = sh.pool_p[u];
               const bool gt = va > vb || (va == vb && pa > pb);
               if (gt == up) {
                 sh.pool_v[t] = vb;
@@ -1572,23 +1655,83 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
           __syncthreads();
         }
       }
-      // walk: the entries inside this output's window, in value order
+      // split the sorted pool into its core entries (in every window of the
+      // block) and its fringe entries, each list in value order
+      {
+        constexpr int kPer = kRmPool / kRmBlock;  // entries per thread
+        const int cbeg = (int)(Clo - Ulo), cend = (int)(Chi - Ulo);
+        int ncore = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+          const int t = tid * kPer + q;
+          ncore += (t < pn && sh.pool_p[t] >= cbeg && sh.pool_p[t] < cend) ? 1 : 0;
+        }
+        const uint32_t inc = wave_scan((uint32_t)ncore);
+        if (lane_id() == kWave - 1) sh.wred[wave_id()] = (int32_t)inc;
+        __syncthreads();
+        int cbase = 0;
+        for (int w = 0; w < wave_id(); ++w) cbase += sh.wred[w];
+        int ctot = 0;
+        for (int w = 0; w < kRmBlock / kWave; ++w) ctot += sh.wred[w];
+        int c = cbase + (int)inc - ncore;          // core entries before this thread's
+        int f = tid * kPer - c;                    // fringe entries before them
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+          const int t = tid * kPer + q;
+          if (t < pn) {
+            const int16_t pp = sh.pool_p[t];
+            if (pp >= cbeg && pp < cend) {
+              sh.core_at[c++] = (int16_t)t;
+            } else {
+              sh.fr_at[f] = (int16_t)t;
+              sh.fr_p[f++] = pp;
+            }
+          }
+        }
+        if (tid == 0) {
+          sh.n_core = ctot;
+          sh.n_fr = pn - ctot;
+        }
+        __syncthreads();
+      }
+      // each output: the in-window entries in value order are the core
+      // entries with this output's in-window fringe entries merged in; walk
+      // the fringe list and take the targets' ranks
       if (live) {
         const int64_t t1 = k1 - below, t2 = k2 - below;
         const int32_t plo = (int32_t)(lo_i - Ulo), phi = (int32_t)(hi_i - Ulo);
-        int64_t c = 0;
+        const int nf = sh.n_fr, ncr = sh.n_core;
+        auto core_val = [&](int64_t r) {  // the r-th core entry (clamped: r is in range)
+          r = r < 0 ? 0 : (r >= ncr ? ncr - 1 : r);
+          return sh.pool_v[sh.core_at[r]];
+        };
         double m1 = 0.0, m2 = 0.0;
-        for (int j = 0; j < pn; ++j) {
-          const int32_t pp = sh.pool_p[j];
-          if (pp >= plo && pp < phi) {
-            if (c == t1) m1 = sh.pool_v[j];
-            if (c == t2) {
-              m2 = sh.pool_v[j];
-              break;
+        bool got1 = false, got2 = false;
+        int64_t jin = 0;  // in-window fringe entries so far
+        for (int j = 0; j < nf && !got2; ++j) {
+          const int32_t pp = sh.fr_p[j];
+          if (pp < plo || pp >= phi) continue;
+          const int64_t before = (int64_t)(sh.fr_at[j] - j) + jin;  // in-window entries before it
+          if (!got1) {
+            if (t1 < before) {
+              m1 = core_val(t1 - jin);
+              got1 = true;
+            } else if (t1 == before) {
+              m1 = sh.pool_v[sh.fr_at[j]];
+              got1 = true;
             }
-            ++c;
           }
+          if (t2 < before) {
+            m2 = core_val(t2 - jin);
+            got2 = true;
+          } else if (t2 == before) {
+            m2 = sh.pool_v[sh.fr_at[j]];
+            got2 = true;
+          }
+          ++jin;
         }
+        if (!got1) m1 = core_val(t1 - jin);
+        if (!got2) m2 = core_val(t2 - jin);
         med[i] = (cnt_i % 2) ? m1 : 0.5 * (m1 + m2);
       }
     }
