@@ -658,6 +658,36 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
     const int e = r * kWave + lane;
     fv[r] = (r < kFullRegs<E> || e < P0) ? row[e] : (T)0;
   }
+  // Float profiles: the boxes come from prefix sums of the profile shifted by
+  // its bin nearest the mean, which keeps them as precise as their own bins
+  // whatever the profile's offset (and exact where the bins are exact small
+  // multiples of a power of two, so exact ties stay ties); the shift is added
+  // back in double.
+  float shift = 0.f;
+  if constexpr (!INT) {
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) t += (double)fv[r];  // pads hold 0
+    const double mean_all = wave_sum(t) / (double)P0;
+    float bd = INFINITY, bv = 0.f;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = r * kWave + lane;
+      const float d = (float)fabs((double)fv[r] - mean_all);
+      if ((r < kFullRegs<E> || e < P0) && d < bd) {
+        bd = d;
+        bv = fv[r];
+      }
+    }
+    const uint32_t kd = fkey(bd), kmin = wave_umin(kd);
+    const int src = __ffsll((unsigned long long)__ballot(kd == kmin)) - 1;
+    shift = __uint_as_float(readlane(__float_as_uint(bv), src));
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = r * kWave + lane;
+      if (r < kFullRegs<E> || e < P0) row[e] = fv[r] - shift;
+    }
+  }
   wave_lds_sync();
   A cex[ER];
   {
@@ -740,7 +770,9 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
         s2 = fma(dv, dv, s2);
       }
       const double var = wave_sum(s2) / (double)c;
-      a = var > 0.0 ? ((double)fval(pk) - (double)w * mean) / (sqrt(var) * wt.sqrtw(i)) : 0.0;
+      // the box maximum is of the shifted profile: I_max - w*I_av is
+      // max_c - w*(I_av - shift)
+      a = var > 0.0 ? ((double)fval(pk) - (double)w * (mean - (double)shift)) / (sqrt(var) * wt.sqrtw(i)) : 0.0;
     }
     if (i == 0 || a > best) {
       best = a;
@@ -830,13 +862,15 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   select_pair<E, !INT>(key, P0, k1, k2, kmin, kmax, scratch, kn, pm, m1, m2);
   uint64_t med2 = 0;
   float med = 0.f;
+  double med_d = 0.0;
   uint32_t dmax;
   if constexpr (INT) {
     med2 = (uint64_t)m1 + (uint64_t)m2;
     const uint64_t up = 2 * (uint64_t)kmax - med2, dn = med2 - 2 * (uint64_t)kmin;
     dmax = (uint32_t)(up > dn ? up : dn);
   } else {
-    med = (float)(0.5 * ((double)fval(m1) + (double)fval(m2)));
+    med_d = 0.5 * ((double)fval(m1) + (double)fval(m2));
+    med = (float)med_d;
     dmax = fkey(fmaxf(fabsf(fval(kmax) - med), fabsf(fval(kmin) - med)));
   }
   // MAD: the same selection on |x - median| (doubled for integers)
@@ -886,6 +920,18 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     return;
   }
 
+  // Float profiles are shifted by the (float) median before the prefix sums,
+  // so the running sums stay near zero and a box C[j+w] - C[j] keeps the
+  // precision of its own bins whatever the profile's offset; the shift is
+  // added back exactly in double below.
+  if constexpr (!INT) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = r * kWave + lane;
+      if (r < kFullRegs<E> || e < P0) row[e] = row[e] - med;
+    }
+    wave_lds_sync();
+  }
   A cex[E];  // C[j] (exclusive prefix) of this lane's bins
   circular_prefix<E, INT>(row, P0, wmax, cex);
 
@@ -944,7 +990,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   const bool live = lane < nw;
   double num;
   if constexpr (INT) num = (double)(2 * (2 * (int64_t)pk_l - (int64_t)wt.w * (int64_t)med2));
-  else num = (double)fval(pk_l) - (double)wt.w * (double)med;
+  else num = (double)fval(pk_l) - (double)wt.w * (med_d - (double)med);
   const double a = live ? num * wt.isq : -INFINITY;
   const bool row0 = nw <= 16;  // every width's lane is in the first row
   const double amax = row0 ? row_dmax16(a) : wave_dmax(a);
