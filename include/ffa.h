@@ -365,20 +365,31 @@ ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,
  * request's footprint -- series copy (host input only) + the plan's
  * ws_bytes + the periodogram (8 B per trial) -- fits in what is free, and
  * enqueues it on the least-loaded stream, next to the requests already
- * running.  A request keeps its memory until it is waited on.  All server
- * calls are thread-safe; ffa_server_destroy must not race with the others.
- * Errors: FFA_ERR_INVALID, FFA_ERR_NOMEM (pool allocation), FFA_ERR_DEVICE. */
+ * running.  When the head does not fit, a later request (among the next 64)
+ * that fits is admitted before it (backfill), until max_bypass requests have
+ * passed that head; then admission waits until the head fits.  max_bypass 0
+ * admits in strict arrival order.  A request keeps its memory until it is
+ * waited on.  All server calls are thread-safe; ffa_server_destroy must not
+ * race with the others.
+ * Errors: FFA_ERR_INVALID (budget below 256 B, n_streams out of range,
+ * max_bypass < 0), FFA_ERR_NOMEM (pool allocation), FFA_ERR_DEVICE. */
 ffa_status ffa_server_create(size_t hbm_budget_bytes, int32_t n_streams,
-                             ffa_server* out);
+                             int32_t max_bypass, ffa_server* out);
 
 /* Submit a search of `series` with `plan`.  Host input (is_device == 0) is
- * copied at the call, so the caller may reuse its buffer at once; a device
- * pointer (is_device != 0) must stay valid until the request completes.
- * The plan must outlive the request.  Returns a ticket (> 0).  Errors:
- * FFA_ERR_INVALID, FFA_ERR_UNSUPPORTED (footprint above the whole budget),
- * FFA_ERR_BUSY (65536 requests pending), FFA_ERR_NOMEM. */
+ * copied at the call, so the caller may reuse its buffer at once;
+ * producer_stream is ignored.  A device series (is_device != 0) is read
+ * only after the work queued on producer_stream (a hipStream_t of the
+ * server's device; NULL = the null stream) before this call has finished:
+ * an event is recorded there now and the request's stream waits on it.  The
+ * series must stay valid and unmodified until the request completes, and the
+ * server's device must be current.  The plan must outlive the request.
+ * Returns a ticket (> 0, issued in order from 1).  Errors: FFA_ERR_INVALID,
+ * FFA_ERR_UNSUPPORTED (footprint above the whole budget), FFA_ERR_BUSY
+ * (65536 requests pending), FFA_ERR_NOMEM, FFA_ERR_DEVICE (event record). */
 ffa_status ffa_server_submit(ffa_server s, ffa_plan plan, const void* series,
-                             int is_device, int64_t* ticket);
+                             int is_device, void* producer_stream,
+                             int64_t* ticket);
 
 /* Wait for a ticket (timeout_us < 0: forever; 0: poll).  Copies the
  * periodogram to the host arrays (n_trials entries each; either may be NULL),
@@ -395,6 +406,13 @@ ffa_status ffa_server_wait(ffa_server s, int64_t ticket, int64_t timeout_us,
 /* Stops admitting, lets the running requests finish, frees the pool and the
  * streams.  Requests not yet collected are dropped. */
 ffa_status ffa_server_destroy(ffa_server s);
+
+/* Test hook for the failure path of ffa_server_wait: the request with this
+ * ticket (issued already or later) fails with FFA_ERR_DEVICE when it is
+ * admitted, before any of its work is enqueued, as a launch the runtime
+ * refused would; every other request is served as usual.  Errors:
+ * FFA_ERR_INVALID (null server, ticket <= 0). */
+ffa_status ffa_debug_server_fail(ffa_server s, int64_t ticket);
 
 const char* ffa_status_str(ffa_status st);
 const char* ffa_last_error(void);

@@ -2,11 +2,15 @@
 //
 // One device arena of the HBM budget holds every admitted request's series
 // copy, workspace and periodogram.  A scheduler thread admits pending
-// requests in arrival order while their footprint fits what is free, and
-// enqueues each on the least-loaded of the server's streams, where it runs
-// next to requests admitted earlier.  A host callback on the stream stamps the
-// completion.  A request keeps its memory until it is waited on, so clients
-// that stop collecting results stop new admissions rather than exhaust memory.
+// requests in arrival order while their footprint fits what is free; when the
+// head does not fit, later requests that do may pass it (backfill), up to a
+// bound on how often the head is passed, after which admission waits for the
+// head.  Each admitted request is enqueued on the least-loaded of the
+// server's streams, where it runs next to requests admitted earlier; a device
+// input is read only after the caller's stream has passed the point of
+// submission.  A host callback on the stream stamps the completion.  A
+// request keeps its memory until it is waited on, so clients that stop
+// collecting results stop new admissions rather than exhaust memory.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -16,6 +20,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -30,6 +35,9 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxPending = 1 << 16;
 constexpr int32_t kMaxStreams = 16;
+// Pending requests looked at behind a head that does not fit (bounds the
+// scheduler's work per wake-up).
+constexpr size_t kBackfillScan = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -76,18 +84,28 @@ struct Request {
   ffa_plan plan = nullptr;
   std::vector<unsigned char> host;  // copy of a host series
   const void* dev_series = nullptr; // caller's device series
+  hipEvent_t ready = nullptr;       // recorded on the producer stream at submit
   size_t series_bytes = 0, ws_bytes = 0, out_bytes = 0, footprint = 0;
   size_t off = 0;                   // arena offset of its block
   int stream = -1;
+  int32_t passed = 0;               // later requests admitted while it was the head
+  bool inject_fail = false;         // test hook: fail before enqueueing anything
   State state = State::kPending;
   ffa_status err = FFA_OK;
   Clock::time_point t_submit, t_done;
+  Request() = default;
+  Request(const Request&) = delete;
+  Request& operator=(const Request&) = delete;
+  ~Request() {
+    if (ready) (void)hipEventDestroy(ready);
+  }
 };
 
 }  // namespace
 
 struct ffa_server_s {
   int device = -1;
+  int32_t max_bypass = 0;
   char* base = nullptr;
   size_t budget = 0;
   std::unique_ptr<Arena> arena;
@@ -100,6 +118,7 @@ struct ffa_server_s {
   std::deque<Request*> pending;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
   int64_t next_ticket = 1;
+  std::set<int64_t> fail_tickets;  // test hook (ffa_debug_server_fail)
   bool stop = false;
   std::thread sched;
 };
@@ -124,10 +143,15 @@ void on_done(void* p) {
 
 // Enqueues one admitted request on its stream (called without the lock).
 ffa_status enqueue(ffa_server_s* s, Request* r) {
+  if (r->inject_fail) return fail(FFA_ERR_DEVICE, "launch failure injected by ffa_debug_server_fail");
   hipStream_t st = s->streams[(size_t)r->stream];
   char* blk = s->base + r->off;
   const void* series = r->dev_series;
   size_t o = 0;
+  if (r->ready) {
+    ffa_status e = check_hip(hipStreamWaitEvent(st, r->ready, 0), "wait for the producer stream");
+    if (e != FFA_OK) return e;
+  }
   if (!series) {
     ffa_status e = check_hip(hipMemcpyAsync(blk, r->host.data(), r->series_bytes, hipMemcpyHostToDevice, st),
                              "series upload");
@@ -151,13 +175,23 @@ void scheduler(ffa_server_s* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
-    // admit in arrival order while the head fits
+    // Admit in arrival order while the head fits.  Behind a head that does
+    // not, a later request that fits is admitted too (backfill) until the
+    // head has been passed max_bypass times; then admission waits for it.
     std::vector<Request*> admitted;
-    while (!s->pending.empty()) {
-      Request* r = s->pending.front();
+    size_t i = 0;
+    while (i < s->pending.size() && i <= kBackfillScan) {
+      Request* head = s->pending.front();
+      if (i > 0 && head->passed >= s->max_bypass) break;
+      Request* r = s->pending[i];
       size_t off = 0;
-      if (!s->arena->alloc(r->footprint, &off)) break;
-      s->pending.pop_front();
+      if (!s->arena->alloc(r->footprint, &off)) {
+        ++i;
+        continue;
+      }
+      if (i > 0) head->passed++;
+      s->pending.erase(s->pending.begin() + (std::ptrdiff_t)i);
+      r->inject_fail = s->fail_tickets.erase(r->ticket) > 0;
       r->off = off;
       r->stream = (int)(std::min_element(s->inflight.begin(), s->inflight.end()) - s->inflight.begin());
       s->inflight[(size_t)r->stream]++;
@@ -197,13 +231,15 @@ Request* find(ffa_server_s* s, int64_t ticket) {
 
 }  // namespace
 
-extern "C" ffa_status ffa_server_create(size_t budget, int32_t n_streams, ffa_server* out) {
+extern "C" ffa_status ffa_server_create(size_t budget, int32_t n_streams, int32_t max_bypass, ffa_server* out) {
   if (!out) return fail(FFA_ERR_INVALID, "null argument");
   *out = nullptr;
   if (budget < kAlign) return fail(FFA_ERR_INVALID, "hbm_budget_bytes too small");
   if (n_streams < 1 || n_streams > kMaxStreams) return fail(FFA_ERR_INVALID, "n_streams must be in [1, 16]");
+  if (max_bypass < 0) return fail(FFA_ERR_INVALID, "max_bypass must be >= 0");
   std::unique_ptr<ffa_server_s> s(new (std::nothrow) ffa_server_s());
   if (!s) return fail(FFA_ERR_NOMEM, "server allocation");
+  s->max_bypass = max_bypass;
   if (hipGetDevice(&s->device) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
   s->budget = budget / kAlign * kAlign;
   if (hipMalloc(reinterpret_cast<void**>(&s->base), s->budget) != hipSuccess) {
@@ -240,7 +276,7 @@ extern "C" ffa_status ffa_server_create(size_t budget, int32_t n_streams, ffa_se
 }
 
 extern "C" ffa_status ffa_server_submit(ffa_server s, ffa_plan p, const void* series, int is_device,
-                                        int64_t* ticket) {
+                                        void* producer_stream, int64_t* ticket) {
   if (!s || !p || !series || !ticket) return fail(FFA_ERR_INVALID, "null argument");
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return fail(FFA_ERR_NOMEM, "request allocation");
@@ -253,6 +289,19 @@ extern "C" ffa_status ffa_server_submit(ffa_server s, ffa_plan p, const void* se
   if (r->footprint > s->budget) return fail(FFA_ERR_UNSUPPORTED, "request footprint exceeds the server's HBM budget");
   if (is_device) {
     r->dev_series = series;
+    // The request's stream waits for this event, so the series is read only
+    // after the work the caller queued before submitting has written it.
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
+    if (cur != s->device) return fail(FFA_ERR_INVALID, "submit a device series with the server's device current");
+    if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess) {
+      r->ready = nullptr;
+      (void)hipGetLastError();
+      return fail(FFA_ERR_DEVICE, "cannot create the producer event");
+    }
+    ffa_status e = check_hip(hipEventRecord(r->ready, static_cast<hipStream_t>(producer_stream)),
+                             "record on the producer stream");
+    if (e != FFA_OK) return e;
   } else {
     try {
       r->host.resize(r->series_bytes);
@@ -313,6 +362,16 @@ extern "C" ffa_status ffa_server_wait(ffa_server s, int64_t ticket, int64_t time
   s->reqs.erase(ticket);
   s->cv.notify_all();
   return e;
+}
+
+// Test hook: the request with this ticket (issued or still to be issued)
+// fails when admitted, before anything of it is enqueued, as a launch that
+// the runtime refused would; the server keeps serving the others.
+extern "C" ffa_status ffa_debug_server_fail(ffa_server s, int64_t ticket) {
+  if (!s || ticket <= 0) return fail(FFA_ERR_INVALID, "null server or bad ticket");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->fail_tickets.insert(ticket);
+  return FFA_OK;
 }
 
 extern "C" ffa_status ffa_server_destroy(ffa_server s) {

@@ -44,7 +44,7 @@ EXPORTS = (
     "ffa_sift", "ffa_snr_histogram", "ffa_sigma_gauss", "ffa_sigma_threshold", "ffa_batch_workspace",
     "ffa_search_batch", "ffa_batch_create", "ffa_batch_destroy", "ffa_batch_query", "ffa_batch_search",
     "ffa_batch_prepare", "ffa_batch_search_prepared", "ffa_server_create", "ffa_server_submit", "ffa_server_wait",
-    "ffa_server_destroy", "ffa_status_str", "ffa_last_error",
+    "ffa_server_destroy", "ffa_debug_server_fail", "ffa_status_str", "ffa_last_error",
 )
 
 
@@ -138,10 +138,11 @@ _lib.ffa_batch_query.argtypes = [_vp, _P(_sz), _P(_i64), _P(_i32)]
 _lib.ffa_batch_search.argtypes = [_vp, _P(_vp), _P(_vp), _P(_vp), _vp, _sz, _vp]
 _lib.ffa_batch_prepare.argtypes = [_vp, _P(_vp), _vp, _sz, _vp]
 _lib.ffa_batch_search_prepared.argtypes = [_vp, _P(_vp), _P(_vp), _vp, _sz, _vp]
-_lib.ffa_server_create.argtypes = [_sz, _i32, _P(_vp)]
-_lib.ffa_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int, _P(_i64)]
+_lib.ffa_server_create.argtypes = [_sz, _i32, _i32, _P(_vp)]
+_lib.ffa_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, _P(_i64)]
 _lib.ffa_server_wait.argtypes = [_vp, _i64, _i64, _vp, _vp, _P(ctypes.c_double)]
 _lib.ffa_server_destroy.argtypes = [_vp]
+_lib.ffa_debug_server_fail.argtypes = [_vp, _i64]
 _lib.ffa_status_str.argtypes = [ctypes.c_int]
 _lib.ffa_status_str.restype = ctypes.c_char_p
 _lib.ffa_last_error.argtypes = []
@@ -581,18 +582,21 @@ class Batch:
 
 class Server:
     """Continuous-batching search server (ffa_server_*): one HBM pool of
-    ``hbm_budget_bytes`` on the current GPU and ``n_streams`` streams."""
+    ``hbm_budget_bytes`` on the current GPU and ``n_streams`` streams.  A
+    request that does not fit may be passed by up to ``max_bypass`` later
+    ones that do (0: strict arrival order)."""
 
-    def __init__(self, hbm_budget_bytes: int, n_streams: int = 4):
+    def __init__(self, hbm_budget_bytes: int, n_streams: int = 4, max_bypass: int = 4):
         h = _vp()
-        _check(_lib.ffa_server_create(ctypes.c_size_t(hbm_budget_bytes), n_streams, ctypes.byref(h)),
+        _check(_lib.ffa_server_create(ctypes.c_size_t(hbm_budget_bytes), n_streams, max_bypass, ctypes.byref(h)),
                "ffa_server_create")
         self._h = h.value
         self._plans = {}
 
     def submit(self, plan: Plan, series) -> int:
         """Queue a search of ``series``: a numpy array (copied now) or a cuda
-        tensor (read when the request runs).  Returns the ticket."""
+        tensor (read when the request runs, after the work queued on the
+        current torch stream so far).  Returns the ticket."""
         import numpy as np
 
         want = np.uint8 if plan.dtype == "u8" else np.float32
@@ -601,10 +605,13 @@ class Server:
             if series.dtype != want or series.size != plan.N:
                 raise ValueError(f"series must hold {plan.N} {np.dtype(want).name} samples")
             arr = np.ascontiguousarray(series)
-            st = _lib.ffa_server_submit(self._h, plan.handle, arr.ctypes.data, 0, ctypes.byref(t))
+            st = _lib.ffa_server_submit(self._h, plan.handle, arr.ctypes.data, 0, None, ctypes.byref(t))
         else:
+            import torch
+
             plan._check_series(series)
-            st = _lib.ffa_server_submit(self._h, plan.handle, series.data_ptr(), 1, ctypes.byref(t))
+            producer = torch.cuda.current_stream(series.device).cuda_stream
+            st = _lib.ffa_server_submit(self._h, plan.handle, series.data_ptr(), 1, producer, ctypes.byref(t))
         _check(st, "ffa_server_submit")
         self._plans[t.value] = (plan, series)  # keep both alive until the wait
         return t.value
@@ -624,6 +631,10 @@ class Server:
             self._plans.pop(ticket, None)
         _check(st, "ffa_server_wait")
         return snr, wid, lat.value
+
+    def fail_ticket(self, ticket: int) -> None:
+        """Test hook (ffa_debug_server_fail): that request fails on admission."""
+        _check(_lib.ffa_debug_server_fail(self._h, ticket), "ffa_debug_server_fail")
 
     def close(self) -> None:
         if getattr(self, "_h", None):

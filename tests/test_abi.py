@@ -178,12 +178,14 @@ def test_server_argument_errors_before_gpu():
     """Bad server arguments are refused on the host, before any device call."""
     lib = ffa.lib()
     h = ctypes.c_void_p()
-    assert lib.ffa_server_create(1 << 30, 4, None) == ffa.FFA_ERR_INVALID
-    assert lib.ffa_server_create(1 << 30, 0, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
-    assert lib.ffa_server_create(1 << 30, 17, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
-    assert lib.ffa_server_create(100, 2, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(1 << 30, 4, 0, None) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(1 << 30, 0, 0, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(1 << 30, 17, 0, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(100, 2, 0, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_create(1 << 30, 2, -1, ctypes.byref(h)) == ffa.FFA_ERR_INVALID
     t = ctypes.c_int64()
-    assert lib.ffa_server_submit(None, None, None, 0, ctypes.byref(t)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_server_submit(None, None, None, 0, None, ctypes.byref(t)) == ffa.FFA_ERR_INVALID
+    assert lib.ffa_debug_server_fail(None, 1) == ffa.FFA_ERR_INVALID
     assert lib.ffa_server_wait(None, 1, 0, None, None, None) == ffa.FFA_ERR_INVALID
     assert lib.ffa_server_destroy(None) == ffa.FFA_ERR_INVALID
 

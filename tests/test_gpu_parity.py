@@ -4,7 +4,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from parity import check_periodogram, check_profiles, step_trials
+from parity import check_periodogram, check_profiles, pulsar_snr, step_trials
 
 pytestmark = pytest.mark.gpu
 
@@ -152,8 +152,9 @@ def test_workload2_sampled(torch_cuda, ffa, oracle_mod):
 
     s = synth.workload2()
     pa = s.plan
-    run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
-             list(pa.widths), "u8", steps_max=24, check_fold=3)
+    plan, _ = run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
+                       list(pa.widths), "u8", steps_max=24, check_fold=3)
+    _assert_recovered(torch_cuda, plan, s, 10.0)
 
 
 def test_workload3_sampled(torch_cuda, ffa, oracle_mod):
@@ -163,9 +164,25 @@ def test_workload3_sampled(torch_cuda, ffa, oracle_mod):
 
     s = synth.workload3()
     pa = s.plan
-    run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
-             list(pa.widths), "f32", steps_max=10, check_fold=2, dered_window=pa.dered_window,
-             dered_stride=pa.dered_stride)
+    plan, _ = run_case(torch_cuda, ffa, oracle_mod, s.data, pa.N, pa.tsamp, pa.pmin, pa.pmax, pa.bins_min,
+                       list(pa.widths), "f32", steps_max=10, check_fold=2, dered_window=pa.dered_window,
+                       dered_stride=pa.dered_stride)
+    _assert_recovered(torch_cuda, plan, s, 6.6)
+
+
+def _assert_recovered(torch, plan, series, floor):
+    """Every injected pulsar peaks at its own period at or above ``floor``
+    (6.6 is Algorithm 1's 5-sigma white-noise level of Sec. 4.1.2) and at
+    or above 60% of its injected S/N (what the discrete widths, the trial
+    grid and the dereddening may cost)."""
+    snr, _ = plan.search(torch.from_numpy(series.data).cuda())
+    snr = snr.cpu().numpy()
+    periods = plan.periods()
+    for p in series.pulsars:
+        peak = pulsar_snr(periods, snr, p.period_s)
+        print(f"pulsar P={p.period_s:.4f} s duty={p.duty:.3f} injected S/N {p.snr:.1f}: found {peak:.2f}",
+              flush=True)
+        assert peak >= max(floor, 0.6 * p.snr), (p, peak)
 
 
 def test_deterministic(torch_cuda, ffa):

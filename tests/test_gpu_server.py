@@ -108,3 +108,112 @@ def test_server_concurrent_clients(env):
         t.join(timeout=120)
     assert not errors
     srv.close()
+
+
+def test_server_failure_isolation(env):
+    """A request whose launch fails (forced on the host by the test hook,
+    before anything of it is enqueued) reports FFA_ERR_DEVICE; every other
+    request, before and after it, is served bit for bit, and the server keeps
+    admitting afterwards."""
+    torch, ffa, synth = env
+    plans = [ffa.Plan(60000, 1e-3, 0.2, 0.9, 200, W10, "u8"),
+             ffa.Plan(80000, 1e-3, 0.3, 1.5, 256, None, "f32")]
+    srv = ffa.Server(2 << 30, 3)
+    srv.fail_ticket(4)  # tickets are issued from 1 in submission order
+    jobs = []
+    for i in range(8):
+        p = plans[i % 2]
+        x = synth.random_series(1200 + i, p.N, p.dtype)
+        jobs.append((srv.submit(p, x), p, x))
+    assert [t for t, _, _ in jobs] == list(range(1, 9))
+    for t, p, x in jobs:
+        print("ticket", t, flush=True)
+        if t == 4:
+            with pytest.raises(ffa.FFAError) as e:
+                srv.wait(t)
+            assert e.value.status == ffa.FFA_ERR_DEVICE
+            continue
+        s, w, _ = srv.wait(t)
+        s0, w0 = _reference(torch, p, x)
+        assert np.array_equal(s, s0) and np.array_equal(w, w0), t
+    x = synth.random_series(1300, plans[0].N, "u8")
+    s, w, _ = srv.wait(srv.submit(plans[0], x))
+    s0, w0 = _reference(torch, plans[0], x)
+    assert np.array_equal(s, s0) and np.array_equal(w, w0)
+    srv.close()
+
+
+def _backfill_setup(ffa):
+    big = ffa.Plan(200000, 1e-3, 0.2, 1.0, 200, W10, "u8")
+    small = ffa.Plan(30000, 1e-3, 0.2, 0.6, 200, W10, "u8")
+    fb, fs = _footprint(big, True), _footprint(small, True)
+    assert fb > fs + 8192 and fs > 8192
+    return big, small, fb + fs + 4096  # one big and one small fit, no more
+
+
+def test_server_strict_order(env):
+    """max_bypass 0: a small request behind a big one that does not fit
+    waits, though it would fit."""
+    torch, ffa, synth = env
+    big, small, budget = _backfill_setup(ffa)
+    srv = ffa.Server(budget, 2, max_bypass=0)
+    xb = [synth.random_series(60 + i, big.N, "u8") for i in range(2)]
+    xs = synth.random_series(70, small.N, "u8")
+    tb = [srv.submit(big, x) for x in xb]
+    ts = srv.submit(small, xs)
+    with pytest.raises(ffa.FFAError) as e:
+        srv.wait(ts, timeout_s=0.3)
+    assert e.value.status == ffa.FFA_ERR_TIMEOUT
+    for t, p, x in [(tb[0], big, xb[0]), (tb[1], big, xb[1]), (ts, small, xs)]:
+        s, w, _ = srv.wait(t)
+        s0, w0 = _reference(torch, p, x)
+        assert np.array_equal(s, s0) and np.array_equal(w, w0), t
+    srv.close()
+
+
+def test_server_backfill_and_aging_bound(env):
+    """max_bypass 1: the first small request passes the blocked big one; once
+    it has, the second small waits for the big one although it would fit."""
+    torch, ffa, synth = env
+    big, small, budget = _backfill_setup(ffa)
+    srv = ffa.Server(budget, 2, max_bypass=1)
+    xb = [synth.random_series(80 + i, big.N, "u8") for i in range(2)]
+    xs = [synth.random_series(90 + i, small.N, "u8") for i in range(2)]
+    tb = [srv.submit(big, x) for x in xb]
+    ts = [srv.submit(small, x) for x in xs]
+    s, w, _ = srv.wait(ts[0], timeout_s=60)  # admitted past the blocked head
+    s0, w0 = _reference(torch, small, xs[0])
+    assert np.array_equal(s, s0) and np.array_equal(w, w0)
+    with pytest.raises(ffa.FFAError) as e:  # fits now, but the head was passed once
+        srv.wait(ts[1], timeout_s=0.3)
+    assert e.value.status == ffa.FFA_ERR_TIMEOUT
+    for t, p, x in [(tb[0], big, xb[0]), (tb[1], big, xb[1]), (ts[1], small, xs[1])]:
+        s, w, _ = srv.wait(t)
+        s0, w0 = _reference(torch, p, x)
+        assert np.array_equal(s, s0) and np.array_equal(w, w0), t
+    srv.close()
+
+
+def test_server_device_input_after_producer_stream(env):
+    """A device series written by work still queued on the caller's stream
+    at submission is read only after that work: the request's stream waits
+    on an event recorded on the producer stream."""
+    torch, ffa, synth = env
+    p = ffa.Plan(1 << 18, 1e-3, 0.256, 2.048, 256, W10, "u8")
+    x_np = synth.random_series(1400, p.N, "u8")
+    src = torch.from_numpy(x_np).cuda()
+    dst = torch.zeros_like(src)
+    a = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    srv = ffa.Server(2 << 30, 2)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for _ in range(20):  # keep the producer stream busy ahead of the copy
+            a = torch.mm(a, a).clamp_(-1.0, 1.0)
+        dst.copy_(src)
+        t = srv.submit(p, dst)
+    s, w, _ = srv.wait(t)
+    torch.cuda.synchronize()
+    s0, w0 = _reference(torch, p, x_np)
+    assert np.array_equal(s, s0) and np.array_equal(w, w0)
+    srv.close()
