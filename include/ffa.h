@@ -105,8 +105,9 @@ typedef struct {
   int32_t dered_stride;
 } ffa_plan_desc;
 
-/* Build a plan: step list, pass split of every step, device-side tables.
- * Allocates device memory for the tables on the current GPU.  Errors:
+/* Build a plan: step list, pass split of every step, work queue.  Host
+ * only (no device call); the plan's device tables are made on a GPU by the
+ * first call there that needs them, or by ffa_plan_upload.  Errors:
  * FFA_ERR_INVALID (bad field, no step, a step with no usable width),
  * FFA_ERR_UNSUPPORTED (uint8 series with 255*N >= 2^31, or a step too large
  * for the kernels), FFA_ERR_NOMEM. */
