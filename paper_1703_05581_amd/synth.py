@@ -26,7 +26,7 @@ them; the shapes follow Sec. 2.4 and Sec. 4 of the paper):
   6 "null"    : 26 f32 series of white N(0,1) noise for the false-alarm statistics of
                 Sec. 4.1.2: 2^21 samples of 2.048 ms (an HTRU-length observation of 64 us
                 samples downsampled by 2^5), 1-20 s, base period 488 bins (1 s, the lowest
-                trial period in samples), the paper's default widths; about 1.5e8 trials.
+                trial period in samples), the paper's default widths; 1.03e8 trials over the 26.
 """
 from __future__ import annotations
 
