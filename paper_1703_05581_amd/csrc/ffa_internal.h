@@ -55,7 +55,7 @@ struct Phase {
   int32_t u16;          // 1: the tile keeps its rows as 16-bit sums in LDS
   int32_t ring64;       // multi-pass step: its intermediates start at ring_off + 64*ring64
   int32_t series;       // series of a batch (index of its output pointers); 0 for one plan
-  int32_t in_u16;       // 1: the previous pass left its partials in the ring as 16-bit sums
+  int32_t reserved;
 };
 static_assert(sizeof(Phase) == 104, "phase layout");
 

@@ -1145,25 +1145,17 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
 
   if constexpr (INT) {
     if (ph.u16) {  // a first pass whose sums stay below 2^16 (the planner checks)
-      // The partials go to the ring as 16-bit sums too, packed from the start
-      // of the step's range (16-bit element 2*buf0 + i holds partial element i).
       uint16_t* l16 = reinterpret_cast<uint16_t*>(lds_raw);
       stage_rows(l16, ws + src_off, R, valid, P0, S);
       __syncthreads();
       butterfly<uint16_t>(l16, S, P0, H, d);
       const int64_t Gout = Gin >> d;
-      write_partials(l16, reinterpret_cast<uint16_t*>(ws) + 2 * buf0 + (((int64_t)q << d) * Gout + h) * P0, R, d,
-                     S, P0, Gout * P0, h);
+      write_partials(l16, ws + ((ph.pass & 1) ? buf1 : buf0) + (((int64_t)q << d) * Gout + h) * P0, R, d, S, P0,
+                     Gout * P0, h);
       return;
     }
-    if (ph.in_u16) {  // the second pass of such a step reads them back
-      stage_rows(lds, reinterpret_cast<const uint16_t*>(ws) + 2 * buf0 + (src_off - buf0), R, valid, P0, S);
-    } else {
-      stage_rows(lds, ws + src_off, R, valid, P0, S);
-    }
-  } else {
-    stage_rows(lds, ws + src_off, R, valid, P0, S);
   }
+  stage_rows(lds, ws + src_off, R, valid, P0, S);
   __syncthreads();
 
   butterfly<T>(lds, S, P0, H, d);

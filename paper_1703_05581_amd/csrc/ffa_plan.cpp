@@ -231,9 +231,6 @@ bool queue_valid(const std::vector<Step>& steps, const Queue& q, int acc_int) {
     if (ph.halo < std::min<int64_t>(R / 2, s.P0) || ph.halo > s.P0) return false;
     if (ph.stride < s.P0 + ph.halo || (last && ph.stride < s.P0 + s.wmax + 1)) return false;
     if (ph.u16 && (ph.pass != 0 || last || !acc_int || s.octave + dp > 8)) return false;
-    // 16-bit partials in the ring exactly when the first pass kept 16-bit rows
-    if (ph.u16 != (ph.pass == 0 && s.u16_first ? 1 : 0) || ph.in_u16 != (ph.pass == 1 && s.u16_first ? 1 : 0))
-      return false;
     const int64_t lds = phase_lds(ph);
     if (lds > (int64_t)kLdsBytes || lds > w.lds_bytes || ph.P0 > w.max_P0) return false;
     if (ph.wofs != s.wofs || ph.nw != s.nw || (last && s.nw < 1)) return false;
@@ -655,7 +652,6 @@ extern "C" ffa_status ffa_plan_create_opts(const ffa_plan_desc* d, const ffa_pla
       ph.D = D;
       ph.vin = (int32_t)vin;
       ph.u16 = pass == 0 && s.u16_first ? 1 : 0;
-      ph.in_u16 = pass == 1 && s.u16_first ? 1 : 0;
       ph.stride = stride_of(s, dp, last, esz_of(ph));
       ph.halo = halo_of(s.P0, dp);
       ph.wofs = s.wofs;

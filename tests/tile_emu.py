@@ -13,7 +13,7 @@ PHASE_DT = np.dtype([
     ("ntiles", "<i4"), ("ng", "<i4"), ("step", "<i4"), ("pass_", "<i4"), ("last", "<i4"),
     ("P0", "<i4"), ("M", "<i4"), ("depth", "<i4"), ("D", "<i4"), ("vin", "<i4"),
     ("stride", "<i4"), ("halo", "<i4"), ("wofs", "<i4"), ("nw", "<i4"), ("isqrt_ofs", "<i4"),
-    ("launch", "<i4"), ("u16", "<i4"), ("ring64", "<i4"), ("series", "<i4"), ("in_u16", "<i4")])
+    ("launch", "<i4"), ("u16", "<i4"), ("ring64", "<i4"), ("series", "<i4"), ("reserved", "<i4")])
 assert PHASE_DT.itemsize == 104
 SCRATCH = 16 * 64 * 4
 LDS_MAX = 160 * 1024
@@ -83,7 +83,6 @@ def _check_queue(ph, L, pass0, n_trials, u16_ok):
     for x in ph:
         npass[int(x["step"])] = max(npass.get(int(x["step"]), 0), int(x["pass_"]) + 1)
     live = {}        # step -> (start, end) of the ring range its intermediates hold
-    u16_steps = set()  # steps whose first pass keeps 16-bit rows (and writes 16-bit partials)
     ended = {}       # step -> launch of its last pass
     for x in ph:
         w = int(x["launch"])
@@ -97,9 +96,6 @@ def _check_queue(ph, L, pass0, n_trials, u16_ok):
         if x["u16"]:
             # 16-bit rows only on a first pass of a uint8 plan whose sums fit
             assert p == 0 and not x["last"] and u16_ok(x, d), s
-            u16_steps.add(s)
-        # the second pass reads 16-bit partials exactly when the first wrote them
-        assert bool(x["in_u16"]) == (p == 1 and s in u16_steps), ("16-bit ring", s, p)
         lds = R * int(x["stride"]) * esz + (SCRATCH if x["last"] else 0)
         assert lds <= wlds <= LDS_MAX and P0 <= wp0
         MP = M * P0
