@@ -40,6 +40,8 @@ struct ClassDev {
 struct BatchDev {
   int device = -1;
   std::vector<ClassDev> cls;
+  DeredSeg* dered_segs = nullptr;  // the dereddening plan of all the batch's float series
+  int32_t* dered_block_seg = nullptr;
   hipEvent_t done = nullptr;  // recorded after each search (cached batches only)
 };
 
@@ -69,6 +71,8 @@ struct ffa_batch_s {
   std::vector<int64_t> series_base;  // element offset of each series' region
   int64_t outs_off = 0;              // element offset of the SeriesOut table
   std::vector<BatchClass> classes;
+  DeredPlan dered;                   // exact dereddening of every float series, all at once
+  std::vector<uint8_t> dered_by_batch;  // series whose dereddening is in `dered`
   int64_t n_tiles = 0;
   int32_t n_launches = 0;
   size_t ws_bytes = 0;
@@ -89,6 +93,8 @@ void free_batch_device(ffa_batch_s* b) {
       (void)hipEventDestroy(d.done);
     }
     for (auto& c : d.cls) free_class(c);
+    if (d.dered_segs) (void)hipFree(d.dered_segs);
+    if (d.dered_block_seg) (void)hipFree(d.dered_block_seg);
     if (d.device != cur && cur >= 0) (void)hipSetDevice(cur);
   }
   b->dev.clear();
@@ -111,6 +117,18 @@ ffa_status plan_batch(int32_t n, const ffa_plan* plans, ffa_batch_s** out) {
     b->series_base.push_back(cur);
     cur = round_up(cur + plans[i]->series_elems, 64);
   }
+  // the exact dereddening of every float series as one plan of launches
+  b->dered_by_batch.assign((size_t)n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    if (plans[i]->dered.segs.empty()) continue;
+    b->dered_by_batch[(size_t)i] = 1;
+    for (DeredSeg sg : plans[i]->dered.segs) {
+      sg.x_off += b->series_base[(size_t)i];
+      sg.out_off += b->series_base[(size_t)i];
+      b->dered.segs.push_back(sg);
+    }
+  }
+  plan_dered(b->dered);
   // classes: (exact integer folds, algorithm, selection exits)
   std::vector<int32_t> cls_of((size_t)n, -1);
   for (int32_t i = 0; i < n; ++i) {
@@ -213,10 +231,13 @@ ffa_status batch_device(ffa_batch_s* b, BatchDev** out) {
   d.device = dev;
   auto release = [&] {
     for (auto& c : d.cls) free_class(c);
+    if (d.dered_segs) (void)hipFree(d.dered_segs);
+    if (d.dered_block_seg) (void)hipFree(d.dered_block_seg);
     if (d.done) (void)hipEventDestroy(d.done);
   };
   ffa_status st = FFA_OK;
   if (b->track_use) st = check_hip(hipEventCreateWithFlags(&d.done, hipEventDisableTiming), "batch event");
+  if (st == FFA_OK) st = upload_dered(b->dered, &d.dered_segs, &d.dered_block_seg);
   for (const BatchClass& k : b->classes) {
     if (st != FFA_OK) break;
     ClassDev c;
@@ -267,11 +288,17 @@ ffa_status prepare_batch(ffa_batch_s* b, const void* const* d_series, void* d_ws
   const size_t n = b->plans.size();
   for (size_t i = 0; i < n; ++i)
     if (!d_series[i]) return fail(FFA_ERR_INVALID, "null series");
+  BatchDev* dev = nullptr;
+  s = batch_device(b, &dev);
+  if (s != FFA_OK) return s;
   char* ws = reinterpret_cast<char*>(d_ws);
   for (size_t i = 0; i < n && s == FFA_OK; ++i) {
     const ffa_plan p = b->plans[i];
-    s = build_octaves(p, d_series[i], ws + (size_t)b->series_base[i] * 4, p->n_octaves - 1, 1, st);
+    s = build_octaves(p, d_series[i], ws + (size_t)b->series_base[i] * 4, p->n_octaves - 1, 1, st, nullptr,
+                      !b->dered_by_batch[i]);
   }
+  // every float series' octaves dereddened together
+  if (s == FFA_OK && dev->dered_segs) s = run_dered(b->dered, dev->dered_segs, dev->dered_block_seg, d_ws, st);
   return s;
 }
 

@@ -38,7 +38,7 @@ namespace ffa {
 // Octave series 0..last_octave of one series into the series region at the
 // start of `ws`.  Float input is centred on its mean when `center`.
 ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave, int center,
-                         hipStream_t st) {
+                         hipStream_t st, const DeviceTables* dt, bool dered) {
   const int int_sums = p->desc.dtype == FFA_IN_U8;
   ffa_status s = FFA_OK;
   if (p->dered_W > 0 && !int_sums) {
@@ -49,6 +49,10 @@ ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_
     for (int32_t o = 1; o <= last_octave && s == FFA_OK; ++o)
       s = check_hip(launch_halve_f64(ws, p->raw_off[o - 1], p->oct_len[o], p->raw_off[o], st),
                     "downsample kernel");
+    if (s != FFA_OK || !dered) return s;
+    // the exact filter of every octave at once, from the plan's tables
+    if (dt && dt->dered_segs && last_octave == p->n_octaves - 1)
+      return run_dered(p->dered, dt->dered_segs, dt->dered_block_seg, ws, st);
     for (int32_t o = p->dered_oct0; o <= last_octave && s == FFA_OK; ++o)
       s = check_hip(launch_deredden(ws, 2, p->raw_off[o], p->oct_len[o], p->dered_W, p->dered_stride,
                                     p->knots_off, p->oct_off[o], st),
@@ -107,7 +111,10 @@ extern "C" ffa_status ffa_prepare(ffa_plan p, const void* d_series, void* d_ws, 
   if (!p || !d_series) return fail(FFA_ERR_INVALID, "null argument");
   ffa_status s = check_ws(p->ws_bytes, d_ws, ws_bytes);
   if (s != FFA_OK) return s;
-  return build_octaves(p, d_series, d_ws, p->n_octaves - 1, 1, reinterpret_cast<hipStream_t>(stream));
+  const DeviceTables* dt = nullptr;
+  s = device_tables(p, &dt);
+  if (s != FFA_OK) return s;
+  return build_octaves(p, d_series, d_ws, p->n_octaves - 1, 1, reinterpret_cast<hipStream_t>(stream), dt);
 }
 
 extern "C" ffa_status ffa_search_prepared(ffa_plan p, float* d_snr, int32_t* d_width, void* d_ws,
@@ -140,7 +147,7 @@ extern "C" ffa_status ffa_fold(ffa_plan p, const void* d_series, int32_t step, v
   if (s != FFA_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Step& sp = p->steps[step];
-  s = build_octaves(p, d_series, d_ws, sp.octave, 0, st);
+  s = build_octaves(p, d_series, d_ws, sp.octave, 0, st, dt);
   if (s != FFA_OK) return s;
   // the step's passes in order, one launch each
   const int is_int = p->acc_int;

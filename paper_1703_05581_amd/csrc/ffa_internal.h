@@ -159,6 +159,34 @@ constexpr int32_t kSiftMaxPeaks = 16384;
 constexpr int kSiftBlock = 1024;  // trials per block of the compaction
 
 // Device copies of a plan's tables (made on first use on a device).
+// One series of the exact running-median dereddening (paper Sec. 2.3.1) in
+// a launch over many: the raw octave series at x_off (doubles) is filtered
+// into the float32 series at out_off (offsets in 4-byte elements from the
+// workspace base), with `window` samples.
+struct DeredSeg {
+  int64_t x_off;
+  int64_t out_off;
+  int64_t n;
+  int64_t block0;     // first block of the segment (blocks are numbered across all launches)
+  int32_t window;
+  int32_t use_stage;  // the union of a block's windows is staged in LDS
+};
+
+// Blocks [block0, block0 + blocks) of a dereddening plan, `lds` bytes each.
+struct DeredLaunch {
+  int64_t block0;
+  int64_t blocks;
+  int32_t lds;
+};
+
+// The exact dereddening of several series as a few launches: segments grouped
+// by how many of their blocks share a CU, and the segment of every block.
+struct DeredPlan {
+  std::vector<DeredSeg> segs;
+  std::vector<int32_t> block_seg;
+  std::vector<DeredLaunch> launches;
+};
+
 struct DeviceTables {
   int device = -1;
   StepDev* steps = nullptr;
@@ -167,6 +195,8 @@ struct DeviceTables {
   int32_t* tile_phase = nullptr;
   int32_t* widths = nullptr;
   double* sqrtw = nullptr;
+  DeredSeg* dered_segs = nullptr;       // the plan's dereddening plan (float input, exact filter)
+  int32_t* dered_block_seg = nullptr;
 };
 
 }  // namespace ffa
@@ -202,6 +232,7 @@ struct ffa_plan_s {
   int32_t dered_oct0 = 0;               // first octave a step uses (the ones below only feed halving)
   int64_t knots_off = 0;                // workspace: knot medians (double) of one octave series
   std::vector<int64_t> raw_off;         // float input, dereddened: raw octave series in double
+  ffa::DeredPlan dered;                 // float input, exact filter: every octave's dereddening at once
   int64_t ring_off = 0;                 // workspace: series region, knots, then the ring
   int64_t sift_elems = 0;               // scratch of ffa_sift, from ring_off
   size_t ws_bytes = 0;
@@ -223,8 +254,19 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out);
 // nothing); FFA_ERR_INVALID otherwise.
 ffa_status find_device_tables(ffa_plan p, const DeviceTables** out);
 
+// dt: the plan's device tables on the current GPU (null: the octaves are
+// dereddened one launch each); dered = false leaves the dereddening of float
+// input to the caller (a batch runs it for all its series at once).
 ffa_status build_octaves(ffa_plan p, const void* series, void* ws, int32_t last_octave,
-                         int center, hipStream_t st);
+                         int center, hipStream_t st, const DeviceTables* dt, bool dered = true);
+// Groups the segments of dp (x_off, out_off, n and window set) into
+// launches and numbers their blocks.
+void plan_dered(DeredPlan& dp);
+// Copies a dereddening plan's tables to the device (null pointers when it is empty).
+ffa_status upload_dered(const DeredPlan& dp, DeredSeg** segs, int32_t** block_seg);
+// Runs every launch of dp on ws.
+ffa_status run_dered(const DeredPlan& dp, const DeredSeg* d_segs, const int32_t* d_block_seg, void* ws,
+                     hipStream_t st);
 // Every launch of plan p's search on `st`, workspace `ws` already holding the
 // octave series.
 ffa_status run_launches(ffa_plan p, const DeviceTables* dt, float* snr, int32_t* width, void* ws,
@@ -243,6 +285,13 @@ hipError_t launch_halve(void* ws, int is_int, int64_t in_off, int64_t n_out, int
 // (double) in ws[knots_off ..) (see ffa_plan_desc.dered_window).
 hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, int32_t window, int32_t stride,
                            int64_t knots_off, int64_t out_off, hipStream_t st);
+// LDS bytes of one block of the exact running median of an n-sample series
+// (and whether it stages the union of its windows), and its block count.
+size_t dered_block_lds(int64_t n, int32_t window, int32_t* use_stage);
+int64_t dered_block_count(int64_t n);
+// One launch of a dereddening plan (device tables).
+hipError_t launch_dered_batch(const DeredSeg* segs, const int32_t* block_seg, const DeredLaunch& L, void* ws,
+                              hipStream_t st);
 // float32 -> double copy, and one halving of a double series (element offsets)
 hipError_t launch_prep_f64(const float* series, int64_t n, void* ws, int64_t out_off, hipStream_t st);
 hipError_t launch_halve_f64(void* ws, int64_t in_off, int64_t n_out, int64_t out_off, hipStream_t st);

@@ -1520,15 +1520,15 @@ __device__ double rm_kth(RmShared& sh, Get get, int64_t cnt, int64_t r) {
 
 // One block of outputs: med[i] for i in [blockIdx.x * kRmBlock, ...).
 // use_stage: the launch gave the workgroup LDS for kRmStageMax values.
-template <typename T>
-__global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __restrict__ x, int64_t n,
-                                                                  int32_t window, int use_stage,
-                                                                  double* __restrict__ med) {
-  extern __shared__ __align__(16) unsigned char rm_lds[];
+// Block `blk` of the running median of x[0..n): its outputs' medians go to
+// sink(i, median).
+template <typename T, typename Sink>
+__device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int32_t window, int use_stage,
+                                         int64_t blk, unsigned char* rm_lds, Sink sink) {
   RmShared& sh = *reinterpret_cast<RmShared*>(rm_lds);
   double* stage = reinterpret_cast<double*>(rm_lds + ((sizeof(RmShared) + 15) & ~(size_t)15));
   const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * kRmBlock;
+  const int64_t i0 = blk * kRmBlock;
   const int64_t i1 = i0 + kRmBlock < n ? i0 + kRmBlock : n;
   const int64_t h = window / 2;
   auto wlo = [&](int64_t i) { const int64_t v = i - h; return v < 0 ? (int64_t)0 : v; };
@@ -1778,7 +1778,7 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
         }
         if (!got1) m1 = core_val(t1 - jin);
         if (!got2) m2 = core_val(t2 - jin);
-        med[i] = (cnt_i % 2) ? m1 : 0.5 * (m1 + m2);
+        sink(i, (cnt_i % 2) ? m1 : 0.5 * (m1 + m2));
       }
     }
   }
@@ -1789,9 +1789,33 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
       auto win = [&](int64_t j) { return val(lo + j); };
       const double m1 = rm_kth(sh, win, c, (c - 1) / 2);
       const double m = (c % 2) ? m1 : 0.5 * (m1 + rm_kth(sh, win, c, c / 2));
-      if (tid == 0) med[u] = m;
+      if (tid == 0) sink(u, m);
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __restrict__ x, int64_t n,
+                                                                  int32_t window, int use_stage,
+                                                                  double* __restrict__ med) {
+  extern __shared__ __align__(16) unsigned char rm_lds[];
+  rm_block(x, n, window, use_stage, (int64_t)blockIdx.x, rm_lds, [&](int64_t i, double m) { med[i] = m; });
+}
+
+// The exact dereddening of many series in one launch: block b runs block
+// b - block0 of its segment's running median (the segment from a per-block
+// map) and writes x[i] - median, in double, rounded once to float32.  Input
+// (double) and output (float32) never overlap.
+__global__ __launch_bounds__(kRmBlock) void dered_batch_kernel(const DeredSeg* __restrict__ segs,
+                                                               const int32_t* __restrict__ block_seg,
+                                                               int64_t block_base, float* __restrict__ ws) {
+  extern __shared__ __align__(16) unsigned char rm_lds[];
+  const int64_t b = block_base + blockIdx.x;
+  const DeredSeg sg = segs[block_seg[b]];
+  const double* x = reinterpret_cast<const double*>(ws + sg.x_off);
+  float* out = ws + sg.out_off;
+  rm_block(x, sg.n, sg.window, sg.use_stage, b - sg.block0, rm_lds,
+           [&](int64_t i, double m) { out[i] = (float)(x[i] - m); });
 }
 
 // out[i] = x[i] - med[i], in double, rounded once to float32 (`out` may alias
@@ -2240,6 +2264,25 @@ hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, i
   else if (src_type == 1) FFA_DERED(float);
   else FFA_DERED(double);
 #undef FFA_DERED
+  return hipGetLastError();
+}
+
+size_t dered_block_lds(int64_t n, int32_t window, int32_t* use_stage) {
+  const int64_t stage_n = std::min<int64_t>((int64_t)window + kRmBlock - 1, n);
+  *use_stage = stage_n <= kRmStageMax ? 1 : 0;
+  return ((sizeof(RmShared) + 15) & ~(size_t)15) + (*use_stage ? (size_t)stage_n * sizeof(double) : 0);
+}
+
+int64_t dered_block_count(int64_t n) { return (n + kRmBlock - 1) / kRmBlock; }
+
+hipError_t launch_dered_batch(const DeredSeg* segs, const int32_t* block_seg, const DeredLaunch& L, void* ws,
+                              hipStream_t st) {
+  if (L.blocks < 1) return hipSuccess;
+  if (L.blocks > 0x7fffffff || L.lds > (int32_t)kLdsBytes) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dered_batch_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+  dered_batch_kernel<<<(unsigned)L.blocks, kRmBlock, (size_t)L.lds, st>>>(segs, block_seg, L.block0,
+                                                                          reinterpret_cast<float*>(ws));
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ extern "C" ffa_status ffa_search_noalloc(ffa_plan p, const void* d_series, float
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   // nothing in the workspace needs to start at zero: every element a search
   // reads (centring sums, octave series, ring) is written by it first
-  s = build_octaves(p, d_series, ws, p->n_octaves - 1, 1, st);
+  s = build_octaves(p, d_series, ws, p->n_octaves - 1, 1, st, dt);
   if (s != FFA_OK) return s;
   return run_launches(p, dt, d_snr, d_width, ws, st);
 }

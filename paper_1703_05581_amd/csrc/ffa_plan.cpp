@@ -371,6 +371,74 @@ ffa_status check_hip(hipError_t e, const char* what) {
 
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
+void plan_dered(DeredPlan& dp) {
+  dp.block_seg.clear();
+  dp.launches.clear();
+  // blocks of one segment that fit a CU together (at most 8 of 256 threads)
+  std::vector<int32_t> lds(dp.segs.size());
+  std::vector<int32_t> per_cu(dp.segs.size());
+  for (size_t i = 0; i < dp.segs.size(); ++i) {
+    int32_t use_stage = 0;
+    lds[i] = (int32_t)dered_block_lds(dp.segs[i].n, dp.segs[i].window, &use_stage);
+    dp.segs[i].use_stage = use_stage;
+    per_cu[i] = (int32_t)std::max<size_t>(1, std::min<size_t>(8, kLdsBytes / (size_t)lds[i]));
+  }
+  std::vector<size_t> order(dp.segs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return per_cu[a] > per_cu[b]; });
+  std::vector<DeredSeg> segs;
+  int64_t blk = 0;
+  for (size_t k = 0; k < order.size(); ++k) {
+    const size_t i = order[k];
+    if (dp.launches.empty() || per_cu[i] != per_cu[order[k - 1]])
+      dp.launches.push_back(DeredLaunch{blk, 0, 0});
+    DeredLaunch& L = dp.launches.back();
+    DeredSeg sg = dp.segs[i];
+    sg.block0 = blk;
+    const int64_t nb = dered_block_count(sg.n);
+    for (int64_t b = 0; b < nb; ++b) dp.block_seg.push_back((int32_t)segs.size());
+    segs.push_back(sg);
+    blk += nb;
+    L.blocks += nb;
+    L.lds = std::max(L.lds, lds[i]);
+  }
+  dp.segs = std::move(segs);
+}
+
+ffa_status upload_dered(const DeredPlan& dp, DeredSeg** segs, int32_t** block_seg) {
+  *segs = nullptr;
+  *block_seg = nullptr;
+  if (dp.segs.empty()) return FFA_OK;
+  const size_t sb = dp.segs.size() * sizeof(DeredSeg), bb = dp.block_seg.size() * sizeof(int32_t);
+  if (hipMalloc(segs, sb) != hipSuccess || hipMalloc(block_seg, bb) != hipSuccess) {
+    if (*segs) (void)hipFree(*segs);
+    *segs = nullptr;
+    *block_seg = nullptr;
+    (void)hipGetLastError();
+    return fail(FFA_ERR_NOMEM, "dereddening tables: hipMalloc failed");
+  }
+  ffa_status st = check_hip(hipMemcpy(*segs, dp.segs.data(), sb, hipMemcpyHostToDevice), "upload dereddening plan");
+  if (st == FFA_OK)
+    st = check_hip(hipMemcpy(*block_seg, dp.block_seg.data(), bb, hipMemcpyHostToDevice),
+                   "upload dereddening block map");
+  if (st != FFA_OK) {
+    (void)hipFree(*segs);
+    (void)hipFree(*block_seg);
+    *segs = nullptr;
+    *block_seg = nullptr;
+  }
+  return st;
+}
+
+ffa_status run_dered(const DeredPlan& dp, const DeredSeg* d_segs, const int32_t* d_block_seg, void* ws,
+                     hipStream_t st) {
+  for (const DeredLaunch& L : dp.launches) {
+    const ffa_status s = check_hip(launch_dered_batch(d_segs, d_block_seg, L, ws, st), "dereddening kernel");
+    if (s != FFA_OK) return s;
+  }
+  return FFA_OK;
+}
+
 ffa_status find_device_tables(ffa_plan p, const DeviceTables** out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(FFA_ERR_DEVICE, "hipGetDevice failed");
@@ -436,6 +504,7 @@ ffa_status device_tables(ffa_plan p, const DeviceTables** out) {
   if (st == FFA_OK && !p->sqrtw.empty())
     st = check_hip(hipMemcpy(t.sqrtw, p->sqrtw.data(), p->sqrtw.size() * sizeof(double),
                              hipMemcpyHostToDevice), "upload sqrt widths");
+  if (st == FFA_OK) st = upload_dered(p->dered, &t.dered_segs, &t.dered_block_seg);
   if (st != FFA_OK) {
     free_all();
     return st;
@@ -613,6 +682,14 @@ extern "C" ffa_status ffa_plan_create_opts(const ffa_plan_desc* d, const ffa_pla
       p->raw_off.push_back(cur);
       cur = round_up(cur + 2 * (d->N >> o), 64);
     }
+    // the exact filter runs every used octave in one plan of launches
+    if (p->dered_stride == 1) {
+      for (int32_t o = p->dered_oct0; o < p->n_octaves; ++o)
+        if (p->oct_len[(size_t)o] > 0)
+          p->dered.segs.push_back(DeredSeg{p->raw_off[(size_t)o], p->oct_off[(size_t)o], p->oct_len[(size_t)o], 0,
+                                           p->dered_W, 0});
+      plan_dered(p->dered);
+    }
   }
   p->series_elems = cur;
 
@@ -735,6 +812,8 @@ extern "C" ffa_status ffa_plan_destroy(ffa_plan p) {
     (void)hipFree(t.steps);
     (void)hipFree(t.widths);
     (void)hipFree(t.sqrtw);
+    if (t.dered_segs) (void)hipFree(t.dered_segs);
+    if (t.dered_block_seg) (void)hipFree(t.dered_block_seg);
     if (t.device != cur && cur >= 0) (void)hipSetDevice(cur);
   }
   delete p;
