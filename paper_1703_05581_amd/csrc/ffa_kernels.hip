@@ -1381,7 +1381,8 @@ __global__ __launch_bounds__(kKnotThreads) void knot_median_kernel(const T* __re
 // (windows shorter than the block) or that are too long to stage in LDS
 // select every output's median directly instead.
 
-constexpr int kRmBlock = 256;     // outputs (and threads) per workgroup
+constexpr int kRmBlock = 256;     // outputs per workgroup
+constexpr int kRmThreads = 1024;  // threads per workgroup (the passes over a window use all)
 constexpr int kRmPool = 1024;     // pool entries
 constexpr int kRmStageMax = 16384;  // window values staged in LDS (doubles)
 constexpr int kRmBins = 1024;      // buckets of the pass that bounds the medians
@@ -1394,14 +1395,16 @@ struct RmShared {
   int16_t fr_p[kRmPool];      // its union index
   double cand[kRmBlock];
   int32_t scanL[kRmBlock], scanR[kRmBlock];
-  int32_t wred[kRmBlock / kWave], wred2[kRmBlock / kWave];
-  int64_t wred64[kRmBlock / kWave], wred64b[kRmBlock / kWave];
-  double dred[kRmBlock / kWave];
+  int32_t wred[kRmThreads / kWave], wred2[kRmThreads / kWave];
+  int64_t wred64[kRmThreads / kWave], wred64b[kRmThreads / kWave];
+  double dred[kRmThreads / kWave];
   uint32_t hist[kRmBins];
   int32_t pool_n, n_core, n_fr, qa, qb;
   double res;
 };
 static_assert(kRmStageMax <= 32767 && kRmPool <= 32767, "16-bit indices of the running median");
+static_assert(kRmThreads >= kRmBlock && kRmBins % kRmThreads == 0 && kRmPool % kRmThreads == 0,
+              "threads of the running median");
 
 // Block-wide reductions (every thread returns the result).
 __device__ __forceinline__ int64_t rm_sum(RmShared& sh, int64_t v) {
@@ -1409,7 +1412,7 @@ __device__ __forceinline__ int64_t rm_sum(RmShared& sh, int64_t v) {
   if (lane_id() == 0) sh.wred64[wave_id()] = v;
   __syncthreads();
   int64_t t = 0;
-  for (int w = 0; w < kRmBlock / kWave; ++w) t += sh.wred64[w];
+  for (int w = 0; w < kRmThreads / kWave; ++w) t += sh.wred64[w];
   __syncthreads();
   return t;
 }
@@ -1422,7 +1425,7 @@ __device__ __forceinline__ void rm_sum2(RmShared& sh, int64_t& a, int64_t& b) {
   }
   __syncthreads();
   int64_t ta = 0, tb = 0;
-  for (int w = 0; w < kRmBlock / kWave; ++w) {
+  for (int w = 0; w < kRmThreads / kWave; ++w) {
     ta += sh.wred64[w];
     tb += sh.wred64b[w];
   }
@@ -1435,7 +1438,7 @@ __device__ __forceinline__ double rm_min(RmShared& sh, double v) {
   if (lane_id() == 0) sh.dred[wave_id()] = v;
   __syncthreads();
   double t = sh.dred[0];
-  for (int w = 1; w < kRmBlock / kWave; ++w) t = fmin(t, sh.dred[w]);
+  for (int w = 1; w < kRmThreads / kWave; ++w) t = fmin(t, sh.dred[w]);
   __syncthreads();
   return t;
 }
@@ -1444,7 +1447,7 @@ __device__ __forceinline__ double rm_max(RmShared& sh, double v) {
   if (lane_id() == 0) sh.dred[wave_id()] = v;
   __syncthreads();
   double t = sh.dred[0];
-  for (int w = 1; w < kRmBlock / kWave; ++w) t = fmax(t, sh.dred[w]);
+  for (int w = 1; w < kRmThreads / kWave; ++w) t = fmax(t, sh.dred[w]);
   __syncthreads();
   return t;
 }
@@ -1457,7 +1460,7 @@ template <typename Get>
 __device__ double rm_kth(RmShared& sh, Get get, int64_t cnt, int64_t r) {
   const int tid = threadIdx.x;
   double mn = INFINITY, mx = -INFINITY;
-  for (int64_t j = tid; j < cnt; j += kRmBlock) {
+  for (int64_t j = tid; j < cnt; j += kRmThreads) {
     const double v = get(j);
     mn = fmin(mn, v);
     mx = fmax(mx, v);
@@ -1471,7 +1474,7 @@ __device__ double rm_kth(RmShared& sh, Get get, int64_t cnt, int64_t r) {
       // gather the values in [a, b] and rank them
       if (tid == 0) sh.pool_n = 0;
       __syncthreads();
-      for (int64_t j = tid; j < cnt; j += kRmBlock) {
+      for (int64_t j = tid; j < cnt; j += kRmThreads) {
         const double v = get(j);
         if (v >= a && v <= b) {
           const int at = atomicAdd(&sh.pool_n, 1);
@@ -1500,12 +1503,12 @@ __device__ double rm_kth(RmShared& sh, Get get, int64_t cnt, int64_t r) {
       // bracket holds only the values a and b
       __syncthreads();
       int64_t le = 0;
-      for (int64_t j = tid; j < cnt; j += kRmBlock) le += get(j) <= a;
+      for (int64_t j = tid; j < cnt; j += kRmThreads) le += get(j) <= a;
       le = rm_sum(sh, le);
       return le > r ? a : b;
     }
     int64_t c = 0;  // count(<= mid)
-    for (int64_t j = tid; j < cnt; j += kRmBlock) c += get(j) <= mid;
+    for (int64_t j = tid; j < cnt; j += kRmThreads) c += get(j) <= mid;
     c = rm_sum(sh, c);
     if (c > r) {
       b = mid;
@@ -1538,11 +1541,11 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
   const int64_t nU = Uhi - Ulo;
   const bool staged = use_stage && nU <= kRmStageMax;
   if (staged)
-    for (int64_t j = tid; j < nU; j += kRmBlock) stage[j] = (double)x[Ulo + j];
+    for (int64_t j = tid; j < nU; j += kRmThreads) stage[j] = (double)x[Ulo + j];
   __syncthreads();
   auto val = [&](int64_t pos) -> double { return staged ? stage[pos - Ulo] : (double)x[pos]; };
   const int64_t i = i0 + tid;
-  const bool live = i < i1;
+  const bool live = tid < kRmBlock && i < i1;
   const int64_t lo_i = live ? wlo(i) : 0, hi_i = live ? whi(i) : 1;
   const int64_t cnt_i = hi_i - lo_i;
   const int64_t k1 = (cnt_i - 1) / 2, k2 = cnt_i / 2;
@@ -1569,7 +1572,7 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
     const bool skip1 = !(ra_d >= 0.0), skip2 = !(rb_d < (double)nC);
     const int64_t ra = skip1 ? 0 : (int64_t)ra_d, rb = skip2 ? 0 : (int64_t)rb_d;
     double mn = INFINITY, mx = -INFINITY;
-    for (int64_t j = tid; j < nC; j += kRmBlock) {
+    for (int64_t j = tid; j < nC; j += kRmThreads) {
       mn = fmin(mn, core[j]);
       mx = fmax(mx, core[j]);
     }
@@ -1583,12 +1586,12 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
         const int q = (int)((v - mn) * scale);
         return q < kRmBins - 1 ? q : kRmBins - 1;
       };
-      for (int q = tid; q < kRmBins; q += kRmBlock) sh.hist[q] = 0u;
+      for (int q = tid; q < kRmBins; q += kRmThreads) sh.hist[q] = 0u;
       __syncthreads();
-      for (int64_t j = tid; j < nC; j += kRmBlock) atomicAdd(&sh.hist[bucket(core[j])], 1u);
+      for (int64_t j = tid; j < nC; j += kRmThreads) atomicAdd(&sh.hist[bucket(core[j])], 1u);
       __syncthreads();
-      // exclusive prefix counts of the buckets, kRmBins / kRmBlock per thread
-      constexpr int kPerB = kRmBins / kRmBlock;
+      // exclusive prefix counts of the buckets, kRmBins / kRmThreads per thread
+      constexpr int kPerB = kRmBins / kRmThreads;
       uint32_t hv[kPerB], own = 0;
 #pragma unroll
       for (int q = 0; q < kPerB; ++q) {
@@ -1614,7 +1617,7 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
       __syncthreads();
       const int qa = sh.qa, qb = sh.qb;
       double lo_a = INFINITY, hi_b = -INFINITY;
-      for (int64_t j = tid; j < nC; j += kRmBlock) {
+      for (int64_t j = tid; j < nC; j += kRmThreads) {
         const double v = core[j];
         const int q = bucket(v);
         if (q == qa) lo_a = fmin(lo_a, v);
@@ -1629,7 +1632,7 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
     if (tid == 0) sh.pool_n = 0;
     __syncthreads();
     int64_t core_below = 0;
-    for (int64_t j = tid; j < nU; j += kRmBlock) {
+    for (int64_t j = tid; j < nU; j += kRmThreads) {
       const double v = stage[j];
       const int64_t pos = Ulo + j;
       if (v >= v_a && v <= v_b) {
@@ -1659,10 +1662,12 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
       baseR += sh.wred2[w];
     }
     int32_t totalL = 0;
-    for (int w = 0; w < kRmBlock / kWave; ++w) totalL += sh.wred[w];
+    for (int w = 0; w < kRmThreads / kWave; ++w) totalL += sh.wred[w];
     __syncthreads();
-    sh.scanL[tid] = baseL + (int32_t)sl - (int32_t)bl;  // exclusive prefix
-    sh.scanR[tid] = baseR + (int32_t)sr - (int32_t)br;
+    if (tid < kRmBlock) {
+      sh.scanL[tid] = baseL + (int32_t)sl - (int32_t)bl;  // exclusive prefix
+      sh.scanR[tid] = baseR + (int32_t)sr - (int32_t)br;
+    }
     __syncthreads();
     const int pn = sh.pool_n;
     if (pn > kRmPool) {
@@ -1676,14 +1681,14 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
       // bitonic sort of the pool by (value, position), padded to a power of two
       int np2 = 1;
       while (np2 < pn) np2 <<= 1;
-      for (int j = pn + tid; j < np2; j += kRmBlock) {
+      for (int j = pn + tid; j < np2; j += kRmThreads) {
         sh.pool_v[j] = INFINITY;
         sh.pool_p[j] = 0x7fff;
       }
       __syncthreads();
       for (int k = 2; k <= np2; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          for (int t = tid; t < np2; t += kRmBlock) {
+          for (int t = tid; t < np2; t += kRmThreads) {
             const int u = t ^ jj;
             if (u > t) {
               const bool up = (t & k) == 0;
@@ -1704,7 +1709,7 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
       // split the sorted pool into its core entries (in every window of the
       // block) and its fringe entries, each list in value order
       {
-        constexpr int kPer = kRmPool / kRmBlock;  // entries per thread
+        constexpr int kPer = kRmPool / kRmThreads;  // entries per thread
         const int cbeg = (int)(Clo - Ulo), cend = (int)(Chi - Ulo);
         int ncore = 0;
 #pragma unroll
@@ -1718,7 +1723,7 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
         int cbase = 0;
         for (int w = 0; w < wave_id(); ++w) cbase += sh.wred[w];
         int ctot = 0;
-        for (int w = 0; w < kRmBlock / kWave; ++w) ctot += sh.wred[w];
+        for (int w = 0; w < kRmThreads / kWave; ++w) ctot += sh.wred[w];
         int c = cbase + (int)inc - ncore;          // core entries before this thread's
         int f = tid * kPer - c;                    // fringe entries before them
 #pragma unroll
@@ -1795,7 +1800,7 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(kRmThreads, 8) void running_median_kernel(const T* __restrict__ x, int64_t n,
                                                                   int32_t window, int use_stage,
                                                                   double* __restrict__ med) {
   extern __shared__ __align__(16) unsigned char rm_lds[];
@@ -1806,7 +1811,7 @@ __global__ __launch_bounds__(kRmBlock) void running_median_kernel(const T* __res
 // b - block0 of its segment's running median (the segment from a per-block
 // map) and writes x[i] - median, in double, rounded once to float32.  Input
 // (double) and output (float32) never overlap.
-__global__ __launch_bounds__(kRmBlock) void dered_batch_kernel(const DeredSeg* __restrict__ segs,
+__global__ __launch_bounds__(kRmThreads, 8) void dered_batch_kernel(const DeredSeg* __restrict__ segs,
                                                                const int32_t* __restrict__ block_seg,
                                                                int64_t block_base, float* __restrict__ ws) {
   extern __shared__ __align__(16) unsigned char rm_lds[];
@@ -2253,7 +2258,7 @@ hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, i
     if (stride == 1) {                                                                             \
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&running_median_kernel<TT>),         \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);       \
-      running_median_kernel<TT><<<(unsigned)nb, kRmBlock, rm_lds, st>>>(x, n, window, use_stage, med); \
+      running_median_kernel<TT><<<(unsigned)nb, kRmThreads, rm_lds, st>>>(x, n, window, use_stage, med); \
       median_subtract_kernel<TT><<<gs, tpb, 0, st>>>(x, n, med, out);                              \
     } else {                                                                                       \
       knot_median_kernel<TT><<<(unsigned)nk, kKnotThreads, 0, st>>>(x, n, window, stride, med);    \
@@ -2281,7 +2286,7 @@ hipError_t launch_dered_batch(const DeredSeg* segs, const int32_t* block_seg, co
   if (L.blocks > 0x7fffffff || L.lds > (int32_t)kLdsBytes) return hipErrorInvalidValue;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dered_batch_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-  dered_batch_kernel<<<(unsigned)L.blocks, kRmBlock, (size_t)L.lds, st>>>(segs, block_seg, L.block0,
+  dered_batch_kernel<<<(unsigned)L.blocks, kRmThreads, (size_t)L.lds, st>>>(segs, block_seg, L.block0,
                                                                           reinterpret_cast<float*>(ws));
   return hipGetLastError();
 }

@@ -374,14 +374,14 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 void plan_dered(DeredPlan& dp) {
   dp.block_seg.clear();
   dp.launches.clear();
-  // blocks of one segment that fit a CU together (at most 8 of 256 threads)
+  // blocks of one segment that fit a CU together (1024 threads each: at most 2)
   std::vector<int32_t> lds(dp.segs.size());
   std::vector<int32_t> per_cu(dp.segs.size());
   for (size_t i = 0; i < dp.segs.size(); ++i) {
     int32_t use_stage = 0;
     lds[i] = (int32_t)dered_block_lds(dp.segs[i].n, dp.segs[i].window, &use_stage);
     dp.segs[i].use_stage = use_stage;
-    per_cu[i] = (int32_t)std::max<size_t>(1, std::min<size_t>(8, kLdsBytes / (size_t)lds[i]));
+    per_cu[i] = (int32_t)std::max<size_t>(1, std::min<size_t>(2, kLdsBytes / (size_t)lds[i]));
   }
   std::vector<size_t> order(dp.segs.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
