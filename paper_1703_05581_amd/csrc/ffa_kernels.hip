@@ -1686,9 +1686,13 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
         sh.pool_p[j] = 0x7fff;
       }
       __syncthreads();
+      // (entry t belongs to thread t, so a compare over a distance below 64
+      // stays in one wave and needs no workgroup barrier before or after)
+      static_assert(kRmPool <= kRmThreads, "one pool entry per thread");
       for (int k = 2; k <= np2; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          for (int t = tid; t < np2; t += kRmThreads) {
+          const int t = tid;
+          if (t < np2) {
             const int u = t ^ jj;
             if (u > t) {
               const bool up = (t & k) == 0;
@@ -1703,7 +1707,9 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
               }
             }
           }
-          __syncthreads();
+          const int jn = jj > 1 ? jj >> 1 : (k < np2 ? k : 0);  // the next compare distance (0: sorted)
+          if (jj >= kWave || jn >= kWave || jn == 0) __syncthreads();
+          else wave_lds_sync();
         }
       }
       // split the sorted pool into its core entries (in every window of the
