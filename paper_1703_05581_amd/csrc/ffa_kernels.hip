@@ -602,7 +602,8 @@ constexpr int kFullRegs = E <= 8 ? E - 1 : (E == 12 ? 8 : (E == 16 ? 12 : (E == 
 // C[j + w] - C[j] (modular arithmetic is exact for the integer sums).
 template <int E, bool INT>
 __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int P0, int wmax,
-                                                typename Types<INT>::A (&cex)[E]) {
+                                                typename Types<INT>::A (&cex)[E],
+                                                typename Types<INT>::T shift = 0) {
   using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
   const int lane = lane_id();
@@ -610,7 +611,7 @@ __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = r * kWave + lane;
-    xv[r] = (r < kFullRegs<E> || e < P0) ? (A)row[e] : (A)0;
+    xv[r] = (r < kFullRegs<E> || e < P0) ? (A)(T)(row[e] - shift) : (A)0;
   }
   wave_lds_sync();
   A carry = (A)0;
@@ -682,17 +683,12 @@ __device__ __forceinline__ void score_alg2(typename Types<INT>::T* row, int P0, 
     const uint32_t kd = fkey(bd), kmin = wave_umin(kd);
     const int src = __ffsll((unsigned long long)__ballot(kd == kmin)) - 1;
     shift = __uint_as_float(readlane(__float_as_uint(bv), src));
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int e = r * kWave + lane;
-      if (r < kFullRegs<E> || e < P0) row[e] = fv[r] - shift;
-    }
   }
-  wave_lds_sync();
   A cex[ER];
   {
     A cex_all[E];
-    circular_prefix<E, INT>(row, P0, wmax, cex_all);
+    if constexpr (!INT) circular_prefix<E, INT>(row, P0, wmax, cex_all, shift);
+    else circular_prefix<E, INT>(row, P0, wmax, cex_all);
     if constexpr (kRegs) {
 #pragma unroll
       for (int r = 0; r < E; ++r) cex[r] = cex_all[r];
@@ -924,16 +920,9 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   // so the running sums stay near zero and a box C[j+w] - C[j] keeps the
   // precision of its own bins whatever the profile's offset; the shift is
   // added back exactly in double below.
-  if constexpr (!INT) {
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int e = r * kWave + lane;
-      if (r < kFullRegs<E> || e < P0) row[e] = row[e] - med;
-    }
-    wave_lds_sync();
-  }
   A cex[E];  // C[j] (exclusive prefix) of this lane's bins
-  circular_prefix<E, INT>(row, P0, wmax, cex);
+  if constexpr (!INT) circular_prefix<E, INT>(row, P0, wmax, cex, med);
+  else circular_prefix<E, INT>(row, P0, wmax, cex);
 
   // Each width's score is num_w / ((K*MAD)*sqrt(w)), the box maximum taken
   // over all positions.
