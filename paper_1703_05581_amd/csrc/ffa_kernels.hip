@@ -1074,6 +1074,34 @@ __device__ __forceinline__ void stage_rows(TL* lds, const TS* src, int R, int va
   }
 }
 
+// stage_rows for 4-byte rows through the LDS DMA path: every whole chunk of
+// 64 bins of a row with data goes from global memory straight into LDS
+// (global_load_lds_dword, no registers), all of a wave's chunks in flight at
+// once; the row tails and the zero rows take ordinary stores.  The caller's
+// barrier follows the wait for the DMA below.
+template <typename T>
+__device__ __forceinline__ void stage_rows_dma(T* lds, const T* src, int R, int valid, int P0, int S) {
+  static_assert(sizeof(T) == 4, "4-byte rows");
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int nwaves = blockDim.x / kWave;
+  const int nfull = P0 / kWave;
+  const bool tail = nfull * kWave + lane < P0;
+  for (int r = wave; r < R; r += nwaves) {
+    T* d = lds + (size_t)r * S;
+    if (r < valid) {
+      const T* g = src + (size_t)r * P0 + lane;
+      for (int c = 0; c < nfull; ++c)
+        __builtin_amdgcn_global_load_lds(g + c * kWave, d + c * kWave, 4, 0, 0);
+      if (tail) d[nfull * kWave + lane] = g[nfull * kWave];
+    } else {
+      for (int c = 0; c < nfull; ++c) d[c * kWave + lane] = (T)0;
+      if (tail) d[nfull * kWave + lane] = (T)0;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 // Hand partial t of a first-pass tile (LDS row bitrev(t, d)) to the next
 // pass, rotated left by t*h bins, at out0 + t*dst_step: the levels above
 // this pass then act on the rotated rows like a plain FFA tree.
@@ -1144,7 +1172,7 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
       return;
     }
   }
-  stage_rows(lds, ws + src_off, R, valid, P0, S);
+  stage_rows_dma(lds, ws + src_off, R, valid, P0, S);
   __syncthreads();
 
   butterfly<T>(lds, S, P0, H, d);
