@@ -369,7 +369,9 @@ ffa_status ffa_search_batch(int32_t n, const ffa_plan* plans,
  * running.  When the head does not fit, a later request (among the next 64)
  * that fits is admitted before it (backfill), until max_bypass requests have
  * passed that head; then admission waits until the head fits.  max_bypass 0
- * admits in strict arrival order.  A request keeps its memory until it is
+ * admits in strict arrival order (under heavy load it kept the tail latency
+ * lower than backfill, which delays the largest requests).  A request keeps
+ * its memory until it is
  * waited on.  All server calls are thread-safe; ffa_server_destroy must not
  * race with the others.
  * Errors: FFA_ERR_INVALID (budget below 256 B, n_streams out of range,

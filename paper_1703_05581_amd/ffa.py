@@ -584,9 +584,10 @@ class Server:
     """Continuous-batching search server (ffa_server_*): one HBM pool of
     ``hbm_budget_bytes`` on the current GPU and ``n_streams`` streams.  A
     request that does not fit may be passed by up to ``max_bypass`` later
-    ones that do (0: strict arrival order)."""
+    ones that do (0, the default: strict arrival order, which kept the tail
+    latency lower under heavy load)."""
 
-    def __init__(self, hbm_budget_bytes: int, n_streams: int = 4, max_bypass: int = 4):
+    def __init__(self, hbm_budget_bytes: int, n_streams: int = 4, max_bypass: int = 0):
         h = _vp()
         _check(_lib.ffa_server_create(ctypes.c_size_t(hbm_budget_bytes), n_streams, max_bypass, ctypes.byref(h)),
                "ffa_server_create")
