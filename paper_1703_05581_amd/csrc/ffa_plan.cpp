@@ -862,6 +862,32 @@ extern "C" ffa_status ffa_plan_periods(ffa_plan p, double* out) {
   return FFA_OK;
 }
 
+// Test hook (not in the public header): the plan's dereddening plan.  Writes
+// 6 values per segment (x_off, out_off, n, block0, window, use_stage), then
+// 3 per launch (block0, blocks, lds); returns the segment count (launch count
+// in *n_launches), -1 for a null plan.  Nothing is written when cap is short.
+extern "C" int64_t ffa_debug_dered(ffa_plan p, int64_t* out, int64_t cap, int64_t* n_launches) {
+  if (!p) return -1;
+  const DeredPlan& dp = p->dered;
+  const int64_t ns = (int64_t)dp.segs.size(), nl = (int64_t)dp.launches.size();
+  if (n_launches) *n_launches = nl;
+  if (!out || cap < 6 * ns + 3 * nl) return ns;
+  for (const DeredSeg& g : dp.segs) {
+    *out++ = g.x_off;
+    *out++ = g.out_off;
+    *out++ = g.n;
+    *out++ = g.block0;
+    *out++ = g.window;
+    *out++ = g.use_stage;
+  }
+  for (const DeredLaunch& L : dp.launches) {
+    *out++ = L.block0;
+    *out++ = L.blocks;
+    *out++ = L.lds;
+  }
+  return ns;
+}
+
 // Test hooks (not in the public header): the plan's queue-ordered phases and
 // its workspace layout and launches, so host tests can check the kernel's
 // index arithmetic against the buffers without a GPU.

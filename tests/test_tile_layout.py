@@ -1,7 +1,11 @@
-"""Host-side check of the FFA kernel's addressing and launch order (no GPU)."""
+"""Host-side check of the FFA kernel's addressing and launch order, and of
+the dereddening plan (no GPU)."""
+import ctypes
+
 import numpy as np
 import pytest
 
+import tile_emu
 from paper_1703_05581_amd import ffa, synth
 from tile_emu import check
 
@@ -69,3 +73,57 @@ def test_plan_options_are_checked():
         assert e.value.status == ffa.FFA_ERR_INVALID, bad
     with pytest.raises(ValueError):
         ffa.Plan(65536, 1e-3, 0.5, 1.0, 500, None, opts={"no_such_option": 1})
+
+
+def _dered_plan(plan):
+    lib = ffa.lib()
+    lib.ffa_debug_dered.restype = ctypes.c_int64
+    lib.ffa_debug_dered.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    nl = ctypes.c_int64()
+    ns = lib.ffa_debug_dered(plan.handle, None, 0, ctypes.byref(nl))
+    buf = np.zeros(6 * ns + 3 * nl.value, np.int64)
+    assert lib.ffa_debug_dered(plan.handle, buf.ctypes.data, buf.size, ctypes.byref(nl)) == ns
+    return buf[:6 * ns].reshape(-1, 6), buf[6 * ns:].reshape(-1, 3)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dered_plan_covers_octaves(seed):
+    """Float plans with the exact filter dereddening every folded octave at
+    once: each octave from the lowest folded one is one segment (its double
+    raw series in, its float series out, inside the workspace), blocks of
+    256 outputs numbered without gaps across the launches, each launch's
+    LDS within the CU's and at least what its segments stage."""
+    g = np.random.default_rng(500 + seed)
+    N = int(g.integers(3000, 1 << 21))
+    B = int(g.integers(16, 300))
+    pmin = B * 1e-3 * float(g.uniform(1.0, 3.0))
+    plan = ffa.Plan(N, 1e-3, pmin, pmin * float(g.uniform(2.0, 40.0)), B, None, "f32",
+                    dered_window=int(g.choice([-1, 37, 5000, 40000])))
+    segs, launches = _dered_plan(plan)
+    L = tile_emu.layout(plan)
+    octs = tile_emu.octaves(plan)
+    first = min(plan.step(s).f for s in range(plan.n_steps)).bit_length() - 1
+    assert len(segs) == len(octs) - first
+    blk = 0
+    for k, (x_off, out_off, n, block0, window, use_stage) in enumerate(segs):
+        assert (out_off, n) in [tuple(o) for o in octs[first:]]
+        assert x_off + 2 * n <= L["ring_off"] and out_off + n <= x_off or x_off + 2 * n <= out_off
+        assert block0 == blk and window > 0
+        stage_n = min(window + 255, n)
+        assert use_stage == (stage_n <= 16384)
+        blk += -(-n // 256)
+    assert launches[0][0] == 0 and sum(int(b) for _, b, _ in launches) == blk
+    for (b0, nb, lds), nxt in zip(launches, list(launches[1:]) + [None]):
+        assert 0 < lds <= 160 * 1024
+        if nxt is not None:
+            assert nxt[0] == b0 + nb
+        inside = [s for s in segs if b0 <= s[3] < b0 + nb]
+        assert inside and all(s[3] + -(-s[2] // 256) <= b0 + nb for s in inside)
+
+
+def test_dered_plan_absent_without_exact_float_filter():
+    """uint8 input, knots, or no dereddening: no dereddening plan."""
+    for dt, dw, st in (("u8", -1, 0), ("f32", -1, 8), ("f32", 0, 0)):
+        plan = ffa.Plan(1 << 16, 1e-3, 0.2, 1.0, 100, None, dt, dered_window=dw, dered_stride=st)
+        segs, launches = _dered_plan(plan)
+        assert len(segs) == 0 and len(launches) == 0
