@@ -179,6 +179,19 @@ ffa_status plan_batch(int32_t n, const ffa_plan* plans, ffa_batch_s** out) {
         kn.split_occupancy = kn.split_occupancy && pk.split_occupancy;
       }
     }
+    // A class with many windows' worth of tiles runs window groups 8x larger
+    // than one plan's, with a ring 4x larger (fewer launches and launch
+    // tails; the batch is one job with one workspace on a 288 GB part).
+    {
+      int64_t class_tiles = 0;
+      for (int32_t i = 0; i < n; ++i)
+        if (cls_of[(size_t)i] == (int32_t)c)
+          for (const Step& ps : plans[i]->steps) class_tiles += ps.total_tiles;
+      if (kn.fixed_steps == 0 && class_tiles >= 64 * (int64_t)kn.window_tiles && kn.window_tiles <= (1 << 21)) {
+        kn.window_tiles *= 8;
+        kn.ring_bytes *= 4;
+      }
+    }
     // steps and their natural-order phases, series by series
     for (int32_t i = 0; i < n; ++i) {
       if (cls_of[(size_t)i] != (int32_t)c) continue;
