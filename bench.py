@@ -41,7 +41,9 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit VALU operations (no packed
 # form is used), in tera-operations per second.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-KERNEL_SRC = os.path.join(ROOT, "paper_1703_05581_amd", "csrc", "ffa_kernels.hip")
+# the sources that decide what the FFA kernel does and how it is launched
+PATH_SRC = [os.path.join(ROOT, "paper_1703_05581_amd", "csrc", f)
+            for f in ("ffa_kernels.hip", "ffa_plan.cpp", "ffa_batch.cpp")]
 TRAFFIC_FILES = {"batch256": os.path.join(ROOT, "profiles", "ffa_tile_kernel.batch256_f32.traffic.md"),
                  "u8_2e20": os.path.join(ROOT, "profiles", "ffa_tile_kernel.u8_2e20.traffic.md")}
 COPY_BYTES = 256 << 20
@@ -142,8 +144,13 @@ def workload_units(plan, u8: bool = True, n_widths: int = 10, alg: int = 1):
 
 
 def source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel and planner sources: counter summaries taken on other
+    sources (another kernel, or other launches) are not used."""
+    h = hashlib.sha256()
+    for path in PATH_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(which: str):
@@ -154,7 +161,7 @@ def stored_traffic(which: str):
         text = open(TRAFFIC_FILES[which]).read()
     except OSError:
         return None
-    h = re.search(r"^kernel_source_sha256_16: (\w+)", text, re.M)
+    h = re.search(r"^path_source_sha256_16: (\w+)", text, re.M)
     b = re.search(r"^traffic_bytes_per_search: ([0-9.eE+]+)", text, re.M)
     if not h or not b or h.group(1) != source_hash():
         return None
@@ -173,7 +180,7 @@ def pmc_summary(db_paths, searches: int) -> None:
     for the 256 MiB device copy."""
     import sqlite3
 
-    print(f"kernel_source_sha256_16: {source_hash()}")
+    print(f"path_source_sha256_16: {source_hash()}")
     print("| kernel | counter | dispatches | mean per dispatch | total |")
     print("|---|---|---|---|---|")
     per_search = {}
