@@ -289,6 +289,9 @@ hipError_t launch_deredden(void* ws, int src_type, int64_t src_off, int64_t n, i
 // (and whether it stages the union of its windows), and its block count.
 size_t dered_block_lds(int64_t n, int32_t window, int32_t* use_stage);
 int64_t dered_block_count(int64_t n);
+// Allows the dereddening kernel the CU's whole LDS on the current device
+// (called where its tables are made, outside any stream capture).
+hipError_t prepare_dered_batch();
 // One launch of a dereddening plan (device tables).
 hipError_t launch_dered_batch(const DeredSeg* segs, const int32_t* block_seg, const DeredLaunch& L, void* ws,
                               hipStream_t st);

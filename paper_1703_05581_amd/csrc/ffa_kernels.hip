@@ -2303,12 +2303,15 @@ size_t dered_block_lds(int64_t n, int32_t window, int32_t* use_stage) {
 
 int64_t dered_block_count(int64_t n) { return (n + kRmBlock - 1) / kRmBlock; }
 
+hipError_t prepare_dered_batch() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&dered_batch_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+}
+
 hipError_t launch_dered_batch(const DeredSeg* segs, const int32_t* block_seg, const DeredLaunch& L, void* ws,
                               hipStream_t st) {
   if (L.blocks < 1) return hipSuccess;
   if (L.blocks > 0x7fffffff || L.lds > (int32_t)kLdsBytes) return hipErrorInvalidValue;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dered_batch_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
   dered_batch_kernel<<<(unsigned)L.blocks, kRmThreads, (size_t)L.lds, st>>>(segs, block_seg, L.block0,
                                                                           reinterpret_cast<float*>(ws));
   return hipGetLastError();

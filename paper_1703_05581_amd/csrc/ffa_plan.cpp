@@ -417,7 +417,9 @@ ffa_status upload_dered(const DeredPlan& dp, DeredSeg** segs, int32_t** block_se
     (void)hipGetLastError();
     return fail(FFA_ERR_NOMEM, "dereddening tables: hipMalloc failed");
   }
-  ffa_status st = check_hip(hipMemcpy(*segs, dp.segs.data(), sb, hipMemcpyHostToDevice), "upload dereddening plan");
+  ffa_status st = check_hip(prepare_dered_batch(), "dereddening kernel attributes");
+  if (st == FFA_OK)
+    st = check_hip(hipMemcpy(*segs, dp.segs.data(), sb, hipMemcpyHostToDevice), "upload dereddening plan");
   if (st == FFA_OK)
     st = check_hip(hipMemcpy(*block_seg, dp.block_seg.data(), bb, hipMemcpyHostToDevice),
                    "upload dereddening block map");

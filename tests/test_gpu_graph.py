@@ -19,13 +19,13 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("dtype,alg", [("u8", 1), ("f32", 1), ("f32", 2)])
-def test_graph_replay_matches_eager(torch_cuda, dtype, alg):
+@pytest.mark.parametrize("dtype,alg,dered", [("u8", 1, 0), ("f32", 1, 0), ("f32", 2, 0), ("f32", 1, -1)])
+def test_graph_replay_matches_eager(torch_cuda, dtype, alg, dered):
     torch = torch_cuda
     from paper_1703_05581_amd import ffa, synth
 
     N = 200000
-    plan = ffa.Plan(N, 1e-3, 0.2, 2.0, 100, W10, dtype, snr=alg)
+    plan = ffa.Plan(N, 1e-3, 0.2, 2.0, 100, W10, dtype, snr=alg, dered_window=dered)
     x = torch.from_numpy(synth.random_series(91, N, dtype)).cuda()
     snr = torch.empty(plan.n_trials, dtype=torch.float32, device="cuda")
     wid = torch.empty(plan.n_trials, dtype=torch.int32, device="cuda")
@@ -33,7 +33,7 @@ def test_graph_replay_matches_eager(torch_cuda, dtype, alg):
     plan.search(x, snr, wid, ws)  # eager, and it makes the plan's device tables
     torch.cuda.synchronize()
     ref = (snr.clone(), wid.clone())
-    print("capture", dtype, alg, plan.n_trials, flush=True)
+    print("capture", dtype, alg, dered, plan.n_trials, flush=True)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         plan.search(x, snr, wid, ws)
@@ -57,3 +57,36 @@ def test_graph_replay_matches_eager(torch_cuda, dtype, alg):
     torch.cuda.synchronize()
     assert torch.equal(snr, s2) and torch.equal(wid, w2)
     assert not torch.equal(snr, ref[0])
+
+
+def test_graph_replay_batch(torch_cuda):
+    """A batched search (uint8 and dereddened float32 series) captured and
+    replayed equals the eager batch, replay after replay."""
+    torch = torch_cuda
+    from paper_1703_05581_amd import ffa, synth
+
+    plans, xs = [], []
+    for i, (dt, dw) in enumerate([("u8", 0), ("f32", -1), ("f32", 0), ("f32", -1)]):
+        N = 60000 + 20000 * i
+        plans.append(ffa.Plan(N, 1e-3, 0.15, 1.2, 120, W10, dt, dered_window=dw))
+        xs.append(torch.from_numpy(synth.random_series(130 + i, N, dt)).cuda())
+    b = ffa.Batch(plans)
+    ws = b.workspace()
+    outs = b.outputs()
+    b.search(xs, outs=outs, ws=ws)  # eager, and it makes the batch's device tables
+    torch.cuda.synchronize()
+    ref = [(s.clone(), w.clone()) for s, w in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.search(xs, outs=outs, ws=ws)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for s, w in outs:
+            s.fill_(-1.0)
+            w.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, ((s, w), (s0, w0)) in enumerate(zip(outs, ref)):
+            assert torch.equal(s, s0) and torch.equal(w, w0), (rep, i)
+    b.close()
