@@ -193,3 +193,26 @@ def test_batch_workload4_forty(env, oracle_mod):
             assert peak >= 6.0, (i, P, peak)
     assert found >= 0.8 * total, (found, total)
     b.close()
+
+
+def test_batch_mixed_dereddening(env):
+    """One batch of float series with the exact filter (dereddened by the
+    batch's own launches), float series with knots and uint8 series with the
+    exact filter (each dereddened on its own), and series without it: every
+    periodogram equals the plain search's, bit for bit."""
+    torch, ffa, synth = env
+    kinds = [("f32", -1, 0), ("f32", 301, 8), ("u8", -1, 0), ("f32", 0, 0), ("f32", 1000, 1), ("u8", 0, 0)]
+    plans, xs = [], []
+    for i, (dt, dw, st) in enumerate(kinds):
+        N = 50000 + 13000 * i
+        plans.append(ffa.Plan(N, 1e-3, 0.2, 1.5, 150, W10, dt, dered_window=dw, dered_stride=st))
+        x = synth.random_series(800 + i, N, dt)
+        if dt == "f32":
+            x = (x + 4.0 * np.sin(np.arange(N) / 700.0)).astype(np.float32)
+        xs.append(torch.from_numpy(x).cuda())
+    outs = ffa.Batch(plans).search(xs)
+    torch.cuda.synchronize()
+    for i, (p, x) in enumerate(zip(plans, xs)):
+        s1, w1 = p.search(x)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i][0], s1) and torch.equal(outs[i][1], w1), (i, kinds[i])
