@@ -1172,7 +1172,12 @@ __global__ __launch_bounds__(kThreads, EMAX <= 8 ? 8 : 4) void ffa_tile_kernel(T
       return;
     }
   }
+  // The DMA loads are issued at raised wave priority, so a workgroup that is
+  // staging gets its loads in flight ahead of the other workgroup's scoring
+  // on the same SIMDs.
+  __builtin_amdgcn_s_setprio(3);
   stage_rows_dma(lds, ws + src_off, R, valid, P0, S);
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
 
   butterfly<T>(lds, S, P0, H, d);
