@@ -22,6 +22,16 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// The lane index as a value the compiler cannot hoist: the scoring helpers
+// take it afresh on every profile, so the lane masks derived from it are
+// recomputed where they are used instead of being held for the whole tile
+// (held, they overflow the scalar registers and go to vector-register lanes).
+__device__ __forceinline__ int lane_fresh() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t & (kWave - 1);
+}
+
 // Index of this wave in its workgroup, as a wave-uniform (scalar) value: the
 // per-wave loops and their index arithmetic then run on the scalar unit.
 __device__ __forceinline__ int wave_id() {
@@ -93,7 +103,7 @@ __device__ __forceinline__ uint32_t bpermute(int src_lane, uint32_t v) {
 }
 
 __device__ __forceinline__ uint32_t wave_umax8(const uint32_t (&v)[8]) {
-  const int lane = lane_id();
+  const int lane = lane_fresh();
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   uint32_t r[4], s[2];
 #pragma unroll
@@ -179,7 +189,7 @@ struct WidthLanes {
 __device__ __forceinline__ void wave_sum2(double a, double b, double& sa, double& sb) {
   auto bits = [](double x) { return (uint64_t)__double_as_longlong(x); };
   auto dbl = [](uint64_t u) { return __longlong_as_double((long long)u); };
-  const int lane = lane_id();
+  const int lane = lane_fresh();
   const bool odd = lane & 1;
   double v = (odd ? b : a) + dbl(dpp64<kDppXor1>(bits(odd ? a : b)));
   v += dbl(dpp64<kDppXor2>(bits(v)));  // the quad
@@ -396,7 +406,7 @@ __device__ __forceinline__ int count_lt(const uint32_t (&key)[E], uint32_t T) {
 // 0..cnt-1: quickselect with the first remaining lane as pivot.  Each round
 // removes at least the pivot, so it ends within cnt rounds.
 __device__ __forceinline__ uint32_t lane_select(uint32_t c, int cnt, int t) {
-  const int lane = lane_id();
+  const int lane = lane_fresh();
   uint64_t active = __ballot(lane < cnt);
   for (int it = 0; it < kWave; ++it) {
     const int src = __ffsll((unsigned long long)active) - 1;
@@ -465,7 +475,7 @@ template <int E, bool FKEY>
 __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int k1, int k2, uint32_t kmin,
                             uint32_t kmax, uint32_t* scratch, SelectKnobs kn, const Prior& pr,
                             uint32_t& v1, uint32_t& v2) {
-  const int lane = lane_id();
+  const int lane = lane_fresh();
   uint32_t lo = kmin, hi = kmax + 1u;  // kmax < kPadKey
   int c_lo = 0, c_hi = n;              // keys below lo / below hi
   bool halve = false;
@@ -606,7 +616,7 @@ __device__ __forceinline__ void circular_prefix(typename Types<INT>::T* row, int
                                                 typename Types<INT>::T shift = 0) {
   using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
-  const int lane = lane_id();
+  const int lane = lane_fresh();
   A xv[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -797,7 +807,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
                               int32_t* width_out) {
   using T = typename Types<INT>::T;
   using A = typename Types<INT>::A;
-  const int lane = lane_id();
+  const int lane = lane_fresh();
   const int k1 = (P0 - 1) / 2;
   const int k2 = P0 / 2;
 
@@ -1001,6 +1011,13 @@ template <bool INT, int EMAX, int ALG>
 __device__ __forceinline__ void score_dispatch(typename Types<INT>::T* row, uint32_t* scratch, int P0, int wmax,
                                const WidthLanes& wt, int nw, SelectKnobs kn, WavePrior& wp, float* snr_out,
                                int32_t* width_out) {
+  // P0, the width count and the widest width are fixed for a tile, so the
+  // compiler would hoist everything derived from them (the per-register bounds
+  // masks above all) out of the loop over a wave's profiles. Held across that
+  // loop they overflow the 80 scalar registers a wave has at 8 waves per SIMD,
+  // and the spills to vector-register lanes cost two readlanes per use. Marked
+  // as redefined here, they are derived again for each profile.
+  asm volatile("" : "+s"(P0), "+s"(nw), "+s"(wmax));
 #define FFA_SCORE(EE)                                                                              \
   do {                                                                                             \
     if constexpr (ALG == 2)                                                                        \
