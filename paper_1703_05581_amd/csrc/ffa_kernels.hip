@@ -1411,11 +1411,12 @@ __global__ __launch_bounds__(kKnotThreads) void knot_median_kernel(const T* __re
 // core C (the samples every one of them holds); output i's window is C plus
 // at most kRmBlock - 1 fringe samples.  So the rank-k value of window i lies
 // between the core's values of rank k - f_i and k (f_i its fringe count),
-// and every median of the block lies in [v_a, v_b], the core's values of the
-// smallest and largest such ranks.  The union's values in [v_a, v_b] form a
+// and every median of the block lies between the core's values of the
+// smallest and largest such ranks.  With the core's values in equal buckets,
+// the union's values in the buckets qa..qb holding those two ranks form a
 // small pool, sorted once; output i's median is the value of rank
 // k - below_i among the pool entries inside its window, below_i being the
-// count of its window's values under v_a.  Each selection is exact; blocks
+// count of its window's values in buckets below qa.  Each selection is exact; blocks
 // whose pool would overflow (many equal values), whose windows share no core
 // (windows shorter than the block) or that are too long to stage in LDS
 // select every output's median directly instead.
@@ -1437,6 +1438,7 @@ struct RmShared {
   int32_t wred[kRmThreads / kWave], wred2[kRmThreads / kWave];
   int64_t wred64[kRmThreads / kWave], wred64b[kRmThreads / kWave];
   double dred[kRmThreads / kWave];
+  double dred4[4][kRmThreads / kWave];
   uint32_t hist[kRmBins];
   int32_t pool_n, n_core, n_fr, qa, qb;
   double res;
@@ -1489,6 +1491,32 @@ __device__ __forceinline__ double rm_max(RmShared& sh, double v) {
   for (int w = 1; w < kRmThreads / kWave; ++w) t = fmax(t, sh.dred[w]);
   __syncthreads();
   return t;
+}
+// Two minima (a, c) and two maxima (b, d) in one exchange.
+__device__ __forceinline__ void rm_ext4(RmShared& sh, double& a, double& b, double& c, double& d) {
+  a = -wave_dmax(-a);
+  b = wave_dmax(b);
+  c = -wave_dmax(-c);
+  d = wave_dmax(d);
+  if (lane_id() == 0) {
+    const int w = wave_id();
+    sh.dred4[0][w] = a;
+    sh.dred4[1][w] = b;
+    sh.dred4[2][w] = c;
+    sh.dred4[3][w] = d;
+  }
+  __syncthreads();
+  a = sh.dred4[0][0];
+  b = sh.dred4[1][0];
+  c = sh.dred4[2][0];
+  d = sh.dred4[3][0];
+  for (int w = 1; w < kRmThreads / kWave; ++w) {
+    a = fmin(a, sh.dred4[0][w]);
+    b = fmax(b, sh.dred4[1][w]);
+    c = fmin(c, sh.dred4[2][w]);
+    d = fmax(d, sh.dred4[3][w]);
+  }
+  __syncthreads();
 }
 
 // The rank-r (0-based) value of the `cnt` values get(0 .. cnt-1), exact.  A
@@ -1579,8 +1607,18 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
   const int64_t Clo = wlo(i1 - 1), Chi = whi(i0);  // their common core
   const int64_t nU = Uhi - Ulo;
   const bool staged = use_stage && nU <= kRmStageMax;
-  if (staged)
-    for (int64_t j = tid; j < nU; j += kRmThreads) stage[j] = (double)x[Ulo + j];
+  double cmn = INFINITY, cmx = -INFINITY;  // the core's extremes, taken while staging
+  if (staged) {
+    const int64_t cb = Clo - Ulo, ce = Chi - Ulo;
+    for (int64_t j = tid; j < nU; j += kRmThreads) {
+      const double v = (double)x[Ulo + j];
+      stage[j] = v;
+      if (j >= cb && j < ce) {
+        cmn = fmin(cmn, v);
+        cmx = fmax(cmx, v);
+      }
+    }
+  }
   __syncthreads();
   auto val = [&](int64_t pos) -> double { return staged ? stage[pos - Ulo] : (double)x[pos]; };
   const int64_t i = i0 + tid;
@@ -1590,41 +1628,37 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
   const int64_t k1 = (cnt_i - 1) / 2, k2 = cnt_i / 2;
   const int64_t nC = Chi - Clo;
   bool direct = !staged || nC < 1;
-  double v_a = 0.0, v_b = 0.0;
   int64_t below = 0;
   if (!direct) {
     // ranks of the core that bound every median of the block: the rank-k
     // value of window i lies between the core's values of rank k - f_i and
-    // k (f_i fringe samples), so [v_a, v_b] below holds every median; with a
-    // rank k - f_i below 0 (a core under half the window) there is no lower
-    // bound, and with k past the core none above
+    // k (f_i fringe samples), so the buckets from the one holding rank ra to
+    // the one holding rank rb below hold every median; with a rank k - f_i
+    // below 0 (a core under half the window) there is no lower bound, and
+    // with k past the core none above
     const int64_t f_i = cnt_i - nC;
-    const double ra_d = rm_min(sh, live ? (double)(k1 - f_i) : INFINITY);
-    const double rb_d = rm_max(sh, live ? (double)k2 : -INFINITY);
-    // Bounds v_a <= C_(ra) and v_b >= C_(rb) in one counting pass: the core's
-    // values go into kRmBins equal buckets between its minimum and maximum
-    // (the bucket index is monotone in the value, so equal values share a
-    // bucket and every bucket lies above the ones below it); v_a is the
-    // smallest value in the bucket holding rank ra, v_b the largest in the
-    // one holding rank rb, so count(< v_a) <= ra < rb < count(<= v_b).
+    double ra_d = live ? (double)(k1 - f_i) : INFINITY;
+    double rb_d = live ? (double)k2 : -INFINITY;
+    double mn = cmn, mx = cmx;
+    rm_ext4(sh, ra_d, rb_d, mn, mx);
+    // Buckets: kRmBins equal ones between the core's minimum and maximum,
+    // -1 below the minimum, the top one at and above the maximum.  The
+    // bucket is monotone in the value, so equal values share a bucket and
+    // every bucket lies above the ones below it; the buckets qa..qb holding
+    // ranks ra and rb then contain every value between those two ranks.
     const double* core = stage + (Clo - Ulo);
     const bool skip1 = !(ra_d >= 0.0), skip2 = !(rb_d < (double)nC);
     const int64_t ra = skip1 ? 0 : (int64_t)ra_d, rb = skip2 ? 0 : (int64_t)rb_d;
-    double mn = INFINITY, mx = -INFINITY;
-    for (int64_t j = tid; j < nC; j += kRmThreads) {
-      mn = fmin(mn, core[j]);
-      mx = fmax(mx, core[j]);
-    }
-    mn = rm_min(sh, mn);
-    mx = rm_max(sh, mx);
-    v_a = mn;
-    v_b = mx;
-    if (mx > mn) {
-      const double scale = (double)kRmBins / (mx - mn);
-      auto bucket = [&](double v) {
-        const int q = (int)((v - mn) * scale);
-        return q < kRmBins - 1 ? q : kRmBins - 1;
-      };
+    const bool spread = mx > mn;
+    const double scale = spread ? (double)kRmBins / (mx - mn) : 0.0;
+    auto bucket = [&](double v) -> int {
+      if (v < mn) return -1;
+      if (!spread) return v > mn ? 1 : 0;  // one value in the core: its own bucket
+      const double t = (v - mn) * scale;
+      return t < (double)(kRmBins - 1) ? (int)t : kRmBins - 1;
+    };
+    int qa = 0, qb = 0;
+    if (spread) {
       for (int q = tid; q < kRmBins; q += kRmThreads) sh.hist[q] = 0u;
       __syncthreads();
       for (int64_t j = tid; j < nC; j += kRmThreads) atomicAdd(&sh.hist[bucket(core[j])], 1u);
@@ -1654,41 +1688,35 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
         run += hv[q];
       }
       __syncthreads();
-      const int qa = sh.qa, qb = sh.qb;
-      double lo_a = INFINITY, hi_b = -INFINITY;
-      for (int64_t j = tid; j < nC; j += kRmThreads) {
-        const double v = core[j];
-        const int q = bucket(v);
-        if (q == qa) lo_a = fmin(lo_a, v);
-        if (q == qb) hi_b = fmax(hi_b, v);
-      }
-      v_a = rm_min(sh, lo_a);
-      v_b = rm_max(sh, hi_b);
+      qa = sh.qa;
+      qb = sh.qb;
     }
-    if (skip1) v_a = -INFINITY;
-    if (skip2) v_b = INFINITY;
-    // the pool: the union's values in [v_a, v_b]; and the values below v_a
+    // below the pool: a bucket under qa (never, without a lower bound)
+    auto under = [&](double v) { return !skip1 && bucket(v) < qa; };
+    // the pool: the union's values in buckets qa..qb; and the core's values below them
     if (tid == 0) sh.pool_n = 0;
     __syncthreads();
     int64_t core_below = 0;
     for (int64_t j = tid; j < nU; j += kRmThreads) {
       const double v = stage[j];
       const int64_t pos = Ulo + j;
-      if (v >= v_a && v <= v_b) {
+      const int q = bucket(v);
+      const bool lo_ok = skip1 || q >= qa;
+      if (lo_ok && (skip2 || q <= qb)) {
         const int at = atomicAdd(&sh.pool_n, 1);
         if (at < kRmPool) {
           sh.pool_v[at] = v;
           sh.pool_p[at] = (int16_t)j;
         }
       }
-      if (pos >= Clo && pos < Chi) core_below += v < v_a;
+      if (pos >= Clo && pos < Chi) core_below += !lo_ok;
     }
     core_below = rm_sum(sh, core_below);
-    // values below v_a in the left fringe [Ulo, Clo) and the right one
+    // values below the pool in the left fringe [Ulo, Clo) and the right one
     // [Chi, Uhi), each at most kRmBlock - 1 samples: exclusive prefix counts
     const int64_t nL = Clo - Ulo, nR = Uhi - Chi;
-    const uint32_t bl = tid < nL ? (stage[tid] < v_a ? 1u : 0u) : 0u;
-    const uint32_t br = tid < nR ? (stage[Chi - Ulo + tid] < v_a ? 1u : 0u) : 0u;
+    const uint32_t bl = tid < nL ? (under(stage[tid]) ? 1u : 0u) : 0u;
+    const uint32_t br = tid < nR ? (under(stage[Chi - Ulo + tid]) ? 1u : 0u) : 0u;
     const uint32_t sl = wave_scan(bl), sr = wave_scan(br);
     if (lane_id() == kWave - 1) {
       sh.wred[wave_id()] = (int32_t)sl;
@@ -1725,25 +1753,27 @@ __device__ __forceinline__ void rm_block(const T* __restrict__ x, int64_t n, int
         sh.pool_p[j] = 0x7fff;
       }
       __syncthreads();
-      // (entry t belongs to thread t, so a compare over a distance below 64
-      // stays in one wave and needs no workgroup barrier before or after)
-      static_assert(kRmPool <= kRmThreads, "one pool entry per thread");
+      // One thread per compare pair: pair p compares entries t and t + jj,
+      // t being p with a zero bit inserted at jj.  For distances up to 64 the
+      // 64 pairs of a wave are the entries [128w, 128w + 128), the same at
+      // every such distance, so those compares need no workgroup barrier
+      // before or after.
+      static_assert(kRmPool <= 2 * kRmThreads, "one compare pair per thread");
       for (int k = 2; k <= np2; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          const int t = tid;
-          if (t < np2) {
-            const int u = t ^ jj;
-            if (u > t) {
-              const bool up = (t & k) == 0;
-              const double va = sh.pool_v[t], vb = sh.pool_v[u];
-              const int16_t pa = sh.pool_p[t], pb = sh.pool_p[u];
-              const bool gt = va > vb || (va == vb && pa > pb);
-              if (gt == up) {
-                sh.pool_v[t] = vb;
-                sh.pool_v[u] = va;
-                sh.pool_p[t] = pb;
-                sh.pool_p[u] = pa;
-              }
+          const int p = tid;
+          if (p < (np2 >> 1)) {
+            const int t = ((p & ~(jj - 1)) << 1) | (p & (jj - 1));
+            const int u = t + jj;
+            const bool up = (t & k) == 0;
+            const double va = sh.pool_v[t], vb = sh.pool_v[u];
+            const int16_t pa = sh.pool_p[t], pb = sh.pool_p[u];
+            const bool gt = va > vb || (va == vb && pa > pb);
+            if (gt == up) {
+              sh.pool_v[t] = vb;
+              sh.pool_v[u] = va;
+              sh.pool_p[t] = pb;
+              sh.pool_p[u] = pa;
             }
           }
           const int jn = jj > 1 ? jj >> 1 : (k < np2 ? k : 0);  // the next compare distance (0: sorted)
