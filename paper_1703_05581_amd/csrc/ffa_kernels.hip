@@ -462,8 +462,10 @@ struct SelectKnobs {
 };
 
 // Exact order statistics v1 = key_(k1) and v2 = key_(k2), k2 in {k1, k1+1},
-// of the n real keys in key[E] (pads are kPadKey), given kmin/kmax of the
-// real keys.  A bracket [lo, hi) holding both targets is narrowed by counting
+// of the n real keys in key[E] (pads are kPadKey), given a bracket [lo0, hi0)
+// of the real keys.  An end given as 0 (lo0) or kPadKey (hi0) is open: if the
+// first round leaves it so, it becomes the keys' minimum (maximum + 1), so
+// the extremes are reduced across the wave only when the pivots miss.  A bracket [lo, hi) holding both targets is narrowed by counting
 // keys below a pivot (one ballot per register).  With a prior (E <= 8) the
 // first round counts its three pivots at once; later pivots interpolate the
 // ranks inside the bracket, falling back to halving it when a round gains
@@ -472,11 +474,11 @@ struct SelectKnobs {
 // the wave's LDS scratch and selected exactly.  FKEY: keys encode floats, so
 // interpolation happens on the float values.  Every exit is exact.
 template <int E, bool FKEY>
-__device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int k1, int k2, uint32_t kmin,
-                            uint32_t kmax, uint32_t* scratch, SelectKnobs kn, const Prior& pr,
+__device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int k1, int k2, uint32_t lo0,
+                            uint32_t hi0, uint32_t* scratch, SelectKnobs kn, const Prior& pr,
                             uint32_t& v1, uint32_t& v2) {
   const int lane = lane_fresh();
-  uint32_t lo = kmin, hi = kmax + 1u;  // kmax < kPadKey
+  uint32_t lo = lo0, hi = hi0;
   int c_lo = 0, c_hi = n;              // keys below lo / below hi
   bool halve = false;
   int side = 0;         // +1: hi moved last round, -1: lo moved
@@ -512,6 +514,18 @@ __device__ __forceinline__ void select_pair(const uint32_t (&key)[E], int n, int
         }
       }
     }
+  }
+  if (lo == 0u) {  // open lower end: the smallest key (count below it is 0)
+    uint32_t mn = kPadKey;
+#pragma unroll
+    for (int r = 0; r < E; ++r) mn = umin(mn, key[r]);
+    lo = wave_umin(mn);
+  }
+  if (hi == kPadKey) {  // open upper end: just above the largest real key (real keys < kPadKey)
+    uint32_t mx = 0u;
+#pragma unroll
+    for (int r = 0; r < E; ++r) mx = umax(mx, key[r] != kPadKey ? key[r] : 0u);
+    hi = wave_umax(mx) + 1u;
   }
   // Rounds past max_iters only halve the key range, which ends the loop
   // within 33 more rounds (the range is at most 2^32).
@@ -812,18 +826,13 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   const int k2 = P0 / 2;
 
   uint32_t key[E];
-  uint32_t kmin = kPadKey, kmax = 0u;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = r * kWave + lane;
     const bool real = r < kFullRegs<E> || e < P0;
     if constexpr (INT) key[r] = real ? (uint32_t)row[e] : kPadKey;
     else key[r] = real ? fkey(row[e]) : kPadKey;
-    kmin = umin(kmin, key[r]);
-    kmax = umax(kmax, real ? key[r] : 0u);
   }
-  kmin = wave_umin(kmin);
-  kmax = wave_umax(kmax);
   // Mean and spread of the profile in float: they only place the selections'
   // first pivots (about 2.5 standard errors either side of the expected
   // median and MAD of normal noise).  Every profile of an FFA execution sums
@@ -835,6 +844,10 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   if constexpr (E <= 8) {
     if (__builtin_amdgcn_readfirstlane(wp.sd > 0.f ? 1 : 0) == 0) {
       float s1 = 0.f, s2 = 0.f;
+      uint32_t kmin = kPadKey;  // moments about the smallest value, for their precision
+#pragma unroll
+      for (int r = 0; r < E; ++r) kmin = umin(kmin, key[r]);
+      kmin = wave_umin(kmin);
       const float base = INT ? (float)kmin : fval(kmin);
 #pragma unroll
       for (int r = 0; r < E; ++r) {
@@ -865,19 +878,15 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
 
   // median (even P0: mean of the two middle order statistics)
   uint32_t m1, m2;
-  select_pair<E, !INT>(key, P0, k1, k2, kmin, kmax, scratch, kn, pm, m1, m2);
+  select_pair<E, !INT>(key, P0, k1, k2, 0u, kPadKey, scratch, kn, pm, m1, m2);
   uint64_t med2 = 0;
   float med = 0.f;
   double med_d = 0.0;
-  uint32_t dmax;
   if constexpr (INT) {
     med2 = (uint64_t)m1 + (uint64_t)m2;
-    const uint64_t up = 2 * (uint64_t)kmax - med2, dn = med2 - 2 * (uint64_t)kmin;
-    dmax = (uint32_t)(up > dn ? up : dn);
   } else {
     med_d = 0.5 * ((double)fval(m1) + (double)fval(m2));
     med = (float)med_d;
-    dmax = fkey(fmaxf(fabsf(fval(kmax) - med), fabsf(fval(kmin) - med)));
   }
   // MAD: the same selection on |x - median| (doubled for integers)
 #pragma unroll
@@ -886,8 +895,8 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     if constexpr (INT) {  // 2*x and med2 are below 2^32 (sums below 2^31)
       const uint32_t tx = 2u * key[r], m2 = (uint32_t)med2;
       key[r] = real ? (tx >= m2 ? tx - m2 : m2 - tx) : kPadKey;
-    } else {
-      key[r] = real ? fkey(fabsf(fval(key[r]) - med)) : kPadKey;
+    } else {  // from the profile in LDS: the key of a value >= 0 is its bits with the top bit set
+      key[r] = real ? (__float_as_uint(fabsf(row[r * kWave + lane] - med)) | 0x80000000u) : kPadKey;
     }
   }
   const uint32_t dmin = INT ? 0u : fkey(0.f);
@@ -904,7 +913,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     }
   }
   uint32_t d1, d2;
-  select_pair<E, !INT>(key, P0, k1, k2, dmin, dmax, scratch, kn, pd, d1, d2);
+  select_pair<E, !INT>(key, P0, k1, k2, dmin, kPadKey, scratch, kn, pd, d1, d2);
   uint64_t mad4 = 0;
   float mad = 0.f;
   bool mad_zero;
