@@ -85,3 +85,23 @@ def test_dered_many_ties(torch_cuda, ffa, oracle_mod):
     x[20000:21000] = 200  # a block of one value
     run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.3, 1.2, 150, W10, "u8", steps_max=12,
              check_fold=2, dered_window=1500, dered_stride=0)
+
+
+@pytest.mark.parametrize("window", [301, 1500])
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_dered_constant_stretch(torch_cuda, ffa, oracle_mod, window, dtype):
+    """A stretch of one repeated value longer than the window plus a block of
+    outputs: the blocks inside it have a core of a single value (one bucket
+    holds every core value; the pool is that value), the blocks at its edges
+    a core of mixed values; the dereddened series still folds to the
+    oracle's profiles and the periodogram matches it."""
+    g = np.random.default_rng(47 + window)
+    N = 60000
+    x = g.standard_normal(N) * 10.0
+    x[20000:32000] = 0.0
+    if dtype == "u8":
+        x = np.clip(np.rint(x + 128), 0, 255).astype(np.uint8)
+    else:
+        x = (x + 5.0).astype(np.float32)
+    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.3, 1.2, 150, W10, dtype, steps_max=12,
+             check_fold=3, dered_window=window, dered_stride=0)
