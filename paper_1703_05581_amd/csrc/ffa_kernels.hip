@@ -935,12 +935,22 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
     return;
   }
 
-  // Float profiles are shifted by the (float) median before the prefix sums,
-  // so the running sums stay near zero and a box C[j+w] - C[j] keeps the
-  // precision of its own bins whatever the profile's offset; the shift is
-  // added back exactly in double below.
+  // Float profiles are shifted by their median before the prefix sums, so a
+  // box C[j+w] - C[j] keeps the precision of its own bins whatever the
+  // profile's offset; the shift is added back exactly in double below.  On a
+  // skewed profile, whose mean lies more than 3 K*MAD/sqrt(P0) from its median
+  // (about a 4-sigma event for normal noise), the running sum of x - median
+  // drifts to P0 * (mean - median), and its float32 rounding grows large
+  // against the MAD; such a profile is shifted by the profiles' shared mean
+  // instead (where the wave holds it, E <= 8), about which the running sum
+  // returns to zero.
+  float cshift = med;
+  if constexpr (E <= 8) {
+    if (__builtin_amdgcn_readfirstlane(fabsf(wp.mean - med) * __builtin_sqrtf((float)P0) > 3.f * wp.sd ? 1 : 0))
+      cshift = wp.mean;
+  }
   A cex[E];  // C[j] (exclusive prefix) of this lane's bins
-  if constexpr (!INT) circular_prefix<E, INT>(row, P0, wmax, cex, med);
+  if constexpr (!INT) circular_prefix<E, INT>(row, P0, wmax, cex, cshift);
   else circular_prefix<E, INT>(row, P0, wmax, cex);
 
   // Each width's score is num_w / ((K*MAD)*sqrt(w)), the box maximum taken
@@ -998,7 +1008,7 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   const bool live = lane < nw;
   double num;
   if constexpr (INT) num = (double)(2 * (2 * (int64_t)pk_l - (int64_t)wt.w * (int64_t)med2));
-  else num = (double)fval(pk_l) - (double)wt.w * (med_d - (double)med);
+  else num = (double)fval(pk_l) - (double)wt.w * (med_d - (double)cshift);
   const double a = live ? num * wt.isq : -INFINITY;
   const bool row0 = nw <= 16;  // every width's lane is in the first row
   const double amax = row0 ? row_dmax16(a) : wave_dmax(a);

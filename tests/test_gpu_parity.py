@@ -242,6 +242,39 @@ def test_selection_paths(torch_cuda, ffa, oracle_mod, knob, dtype):
              steps_max=6, opts=opts)
 
 
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_selection_open_ends(torch_cuda, ffa, oracle_mod, sign, dtype):
+    """Sparse large spikes at random positions make every profile's bins
+    skewed (most bins hold none, a few hold one or more), which puts the
+    profiles' mean, about which the selections' first pivots are placed, far
+    from their median (above it for positive spikes, below for negative
+    ones). The pivots then miss and the open end of the bracket is closed from
+    the keys' extremes; the periodogram still equals the oracle's."""
+    g = np.random.default_rng(71 + sign)
+    N = 40000
+    pos = g.choice(N, N // 400, replace=False)
+    if dtype == "u8":
+        x = np.clip(np.rint(g.standard_normal(N) * 2.0 + 128), 0, 255)
+        x[pos] = 255 if sign > 0 else 0
+        x = x.astype(np.uint8)
+    else:
+        x = g.standard_normal(N) * 10.0
+        x[pos] += sign * 1000.0
+        x = x.astype(np.float32)
+    op = oracle_mod.plan(N, 1e-3, 0.2, 0.9, 200)
+    far = tot = 0
+    for s in range(0, op.n_steps, max(1, op.n_steps // 6)):
+        prof = oracle_mod.fold_step(x, int(op.f[s]), int(op.P0[s]), int(op.m[s]), int(op.M[s]))
+        for F in prof[:: max(1, len(prof) // 4)]:
+            med = np.median(F)
+            mad = np.median(np.abs(F - med))
+            tot += 1
+            far += abs(F.mean() - med) > 3.0 * 1.4826 * mad / np.sqrt(F.size)
+    assert far >= 0.8 * tot, (far, tot)  # the input does what the test is about
+    run_case(torch_cuda, ffa, oracle_mod, x, N, 1e-3, 0.2, 0.9, 200, W10, dtype, steps_max=12)
+
+
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_window_sizes_agree(torch_cuda, ffa, oracle_mod, dtype):
     """The periodogram does not depend on how the queue is cut into launches
