@@ -946,8 +946,8 @@ __device__ __forceinline__ void score_profile(typename Types<INT>::T* row, uint3
   // returns to zero.
   float cshift = med;
   if constexpr (E <= 8) {
-    if (__builtin_amdgcn_readfirstlane(fabsf(wp.mean - med) * __builtin_sqrtf((float)P0) > 3.f * wp.sd ? 1 : 0))
-      cshift = wp.mean;
+    const float dm = wp.mean - med;  // compared squared: no square root
+    if (__builtin_amdgcn_readfirstlane(dm * dm * (float)P0 > 9.f * wp.sd * wp.sd ? 1 : 0)) cshift = wp.mean;
   }
   A cex[E];  // C[j] (exclusive prefix) of this lane's bins
   if constexpr (!INT) circular_prefix<E, INT>(row, P0, wmax, cex, cshift);
