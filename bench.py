@@ -14,8 +14,8 @@ and one search of the 2^20-sample uint8 workload.
 
 Metric: trial*samples/s = sum over FFA executions of M*(m*P0) per second.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one
-GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the library searches on
+one GPU.
 
 Profiling helpers (run under rocprofv3, then summarised by this script):
   --calibrate-copy      after the timed steps, copy 256 MiB device-to-device
@@ -842,7 +842,7 @@ def main():
         pmc_summary(a.pmc_summary, a.searches)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the FFA search runs on one GPU; --gpus must be 1 "
                                    "(no multi-GPU path is built)"}))
         sys.exit(2)
     torch_init()
